@@ -1,0 +1,490 @@
+/*
+ * nncp_oracle.c -- reference implementation of dense nonnegative CP (NNCP)
+ * by alternating updates, in plain C and FP64.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * helper with the GPU library, and the GPU library never calls it.
+ *
+ * Everything is computed from the plain definitions in the paper (PLANC,
+ * arXiv 1909.01149), with no blocking, fusion or dimension tree:
+ *   - the objective, Eq. (eqn:nncp), Section 1;
+ *   - the alternating-update outer/inner iteration, Algorithm 1 (alg:nncp);
+ *   - MTTKRP M^(n) = X_(n) (H^(N) kr ... kr H^(n+1) kr H^(n-1) kr ... kr H^(1)),
+ *     Appendix "Factor Matrix Normalization" and Section 3.2.1 (3-way example);
+ *   - Gram G^(n) = H^(n)^T H^(n) and S^(n) = Hadamard product of the other
+ *     Grams, Algorithm 1;
+ *   - MU rule, Eq. (eqn:muupd); HALS rule, Eq. (eqn:halsupd), Section 3.3;
+ *   - column normalisation with weights lambda, Appendix "Factor Matrix
+ *     Normalization" and Algorithm 4 (alg:Par-NNCP-long);
+ *   - relative error through the identity
+ *     ||X-M||^2 = ||X||^2 - 2<M^(N), Hhat^(N)> + lambda^T (S^(N) * G^(N)) lambda,
+ *     Appendix "Relative Error Computation" and Algorithm 4.
+ *
+ * Readings where the paper is silent or inconsistent (each one is listed in
+ * the design notes of the repository):
+ *   - lambda is folded into the factor being updated before the update,
+ *     because the appendix states that the solve actually computes H^(n) Lambda;
+ *   - MU adds eps (default 1e-16) to the denominator; the paper only says a
+ *     "small value" is added;
+ *   - HALS divides by S(r,r) as in Eq. (eqn:halsupd) and skips a column whose
+ *     S(r,r) is 0; columns are updated in order 1..R using the latest values;
+ *   - HALS normalisation happens once after the whole update (Algorithm 4),
+ *     not after every column;
+ *   - all N factors are given as the start iterate (Algorithm 1 initialises
+ *     only modes 2..N, but MU and HALS need a start value for mode 1 as well);
+ *   - a zero column stays zero with lambda_r = 0;
+ *   - the squared relative error is clamped at 0 before the square root.
+ *
+ * Layouts: the tensor is stored with mode 0 varying fastest (the paper's
+ * "mode-descending, generalizing column-major" order, Section 3.1.1), so the
+ * linear index of (i_0, ..., i_{N-1}) is i_0 + I_0 (i_1 + I_1 (i_2 + ...)).
+ * A factor H^(n) is I_n x R, row-major (entry (i, r) at i*R + r).  Modes are
+ * 0-based here; the paper numbers them from 1.
+ *
+ * Parity status: every function here is pinned by CPU tests against closed
+ * forms, brute force (explicit unfolding times explicit Khatri-Rao product),
+ * invariants or finite differences; see tests/test_oracle_pins.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXN 16
+
+/* ------------------------------------------------------------------ */
+/* helpers: multi-index bookkeeping                                     */
+/* ------------------------------------------------------------------ */
+
+static int64_t prod_dims(int N, const int64_t *dims) {
+  int64_t p = 1;
+  for (int k = 0; k < N; ++k) p *= dims[k];
+  return p;
+}
+
+/* linear index -> multi-index, mode 0 fastest */
+static void unravel(int N, const int64_t *dims, int64_t lin, int64_t *idx) {
+  for (int k = 0; k < N; ++k) {
+    idx[k] = lin % dims[k];
+    lin /= dims[k];
+  }
+}
+
+/* advance a multi-index by one position in memory order */
+static void advance(int N, const int64_t *dims, int64_t *idx) {
+  for (int k = 0; k < N; ++k) {
+    if (++idx[k] < dims[k]) return;
+    idx[k] = 0;
+  }
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* MTTKRP by its definition                                             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * M^(n)[i_n, r] = sum over every entry of X whose mode-n index is i_n of
+ *                 X[i_0..i_{N-1}] * prod_{k != n} H^(k)[i_k, r].
+ * This is the mode-n matricized tensor times the Khatri-Rao product of all
+ * other factors, written entrywise (Section 3.2.1; Appendix, normalisation
+ * paragraph).  One pass over X in memory order; when nthreads > 1 the pass is
+ * cut into nthreads contiguous ranges, each thread accumulates into its own
+ * copy of M, and the copies are added in thread order (so a given nthreads
+ * always gives the same bits).
+ */
+int orc_mttkrp(int N, const int64_t *dims, int R, const double *X,
+               const double *const *H, int mode, double *M, int nthreads) {
+  if (N < 1 || N > ORC_MAXN || R < 1 || mode < 0 || mode >= N) return -1;
+  const int64_t I = prod_dims(N, dims);
+  const int64_t In = dims[mode];
+  if (nthreads < 1) nthreads = 1;
+  double *priv = (double *)calloc((size_t)nthreads * (size_t)(In * R), sizeof(double));
+  if (!priv) return -2;
+
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1)
+#endif
+  for (int t = 0; t < nthreads; ++t) {
+    const int64_t lo = I * t / nthreads, hi = I * (t + 1) / nthreads;
+    double *Mt = priv + (size_t)t * (size_t)(In * R);
+    int64_t idx[ORC_MAXN];
+    if (lo < hi) unravel(N, dims, lo, idx);
+    for (int64_t lin = lo; lin < hi; ++lin) {
+      const double x = X[lin];
+      for (int r = 0; r < R; ++r) {
+        double p = x;
+        for (int k = 0; k < N; ++k)
+          if (k != mode) p *= H[k][idx[k] * R + r];
+        Mt[idx[mode] * R + r] += p;
+      }
+      advance(N, dims, idx);
+    }
+  }
+  for (int64_t e = 0; e < In * R; ++e) {
+    double s = 0.0;
+    for (int t = 0; t < nthreads; ++t) s += priv[(size_t)t * (size_t)(In * R) + e];
+    M[e] = s;
+  }
+  free(priv);
+  return 0;
+}
+
+/*
+ * Selected rows of M^(n): for each requested i_n, sum over the (I / I_n)
+ * entries whose mode-n index is i_n.  Same definition as orc_mttkrp, used to
+ * check full-size problems row by row.
+ */
+int orc_mttkrp_rows(int N, const int64_t *dims, int R, const double *X,
+                    const double *const *H, int mode, const int64_t *rows,
+                    int nrows, double *out, int nthreads) {
+  if (N < 1 || N > ORC_MAXN || R < 1 || mode < 0 || mode >= N) return -1;
+  /* the other modes, in memory order */
+  int64_t odims[ORC_MAXN];
+  int omodes[ORC_MAXN], no = 0;
+  for (int k = 0; k < N; ++k)
+    if (k != mode) { odims[no] = dims[k]; omodes[no] = k; ++no; }
+  int64_t stride[ORC_MAXN];
+  stride[0] = 1;
+  for (int k = 1; k < N; ++k) stride[k] = stride[k - 1] * dims[k - 1];
+  const int64_t J = prod_dims(no, odims);
+  if (nthreads < 1) nthreads = 1;
+
+  for (int q = 0; q < nrows; ++q) {
+    const int64_t in = rows[q];
+    if (in < 0 || in >= dims[mode]) return -1;
+    double *priv = (double *)calloc((size_t)nthreads * (size_t)R, sizeof(double));
+    if (!priv) return -2;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1)
+#endif
+    for (int t = 0; t < nthreads; ++t) {
+      const int64_t lo = J * t / nthreads, hi = J * (t + 1) / nthreads;
+      double *acc = priv + (size_t)t * R;
+      int64_t oidx[ORC_MAXN];
+      if (lo < hi) unravel(no, odims, lo, oidx);
+      for (int64_t j = lo; j < hi; ++j) {
+        int64_t lin = in * stride[mode];
+        for (int a = 0; a < no; ++a) lin += oidx[a] * stride[omodes[a]];
+        const double x = X[lin];
+        for (int r = 0; r < R; ++r) {
+          double p = x;
+          for (int a = 0; a < no; ++a) p *= H[omodes[a]][oidx[a] * R + r];
+          acc[r] += p;
+        }
+        advance(no, odims, oidx);
+      }
+    }
+    for (int r = 0; r < R; ++r) {
+      double s = 0.0;
+      for (int t = 0; t < nthreads; ++t) s += priv[(size_t)t * R + r];
+      out[(size_t)q * R + r] = s;
+    }
+    free(priv);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gram, Hadamard of Grams, sum of squares                              */
+/* ------------------------------------------------------------------ */
+
+/* G = H^T H for an I x R row-major H (Algorithm 1, Gram lines). */
+void orc_gram(int64_t I, int R, const double *H, double *G) {
+  for (int a = 0; a < R; ++a)
+    for (int b = 0; b < R; ++b) {
+      double s = 0.0;
+      for (int64_t i = 0; i < I; ++i) s += H[i * R + a] * H[i * R + b];
+      G[a * R + b] = s;
+    }
+}
+
+/* S = Hadamard product of G[k] over k != mode (Algorithm 1, S^(n) line). */
+void orc_hadamard_except(int N, int R, const double *const *G, int mode, double *S) {
+  for (int e = 0; e < R * R; ++e) {
+    double s = 1.0;
+    for (int k = 0; k < N; ++k)
+      if (k != mode) s *= G[k][e];
+    S[e] = s;
+  }
+}
+
+double orc_sumsq(int64_t n, const double *X) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += X[i] * X[i];
+  return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* factor updates on Hhat = H^(n) diag(lambda)                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Multiplicative update, Eq. (eqn:muupd) written for the factor matrix
+ * (X = H^T, A^T B = M^T, A^T A = S):
+ *   Hhat[i,r] <- Hhat[i,r] * M[i,r] / ((Hhat S)[i,r] + eps).
+ * All entries use the Hhat from before the update.
+ */
+void orc_update_mu(int64_t I, int R, double *Hhat, const double *M,
+                   const double *S, double eps) {
+  double *old = (double *)malloc(sizeof(double) * (size_t)R);
+  for (int64_t i = 0; i < I; ++i) {
+    for (int c = 0; c < R; ++c) old[c] = Hhat[i * R + c];
+    for (int r = 0; r < R; ++r) {
+      double hs = 0.0;
+      for (int c = 0; c < R; ++c) hs += old[c] * S[c * R + r];
+      Hhat[i * R + r] = old[r] * M[i * R + r] / (hs + eps);
+    }
+  }
+  free(old);
+}
+
+/*
+ * HALS, Eq. (eqn:halsupd) written for the factor matrix: for r = 0..R-1 in
+ * order, column r of Hhat becomes
+ *   max(0, Hhat[:,r] + (M[:,r] - (Hhat S)[:,r]) / S[r,r]),
+ * where Hhat already holds the new columns 0..r-1.  A column with S[r,r] = 0
+ * is left unchanged.
+ */
+void orc_update_hals(int64_t I, int R, double *Hhat, const double *M, const double *S) {
+  for (int r = 0; r < R; ++r) {
+    const double d = S[r * R + r];
+    if (!(d > 0.0)) continue;
+    for (int64_t i = 0; i < I; ++i) {
+      double hs = 0.0;
+      for (int c = 0; c < R; ++c) hs += Hhat[i * R + c] * S[c * R + r];
+      const double v = Hhat[i * R + r] + (M[i * R + r] - hs) / d;
+      Hhat[i * R + r] = v > 0.0 ? v : 0.0;
+    }
+  }
+}
+
+/*
+ * Column normalisation (Algorithm 4, column-norm and column-scale lines):
+ * lambda_r = ||Hhat[:,r]||_2 and H[:,r] = Hhat[:,r] / lambda_r, or a zero
+ * column with lambda_r = 0.
+ */
+void orc_normalize(int64_t I, int R, const double *Hhat, double *H, double *lambda) {
+  for (int r = 0; r < R; ++r) {
+    double s = 0.0;
+    for (int64_t i = 0; i < I; ++i) s += Hhat[i * R + r] * Hhat[i * R + r];
+    const double l = sqrt(s);
+    lambda[r] = l;
+    for (int64_t i = 0; i < I; ++i) H[i * R + r] = l > 0.0 ? Hhat[i * R + r] / l : 0.0;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* alternating-update sweeps                                            */
+/* ------------------------------------------------------------------ */
+
+enum { ORC_MU = 0, ORC_HALS = 1 };
+
+/*
+ * nsweeps outer iterations of Algorithm 1 with the local steps of
+ * Algorithm 4 (normalisation and relative error).  H[n] (I_n x R) and
+ * lambda (R) are the start iterate on entry and the result on exit.
+ * relerr[s] receives the relative error after sweep s from the identity;
+ * relerr2_raw[s] (may be NULL) the unclamped squared relative error.
+ * Returns 0, or a negative value on bad arguments.
+ */
+int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const *H,
+               double *lambda, int algo, double eps_mu, int nsweeps,
+               double *relerr, double *relerr2_raw, int nthreads) {
+  if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0) return -1;
+  if (algo != ORC_MU && algo != ORC_HALS) return -1;
+  const int64_t I = prod_dims(N, dims);
+  double *G[ORC_MAXN];
+  int64_t maxI = 0;
+  for (int k = 0; k < N; ++k) {
+    G[k] = (double *)malloc(sizeof(double) * (size_t)R * R);
+    orc_gram(dims[k], R, H[k], G[k]);
+    if (dims[k] > maxI) maxI = dims[k];
+  }
+  double *M = (double *)malloc(sizeof(double) * (size_t)(maxI * R));
+  double *Hhat = (double *)malloc(sizeof(double) * (size_t)(maxI * R));
+  double *S = (double *)malloc(sizeof(double) * (size_t)R * R);
+  const double alpha = orc_sumsq(I, X);
+
+  for (int s = 0; s < nsweeps; ++s) {
+    double beta = 0.0, gamma = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const int64_t In = dims[n];
+      orc_mttkrp(N, dims, R, X, (const double *const *)H, n, M, nthreads);
+      orc_hadamard_except(N, R, (const double *const *)G, n, S);
+      for (int64_t i = 0; i < In; ++i)
+        for (int r = 0; r < R; ++r) Hhat[i * R + r] = H[n][i * R + r] * lambda[r];
+      if (algo == ORC_MU)
+        orc_update_mu(In, R, Hhat, M, S, eps_mu);
+      else
+        orc_update_hals(In, R, Hhat, M, S);
+      orc_normalize(In, R, Hhat, H[n], lambda);
+      orc_gram(In, R, H[n], G[n]);
+      if (n == N - 1) {
+        /* beta = <M^(N), Hhat^(N)>, gamma = lambda^T (S^(N) * G^(N)) lambda */
+        for (int64_t e = 0; e < In * R; ++e) beta += M[e] * Hhat[e];
+        for (int a = 0; a < R; ++a)
+          for (int b = 0; b < R; ++b)
+            gamma += lambda[a] * S[a * R + b] * G[n][a * R + b] * lambda[b];
+      }
+    }
+    const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+    if (relerr2_raw) relerr2_raw[s] = e2;
+    relerr[s] = sqrt(e2 > 0.0 ? e2 : 0.0);
+  }
+  for (int k = 0; k < N; ++k) free(G[k]);
+  free(M);
+  free(Hhat);
+  free(S);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* direct residual, loss and gradient                                   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * E = [[lambda; H]] - X written out entry by entry (lambda may be NULL for
+ * all ones); returns 0.5 * ||E||^2.  If E is not NULL the residual is stored.
+ */
+double orc_residual(int N, const int64_t *dims, int R, const double *X,
+                    const double *const *H, const double *lambda, double *E) {
+  const int64_t I = prod_dims(N, dims);
+  int64_t idx[ORC_MAXN];
+  for (int k = 0; k < N; ++k) idx[k] = 0;
+  double s = 0.0;
+  for (int64_t lin = 0; lin < I; ++lin) {
+    double m = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double p = lambda ? lambda[r] : 1.0;
+      for (int k = 0; k < N; ++k) p *= H[k][idx[k] * R + r];
+      m += p;
+    }
+    const double e = m - X[lin];
+    if (E) E[lin] = e;
+    s += e * e;
+    advance(N, dims, idx);
+  }
+  return 0.5 * s;
+}
+
+/*
+ * Gradient of L = 0.5 ||X - [[H]]||^2 (all lambda = 1) with respect to every
+ * factor: dL/dH^(n) = MTTKRP(E, n) with E = [[H]] - X the explicit residual
+ * tensor.  grads[n] is I_n x R.  Returns L.
+ */
+double orc_grad(int N, const int64_t *dims, int R, const double *X,
+                const double *const *H, double *const *grads, int nthreads) {
+  const int64_t I = prod_dims(N, dims);
+  double *E = (double *)malloc(sizeof(double) * (size_t)I);
+  const double L = orc_residual(N, dims, R, X, H, NULL, E);
+  for (int n = 0; n < N; ++n) orc_mttkrp(N, dims, R, E, H, n, grads[n], nthreads);
+  free(E);
+  return L;
+}
+
+/* ------------------------------------------------------------------ */
+/* projected gradient with Armijo backtracking                          */
+/* ------------------------------------------------------------------ */
+
+/* largest eigenvalue of a symmetric R x R matrix by `iters` power steps from
+ * the all-ones vector (the matrices used here are entrywise nonnegative). */
+double orc_power_lmax(int R, const double *A, int iters) {
+  double *v = (double *)malloc(sizeof(double) * R), *w = (double *)malloc(sizeof(double) * R);
+  for (int i = 0; i < R; ++i) v[i] = 1.0 / sqrt((double)R);
+  double lam = 0.0;
+  for (int t = 0; t < iters; ++t) {
+    double nrm = 0.0;
+    for (int i = 0; i < R; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < R; ++j) s += A[i * R + j] * v[j];
+      w[i] = s;
+      nrm += s * s;
+    }
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0)) { lam = 0.0; break; }
+    for (int i = 0; i < R; ++i) v[i] = w[i] / nrm;
+  }
+  {
+    double num = 0.0;
+    for (int i = 0; i < R; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < R; ++j) s += A[i * R + j] * v[j];
+      num += v[i] * s;
+    }
+    lam = num;
+  }
+  free(v);
+  free(w);
+  return lam;
+}
+
+/*
+ * nsteps projected-gradient steps on L = 0.5 ||X - [[H]]||^2 (lambda = 1,
+ * no normalisation).  Each step: gradients at the current point; step
+ * eta0 = 1 / max_n lmax(S^(n)) (lmax by `power_iters` power steps);
+ * trial H' = max(0, H - eta grad) for all modes at once; accept when
+ * L(H') <= L(H) - armijo_c * sum_n ||H' - H||^2 / eta, otherwise halve eta,
+ * at most max_halvings times; if no trial is accepted H is left unchanged.
+ * loss_hist[t] is L after step t, eta_hist[t] (may be NULL) the accepted eta
+ * (0 if rejected).
+ */
+int orc_pgd(int N, const int64_t *dims, int R, const double *X, double *const *H,
+            int nsteps, double armijo_c, int max_halvings, int power_iters,
+            double *loss_hist, double *eta_hist, int nthreads) {
+  if (N < 2 || N > ORC_MAXN || R < 1) return -1;
+  double *grads[ORC_MAXN], *Hn[ORC_MAXN], *G[ORC_MAXN];
+  for (int k = 0; k < N; ++k) {
+    grads[k] = (double *)malloc(sizeof(double) * (size_t)(dims[k] * R));
+    Hn[k] = (double *)malloc(sizeof(double) * (size_t)(dims[k] * R));
+    G[k] = (double *)malloc(sizeof(double) * (size_t)R * R);
+  }
+  double *S = (double *)malloc(sizeof(double) * (size_t)R * R);
+  for (int t = 0; t < nsteps; ++t) {
+    const double L = orc_grad(N, dims, R, X, (const double *const *)H, grads, nthreads);
+    double lmax = 0.0;
+    for (int k = 0; k < N; ++k) orc_gram(dims[k], R, H[k], G[k]);
+    for (int n = 0; n < N; ++n) {
+      orc_hadamard_except(N, R, (const double *const *)G, n, S);
+      const double l = orc_power_lmax(R, S, power_iters);
+      if (l > lmax) lmax = l;
+    }
+    double eta = lmax > 0.0 ? 1.0 / lmax : 1.0;
+    double accepted = 0.0, Lnew = L;
+    for (int h = 0; h <= max_halvings; ++h) {
+      double d = 0.0;
+      for (int k = 0; k < N; ++k)
+        for (int64_t e = 0; e < dims[k] * R; ++e) {
+          const double v = H[k][e] - eta * grads[k][e];
+          Hn[k][e] = v > 0.0 ? v : 0.0;
+          d += (Hn[k][e] - H[k][e]) * (Hn[k][e] - H[k][e]);
+        }
+      const double Lt = orc_residual(N, dims, R, X, (const double *const *)Hn, NULL, NULL);
+      if (Lt <= L - armijo_c * d / eta) {
+        accepted = eta;
+        Lnew = Lt;
+        for (int k = 0; k < N; ++k)
+          memcpy(H[k], Hn[k], sizeof(double) * (size_t)(dims[k] * R));
+        break;
+      }
+      eta *= 0.5;
+    }
+    loss_hist[t] = Lnew;
+    if (eta_hist) eta_hist[t] = accepted;
+  }
+  for (int k = 0; k < N; ++k) { free(grads[k]); free(Hn[k]); free(G[k]); }
+  free(S);
+  return 0;
+}
