@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the NNCP hot path on one MI355X.
+
+Workload: a 512 x 512 x 512 nonnegative tensor (rank-32 uniform factors plus
+5% |Gaussian| noise), rank R = 32, HALS updates.  One step = one sweep of
+Algorithm 1 over all three modes (MTTKRP through the dimension tree, Gram /
+Hadamard, HALS update, normalisation, relative error).  The timed region runs
+`--steps` sweeps (50 by default, the workload's sweep count) from the start
+factors, for two forms of the same problem on the same GPU:
+  fp32  FP32 tensor, FP32 matrix-core partial MTTKRP
+  bf16  the tensor rounded once to BF16, BF16 matrix-core partial MTTKRP with
+        FP32 accumulation (the reported `value`)
+Inputs are resident in HBM before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "MTTKRP HBM GB/s and NNCP sweeps/s, BF16-MFMA vs FP32 at stated rel error"
+WORKLOAD = "512x512x512 rank-32 uniform + 5% |gaussian| noise, R=32, HALS, 50 sweeps"
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_01149_amd", "csrc", "partial_mttkrp.hip")
+CAT_NAMES = ["gemm_left", "gemm_right", "krp", "mttv", "update"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, or None if it
+    is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_form(nn, torch, X, H0, steps, warmup, algo):
+    """Warm up, reset to the start factors, then time `steps` sweeps."""
+    dev = X.device
+    H = [h.clone() for h in H0]
+    lam = torch.ones(H0[0].shape[1], dtype=torch.float64, device=dev)
+    ctx = nn.Context(X, H, lam)
+    if warmup > 0:
+        ctx.sweep(algo, warmup)
+    torch.cuda.synchronize()
+    for f, h0 in zip(ctx.factors, H0):
+        f.copy_(h0)
+    ctx.lam.fill_(1.0)
+    ctx.set_factors(ctx.factors, ctx.lam)
+    rel = torch.empty(max(1, steps), dtype=torch.float64, device=dev)
+    ctx.timers_enable(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    ctx.sweep(algo, steps, rel)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    cat_ms, cat_n = ctx.timers_read()
+    ctx.timers_enable(False)
+    return ctx, dict(ms=ms, wall_s=wall, relerr=rel.cpu().tolist()[:steps], cat_ms=cat_ms,
+                     cat_n=cat_n)
+
+
+def gemm_bytes(dims, R, xbytes, side):
+    """Algorithmic bytes of one partial MTTKRP: the tensor once plus the
+    output temporary (the Khatri-Rao operand is formed on chip)."""
+    import math
+    I = math.prod(dims)
+    m = dims[0] * dims[1]
+    k = dims[2]
+    out_rows = m if side == 0 else k
+    return I * xbytes + out_rows * R * 4
+
+
+def cpu_baseline(X32, H0, algo_oracle, nthreads):
+    import numpy as np
+    import oracle
+    Xh = X32.double().cpu().numpy().reshape(-1)
+    Hh = [h.double().cpu().numpy() for h in H0]
+    R = Hh[0].shape[1]
+    t0 = time.perf_counter()
+    oracle.sweeps(Xh, Hh, np.ones(R), algo_oracle, 1, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="sweeps/s", cores=nthreads, kind="oracle",
+                sample=f"one HALS sweep (3 MTTKRPs by definition + updates) of the same 512^3 "
+                       f"tensor in FP64, {dt:.2f} s on {nthreads} host threads")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import nncp_inputs as gen
+    import paper_1909_01149_amd as nn
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating 512^3 workload on the GPU")
+    w = gen.workload2(device="cuda:0", keep_fp32=False)
+    dims, R = w["dims"], w["R"]
+    H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+    torch.cuda.synchronize()
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    res = {}
+    ctxs = {}
+    for form, X in (("fp32", w["X32"]), ("bf16", w["Xbf16"])):
+        log(f"timing {form}: {args.warmup} warmup + {args.steps} sweeps")
+        ctx, r = run_form(nn, torch, X, H0, args.steps, args.warmup, nn.NNCP_HALS)
+        r["paths"] = [ctx.gemm_path(0), ctx.gemm_path(1)]
+        res[form] = r
+        ctxs[form] = ctx
+        log(form, f"{r['ms'] / max(1, args.steps):.4f} ms/sweep", "cat_ms", [round(x, 3) for x in r["cat_ms"]],
+            "launches", r["cat_n"], "final relerr", r["relerr"][-1] if r["relerr"] else None)
+
+    # BF16 run's final error measured against the unrounded FP32 tensor
+    rel_bf16_vs_fp32 = None
+    if args.steps > 0:
+        c32 = ctxs["fp32"]
+        cb = ctxs["bf16"]
+        c32.set_factors(cb.factors, cb.lam)
+        rel_bf16_vs_fp32 = float(c32.cp_loss()[1].item())
+
+    steps = max(1, args.steps)
+    b = res["bf16"]
+    f = res["fp32"]
+    sweeps_bf16 = steps / (b["ms"] / 1e3)
+    sweeps_fp32 = steps / (f["ms"] / 1e3)
+
+    def gbps(form, side):
+        r = res[form]
+        n = r["cat_n"][side]
+        if n == 0:
+            return None, None
+        avg_ms = r["cat_ms"][side] / n
+        xb = 2 if form == "bf16" else 4
+        return gemm_bytes(dims, R, xb, side) / (avg_ms / 1e3) / 1e9, avg_ms
+
+    mt = {}
+    for form in ("fp32", "bf16"):
+        for side, name in ((0, "gemm_left"), (1, "gemm_right")):
+            g, a = gbps(form, side)
+            mt[f"{form}_{name}"] = {"GBps": g, "avg_ms": a}
+    # dominant kernel of the reported (bf16) form
+    dom_side = 0 if b["cat_ms"][0] >= b["cat_ms"][1] else 1
+    dom_name = CAT_NAMES[dom_side]
+    ach, avg_ms = gbps("bf16", dom_side)
+    traffic = read_traffic(f"bf16_{dom_name}")
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": (ach / HBM_PEAK_GBPS) if ach else None, "traffic": traffic,
+            "kernel": f"bf16 {dom_name} partial MTTKRP", "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": gemm_bytes(dims, R, 2, dom_side)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthr = min(16, os.cpu_count() or 1)
+        log(f"timing the oracle on {nthr} host threads (one sweep)")
+        cpu = cpu_baseline(w["X32"], H0, oracle.HALS, nthr)
+
+    out = {
+        "metric": METRIC,
+        "value": sweeps_bf16,
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": b["ms"] / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded; rank-32 uniform factors + 5% |gaussian| noise)",
+        "config": {"workload": WORKLOAD, "dims": dims, "R": R, "algo": "hals",
+                   "tensor_dtype": "bf16", "accumulate": "fp32", "factors": "fp32",
+                   "krp_operand": "bf16 hi+lo", "parallelism": "single GPU"},
+        "fp32_form": {"sweeps_per_s": sweeps_fp32, "ms_per_step": f["ms"] / steps,
+                      "final_relerr": f["relerr"][-1] if f["relerr"] else None},
+        "bf16_form": {"sweeps_per_s": sweeps_bf16,
+                      "final_relerr": b["relerr"][-1] if b["relerr"] else None,
+                      "final_relerr_vs_fp32_tensor": rel_bf16_vs_fp32},
+        "bf16_speedup_over_fp32": sweeps_bf16 / sweeps_fp32,
+        "mttkrp": mt,
+        "category_ms_per_sweep": {form: {CAT_NAMES[k]: res[form]["cat_ms"][k] / steps for k in range(5)}
+                                  for form in res},
+        "wall_s": {form: res[form]["wall_s"] for form in res},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * nncp.h -- C ABI of the MI355X (gfx950) library for dense nonnegative CP
+ * decomposition (NNCP) by alternating updates, after PLANC
+ * (Eswar, Hayashi, Ballard, Kannan, Matheson, Park; arXiv 1909.01149).
+ *
+ * Problem (Section 1, Eq. eqn:nncp): given a nonnegative N-way tensor X of
+ * size I_0 x ... x I_{N-1}, find nonnegative factors H^(n) (I_n x R) that
+ * minimise || X - sum_r H^(0)(:,r) o ... o H^(N-1)(:,r) ||^2.  The library
+ * computes the alternating-update iteration of Algorithm 1: for each mode n,
+ * the MTTKRP M^(n), the Hadamard product S^(n) of the other Gram matrices,
+ * an MU (Eq. eqn:muupd) or HALS (Eq. eqn:halsupd) update, column
+ * normalisation, and the relative error through the identity of the
+ * appendix (Algorithm 4).  MTTKRP runs through the dimension tree of
+ * Section 3.2 (Algorithm 3): two partial MTTKRPs (one GEMM each) at the root
+ * and multi-TTVs below.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Modes are 0-based (the paper numbers them from 1).
+ *
+ * Tensor layout: X is dense, mode 0 varies fastest: entry (i_0, ..., i_{N-1})
+ * is at linear index i_0 + I_0 (i_1 + I_1 (i_2 + ...))  (the paper's
+ * "mode-descending, generalizing column-major" order, Section 3.1.1).  In
+ * PyTorch this is a contiguous tensor of shape (I_{N-1}, ..., I_0).
+ *
+ * Factor layout: H^(n) is I_n x R, row-major (entry (i, r) at i*R + r).  The
+ * paper's factors are column-major; the transposition keeps each row's R
+ * values together for the row-parallel updates.  MTTKRP outputs M and
+ * gradients use the same layout and the factor dtype.
+ *
+ * Dtypes (x_dtype, h_dtype): (NNCP_F64, NNCP_F64) "FP64 mode", (NNCP_F32,
+ * NNCP_F32), (NNCP_BF16, NNCP_F32), (NNCP_F16, NNCP_F32).  Anything else
+ * returns NNCP_E_DTYPE.  Partial-MTTKRP accumulation, dimension-tree
+ * temporaries and M use the factor dtype; Gram matrices, S, lambda, the loss
+ * and all scalar reductions are FP64.
+ *
+ * Memory: every pointer argument is device memory unless its comment says
+ * "host".  X, H, lambda, outputs and the workspace belong to the caller and
+ * are borrowed until nncp_destroy; the library never allocates or frees
+ * device memory.  X is only read.  H and lambda are updated in place by
+ * nncp_update_*, nncp_sweep and nncp_pgd.  Device pointers must be 16-byte
+ * aligned.
+ *
+ * Streams: every kernel is launched on the stream given to nncp_init (a
+ * hipStream_t passed as void*; NULL is the default stream).  Calls are
+ * asynchronous and outputs are valid once the stream has been synchronised,
+ * except nncp_pgd, which synchronises to take its step-size decisions.
+ *
+ * Errors: every call returns an int status.  Arguments are validated before
+ * anything is launched, so a failing call launches nothing.  A HIP launch
+ * failure returns NNCP_E_HIP.  nncp_last_error() gives a message for the
+ * calling thread's last failure.  No C++ exception crosses the ABI.  A
+ * context belongs to one stream and is not thread-safe.
+ */
+#ifndef NNCP_H
+#define NNCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NNCP_MAX_MODES 16
+
+enum nncp_status {
+  NNCP_OK = 0,
+  NNCP_E_INVAL = -1,       /* N, dims, R, mode, algo or a pointer is invalid     */
+  NNCP_E_DTYPE = -2,       /* unsupported (x_dtype, h_dtype) pair                */
+  NNCP_E_WORKSPACE = -3,   /* workspace smaller than nncp_workspace_size()       */
+  NNCP_E_HIP = -4,         /* a HIP call or kernel launch failed                 */
+  NNCP_E_STATE = -5,       /* context is NULL or already destroyed               */
+  NNCP_E_UNSUPPORTED = -6  /* valid request outside this build's limits (R>256)  */
+};
+
+enum nncp_dtype { NNCP_F64 = 0, NNCP_F32 = 1, NNCP_BF16 = 2, NNCP_F16 = 3 };
+
+enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1 };
+
+/* Options (pass NULL for the defaults, shown in brackets). */
+typedef struct nncp_options {
+  int split;        /* root split: modes 0..split-1 form the left subtree.  0 =
+                       automatic [0]: the smallest S with
+                       prod(I_0..I_{S-1}) >= prod(I_S..I_{N-1}), clamped to
+                       [1, N-1] (Section 3.2.2; ">=" is the reading of "greater
+                       than" that gives a balanced split for equal halves).  */
+  int krp_split;    /* BF16/FP16 tensors: 1 = feed the Khatri-Rao operand to the
+                       matrix cores as a hi+lo pair of the tensor's type (error
+                       about 2^-16 instead of 2^-8), 0 = single rounding [1]. */
+  int generic;      /* 1 = force the portable vector-ALU partial-MTTKRP kernels
+                       instead of the matrix-core ones [0].                    */
+  double eps_mu;    /* MU denominator guard (Eq. eqn:muupd: "a small value is
+                       added to the denominator") [1e-16].                     */
+} nncp_options;
+
+typedef struct nncp_ctx nncp_ctx;
+
+/*
+ * Bytes of device workspace that nncp_init needs for this problem.  Returns 0
+ * if the arguments are invalid (see nncp_last_error).
+ *   N      number of modes, 2..NNCP_MAX_MODES
+ *   dims   host array of N mode sizes, each >= 1
+ *   R      rank, 1..256
+ */
+size_t nncp_workspace_size(int N, const int64_t *dims, int R, int x_dtype, int h_dtype,
+                           const nncp_options *opt);
+
+/*
+ * Create a context and run the initialisation of Algorithm 1 / Algorithm 4:
+ * the Gram matrix G^(n) = H^(n)^T H^(n) of every factor and alpha = ||X||^2.
+ *   ctx        host out: the new context
+ *   X          tensor (layout above), x_dtype, prod(dims) entries
+ *   H          host array of N device pointers to the factors (start iterate,
+ *              all N modes; Algorithm 1 initialises only modes 2..N but MU and
+ *              HALS need a start value for every mode)
+ *   lambda     R FP64 column weights of the model [[lambda; H]] (pass ones
+ *              for an unnormalised start)
+ *   workspace  device buffer of at least nncp_workspace_size() bytes
+ *   stream     hipStream_t, may be NULL
+ */
+int nncp_init(nncp_ctx **ctx, int N, const int64_t *dims, int R, int x_dtype, const void *X,
+              int h_dtype, void *const *H, double *lambda, void *workspace, size_t ws_bytes,
+              void *stream, const nncp_options *opt);
+
+/* Point the context at other factor / lambda buffers of the same shapes and
+ * recompute the Gram matrices (lambda may be NULL to keep the current one). */
+int nncp_set_factors(nncp_ctx *ctx, void *const *H, double *lambda);
+
+/*
+ * MTTKRP of one mode at the current factors (Algorithm 1, MTTKRP line):
+ *   M^(n) = X_(n) (H^(N-1) kr ... kr H^(n+1) kr H^(n-1) kr ... kr H^(0)),
+ * computed through the dimension tree (Algorithm 3 with the transposes and
+ * Khatri-Rao ranges corrected): the partial MTTKRP at the root of n's
+ * subtree, then multi-TTVs down to n.  One pass over X.
+ *   M  I_n x R, row-major, h_dtype.
+ */
+int nncp_mttkrp(nncp_ctx *ctx, int mode, void *M);
+
+/* G^(n) = H^(n)^T H^(n) (R x R, FP64, row-major) of the current factor; also
+ * refreshes the context's copy used for S^(n). */
+int nncp_gram(nncp_ctx *ctx, int mode, double *G);
+
+/* S^(n) = Hadamard product of G^(k) for k != n (Algorithm 1), R x R FP64. */
+int nncp_hadamard(nncp_ctx *ctx, int mode, double *S);
+
+/*
+ * One factor update of mode n from M = M^(n) (I_n x R, h_dtype) and
+ * S = S^(n) (R x R FP64):  Hhat = H^(n) diag(lambda) (lambda folded into the
+ * factor being solved for, Appendix A), then
+ *   MU   (Eq. eqn:muupd):  Hhat <- Hhat * M / (Hhat S + eps)   [eps < 0: the
+ *                          context's eps_mu]
+ *   HALS (Eq. eqn:halsupd): for r = 0..R-1 in order, if S(r,r) > 0,
+ *                          Hhat(:,r) <- max(0, Hhat(:,r) + (M(:,r) - Hhat S(:,r)) / S(r,r))
+ * then lambda_r = ||Hhat(:,r)||_2, H^(n)(:,r) = Hhat(:,r) / lambda_r (a zero
+ * column stays zero with lambda_r = 0), and G^(n) is recomputed.
+ */
+int nncp_update_mu(nncp_ctx *ctx, int mode, const void *M, const double *S, double eps);
+int nncp_update_hals(nncp_ctx *ctx, int mode, const void *M, const double *S);
+
+/*
+ * Loss of the current model through the identity of the appendix:
+ *   ||X - [[lambda; H]]||^2 = alpha - 2 <M^(N-1), H^(N-1) diag(lambda)>
+ *                             + lambda^T (Hadamard of all G) lambda.
+ *   loss    1 FP64: 0.5 * ||X - [[lambda; H]]||^2 (may be NULL)
+ *   relerr  1 FP64: sqrt(max(0, ||X - model||^2) / alpha) (may be NULL)
+ * Costs one pass over X.
+ */
+int nncp_cp_loss(nncp_ctx *ctx, double *loss, double *relerr);
+
+/*
+ * nsweeps outer iterations of Algorithm 1 (modes 0..N-1 in order), each mode
+ * as nncp_mttkrp + nncp_update_*, with the dimension-tree temporaries reused
+ * across modes as in Algorithm 3 (two passes over X per sweep).  After mode
+ * N-1 the relative error is formed from that mode's M and Hhat (Algorithm 4):
+ *   relerr_hist  nsweeps FP64: relative error after each sweep (may be NULL)
+ */
+int nncp_sweep(nncp_ctx *ctx, int algo, int nsweeps, double *relerr_hist);
+
+/*
+ * Gradient of L = 0.5 ||X - [[H]]||^2 (lambda treated as all ones, no
+ * normalisation) with respect to every factor at the current point:
+ *   dL/dH^(n) = H^(n) S^(n) - M^(n),
+ * with all N MTTKRPs at the same point (two passes over X).
+ *   grads  host array of N device pointers, each I_n x R h_dtype
+ *   loss   1 FP64: L via the identity (may be NULL)
+ */
+int nncp_grad(nncp_ctx *ctx, void *const *grads, double *loss);
+
+/*
+ * nsteps projected-gradient steps on L = 0.5 ||X - [[H]]||^2 (lambda = 1):
+ * gradients at the current point, eta0 = 1 / max_n lmax(S^(n)) (lmax from
+ * power_iters power-iteration steps from the all-ones vector), trial
+ * H' = max(0, H - eta grad) for all modes at once, accepted when
+ * L(H') <= L(H) - armijo_c * sum_n ||H' - H||^2 / eta, else eta is halved,
+ * at most max_halvings times; without an accepted trial H is unchanged.
+ *   loss_hist, eta_hist  host arrays of nsteps FP64 (may be NULL): L after
+ *                        each step and the accepted eta (0 when rejected)
+ * Synchronises the stream once per trial.  Needs R <= 64 (else
+ * NNCP_E_UNSUPPORTED).
+ */
+int nncp_pgd(nncp_ctx *ctx, int nsteps, double armijo_c, int max_halvings, int power_iters,
+             double *loss_hist, double *eta_hist);
+
+/*
+ * Per-category GPU time, from HIP events recorded on the context's stream
+ * around each launch while timing is enabled (the time-breakdown categories
+ * of the paper's experiments, restricted to one GPU):
+ *   0  left partial MTTKRP kernel (GEMM over modes S..N-1)
+ *   1  right partial MTTKRP kernel (GEMM over modes 0..S-1)
+ *   2  Khatri-Rao operands of the partial MTTKRPs
+ *   3  multi-TTVs and split-reduction finalize
+ *   4  factor update (MU/HALS, normalisation, Gram, relative error)
+ * nncp_timers_enable(ctx, 1) starts recording (and clears the totals);
+ * nncp_timers_read synchronises the stream and returns the totals in
+ * milliseconds and the number of timed launches per category (host arrays of
+ * NNCP_TIMER_CATEGORIES entries).  Recording adds two event records per
+ * launch; it allocates no device memory.
+ */
+#define NNCP_TIMER_CATEGORIES 5
+int nncp_timers_enable(nncp_ctx *ctx, int on);
+int nncp_timers_read(nncp_ctx *ctx, double *ms, int64_t *launches);
+
+/* Release the context (host memory only; borrowed buffers are untouched). */
+int nncp_destroy(nncp_ctx *ctx);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char *nncp_last_error(void);
+
+/* Root split S chosen for this context (modes 0..S-1 on the left). */
+int nncp_split(const nncp_ctx *ctx);
+
+/*
+ * Kernel path chosen for the two partial MTTKRPs (side 0 = left, reduces over
+ * modes S..N-1; side 1 = right, reduces over modes 0..S-1): 1 = matrix cores
+ * (MFMA), 0 = vector ALU.  Returns NNCP_E_INVAL for a bad side.
+ */
+int nncp_gemm_path(const nncp_ctx *ctx, int side);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNCP_H */

@@ -1,0 +1,343 @@
+"""ctypes binding of libnncp.so: the C ABI of include/nncp.h under the same
+names, taking torch tensors for device buffers.  Argument marshalling only:
+every step of the computation runs in the library's HIP kernels.
+
+Tensors: X is a contiguous tensor of shape (I_{N-1}, ..., I_0) (mode 0
+fastest) or a flat contiguous tensor of prod(dims) entries; factors are
+contiguous (I_n, R); lambda, Gram and loss buffers are float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnncp.so")
+
+NNCP_OK = 0
+NNCP_E_INVAL = -1
+NNCP_E_DTYPE = -2
+NNCP_E_WORKSPACE = -3
+NNCP_E_HIP = -4
+NNCP_E_STATE = -5
+NNCP_E_UNSUPPORTED = -6
+
+NNCP_F64, NNCP_F32, NNCP_BF16, NNCP_F16 = 0, 1, 2, 3
+NNCP_MU, NNCP_HALS = 0, 1
+NNCP_MAX_MODES = 16
+
+EXPORTS = [
+    "nncp_workspace_size", "nncp_init", "nncp_set_factors", "nncp_mttkrp", "nncp_gram",
+    "nncp_hadamard", "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep",
+    "nncp_grad", "nncp_pgd", "nncp_destroy", "nncp_last_error", "nncp_split",
+    "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read",
+]
+NNCP_TIMER_CATEGORIES = 5
+
+_DT = {torch.float64: NNCP_F64, torch.float32: NNCP_F32, torch.bfloat16: NNCP_BF16,
+       torch.float16: NNCP_F16}
+
+
+class NNCPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nncp error {code}: {msg}")
+        self.code = code
+
+
+class nncp_options(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_int), ("krp_split", ctypes.c_int), ("generic", ctypes.c_int),
+                ("eps_mu", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnncp.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          f"`python -m paper_1909_01149_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    ci, cd, optp = ctypes.c_int, ctypes.c_double, ctypes.POINTER(nncp_options)
+    dp = ctypes.c_void_p
+    L.nncp_workspace_size.argtypes = [ci, i64p, ci, ci, ci, optp]
+    L.nncp_workspace_size.restype = ctypes.c_size_t
+    L.nncp_init.argtypes = [ctypes.POINTER(vp), ci, i64p, ci, ci, vp, ci, ctypes.POINTER(vp), dp, vp,
+                            ctypes.c_size_t, vp, optp]
+    L.nncp_set_factors.argtypes = [vp, ctypes.POINTER(vp), dp]
+    L.nncp_mttkrp.argtypes = [vp, ci, vp]
+    L.nncp_gram.argtypes = [vp, ci, dp]
+    L.nncp_hadamard.argtypes = [vp, ci, dp]
+    L.nncp_update_mu.argtypes = [vp, ci, vp, dp, cd]
+    L.nncp_update_hals.argtypes = [vp, ci, vp, dp]
+    L.nncp_cp_loss.argtypes = [vp, dp, dp]
+    L.nncp_sweep.argtypes = [vp, ci, ci, dp]
+    L.nncp_grad.argtypes = [vp, ctypes.POINTER(vp), dp]
+    L.nncp_pgd.argtypes = [vp, ci, cd, ci, ci, ctypes.POINTER(cd), ctypes.POINTER(cd)]
+    L.nncp_destroy.argtypes = [vp]
+    L.nncp_last_error.restype = ctypes.c_char_p
+    L.nncp_split.argtypes = [vp]
+    L.nncp_gemm_path.argtypes = [vp, ci]
+    L.nncp_timers_enable.argtypes = [vp, ci]
+    L.nncp_timers_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_int64)]
+    for name in ("nncp_timers_enable", "nncp_timers_read",
+                 "nncp_init", "nncp_set_factors", "nncp_mttkrp", "nncp_gram", "nncp_hadamard",
+                 "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep", "nncp_grad",
+                 "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path"):
+        getattr(L, name).restype = ci
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise NNCPError(rc, lib().nncp_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dims(dims):
+    arr = (ctypes.c_int64 * len(dims))(*[int(d) for d in dims])
+    return arr
+
+
+def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16):
+    return nncp_options(int(split), int(krp_split), int(generic), float(eps_mu))
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# functions with the C names (thin wrappers)
+# ---------------------------------------------------------------------------
+
+def nncp_workspace_size(dims, R, x_dtype, h_dtype, **opts) -> int:
+    o = _opts(**opts)
+    n = lib().nncp_workspace_size(len(dims), _dims(dims), int(R), int(x_dtype), int(h_dtype),
+                                  ctypes.byref(o))
+    if n == 0:
+        raise NNCPError(NNCP_E_INVAL, lib().nncp_last_error().decode())
+    return int(n)
+
+
+def nncp_init(dims, R, X, factors, lam, workspace, **opts) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    o = _opts(**opts)
+    x_dt, h_dt = _DT[X.dtype], _DT[factors[0].dtype]
+    _check(lib().nncp_init(ctypes.byref(ctx), len(dims), _dims(dims), int(R), x_dt, _ptr(X), h_dt,
+                           _ptr_array(factors), _ptr(lam), _ptr(workspace),
+                           workspace.numel() * workspace.element_size(),
+                           _stream_handle(X.device), ctypes.byref(o)))
+    return ctx
+
+
+def nncp_set_factors(ctx, factors, lam=None):
+    return _check(lib().nncp_set_factors(ctx, _ptr_array(factors), _ptr(lam)))
+
+
+def nncp_mttkrp(ctx, mode, M):
+    return _check(lib().nncp_mttkrp(ctx, int(mode), _ptr(M)))
+
+
+def nncp_gram(ctx, mode, G):
+    return _check(lib().nncp_gram(ctx, int(mode), _ptr(G)))
+
+
+def nncp_hadamard(ctx, mode, S):
+    return _check(lib().nncp_hadamard(ctx, int(mode), _ptr(S)))
+
+
+def nncp_update_mu(ctx, mode, M, S, eps=-1.0):
+    return _check(lib().nncp_update_mu(ctx, int(mode), _ptr(M), _ptr(S), float(eps)))
+
+
+def nncp_update_hals(ctx, mode, M, S):
+    return _check(lib().nncp_update_hals(ctx, int(mode), _ptr(M), _ptr(S)))
+
+
+def nncp_cp_loss(ctx, loss=None, relerr=None):
+    return _check(lib().nncp_cp_loss(ctx, _ptr(loss), _ptr(relerr)))
+
+
+def nncp_sweep(ctx, algo, nsweeps, relerr_hist=None):
+    return _check(lib().nncp_sweep(ctx, int(algo), int(nsweeps), _ptr(relerr_hist)))
+
+
+def nncp_grad(ctx, grads, loss=None):
+    return _check(lib().nncp_grad(ctx, _ptr_array(grads), _ptr(loss)))
+
+
+def nncp_pgd(ctx, nsteps, armijo_c=1e-4, max_halvings=30, power_iters=50):
+    lh = (ctypes.c_double * max(1, nsteps))()
+    eh = (ctypes.c_double * max(1, nsteps))()
+    _check(lib().nncp_pgd(ctx, int(nsteps), float(armijo_c), int(max_halvings), int(power_iters),
+                          lh, eh))
+    return list(lh)[:nsteps], list(eh)[:nsteps]
+
+
+def nncp_destroy(ctx):
+    return _check(lib().nncp_destroy(ctx))
+
+
+def nncp_split(ctx) -> int:
+    return _check(lib().nncp_split(ctx))
+
+
+def nncp_gemm_path(ctx, side) -> int:
+    return _check(lib().nncp_gemm_path(ctx, int(side)))
+
+
+def nncp_timers_enable(ctx, on: bool):
+    return _check(lib().nncp_timers_enable(ctx, 1 if on else 0))
+
+
+def nncp_timers_read(ctx):
+    """(milliseconds, launches) per timing category (see include/nncp.h)."""
+    ms = (ctypes.c_double * NNCP_TIMER_CATEGORIES)()
+    n = (ctypes.c_int64 * NNCP_TIMER_CATEGORIES)()
+    _check(lib().nncp_timers_read(ctx, ms, n))
+    return list(ms), list(n)
+
+
+# ---------------------------------------------------------------------------
+# convenience: a context that owns references to its torch buffers
+# ---------------------------------------------------------------------------
+
+class Context:
+    """Holds X, the factors, lambda and the workspace (torch tensors on one
+    GPU) for an nncp context.  Factors are updated in place."""
+
+    def __init__(self, X, factors, lam=None, *, split=0, krp_split=1, generic=0, eps_mu=1e-16):
+        if not X.is_cuda:
+            raise ValueError("X must be a GPU tensor")
+        self.dims = [int(f.shape[0]) for f in factors]
+        self.R = int(factors[0].shape[1])
+        self.X = X.contiguous()
+        self.factors = [f.contiguous() for f in factors]
+        dev = X.device
+        self.lam = (lam.to(device=dev, dtype=torch.float64).contiguous() if lam is not None
+                    else torch.ones(self.R, dtype=torch.float64, device=dev))
+        self.opts = dict(split=split, krp_split=krp_split, generic=generic, eps_mu=eps_mu)
+        nbytes = nncp_workspace_size(self.dims, self.R, _DT[X.dtype], _DT[self.factors[0].dtype],
+                                     **self.opts)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.ctx = nncp_init(self.dims, self.R, self.X, self.factors, self.lam, self.workspace,
+                             **self.opts)
+
+    @property
+    def N(self):
+        return len(self.dims)
+
+    @property
+    def hdtype(self):
+        return self.factors[0].dtype
+
+    def split(self) -> int:
+        return nncp_split(self.ctx)
+
+    def gemm_path(self, side: int) -> int:
+        return nncp_gemm_path(self.ctx, side)
+
+    def set_factors(self, factors, lam=None):
+        self.factors = [f.contiguous() for f in factors]
+        if lam is not None:
+            self.lam = lam.contiguous()
+        nncp_set_factors(self.ctx, self.factors, self.lam if lam is not None else None)
+
+    def mttkrp(self, mode: int, out=None):
+        M = out if out is not None else torch.empty(self.dims[mode], self.R, dtype=self.hdtype,
+                                                    device=self.X.device)
+        nncp_mttkrp(self.ctx, mode, M)
+        return M
+
+    def gram(self, mode: int):
+        G = torch.empty(self.R, self.R, dtype=torch.float64, device=self.X.device)
+        nncp_gram(self.ctx, mode, G)
+        return G
+
+    def hadamard(self, mode: int):
+        S = torch.empty(self.R, self.R, dtype=torch.float64, device=self.X.device)
+        nncp_hadamard(self.ctx, mode, S)
+        return S
+
+    def update(self, algo: int, mode: int, M, S, eps: float = -1.0):
+        if algo == NNCP_MU:
+            nncp_update_mu(self.ctx, mode, M, S, eps)
+        else:
+            nncp_update_hals(self.ctx, mode, M, S)
+
+    def cp_loss(self):
+        out = torch.empty(2, dtype=torch.float64, device=self.X.device)
+        nncp_cp_loss(self.ctx, out[0:1], out[1:2])
+        return out
+
+    def sweep(self, algo: int, nsweeps: int, relerr_hist=None):
+        if relerr_hist is None:
+            relerr_hist = torch.empty(max(1, nsweeps), dtype=torch.float64, device=self.X.device)
+        nncp_sweep(self.ctx, algo, nsweeps, relerr_hist)
+        return relerr_hist
+
+    def grad(self, grads=None, loss=None):
+        if grads is None:
+            grads = [torch.empty_like(f) for f in self.factors]
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=self.X.device)
+        nncp_grad(self.ctx, grads, loss)
+        return grads, loss
+
+    def pgd(self, nsteps: int, armijo_c=1e-4, max_halvings=30, power_iters=50):
+        return nncp_pgd(self.ctx, nsteps, armijo_c, max_halvings, power_iters)
+
+    def timers_enable(self, on: bool = True):
+        nncp_timers_enable(self.ctx, on)
+
+    def timers_read(self):
+        return nncp_timers_read(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            nncp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CPLoss(torch.autograd.Function):
+    """L = 0.5 ||X - [[H^(0), ..., H^(N-1)]]||^2 (lambda = 1) with the
+    hand-written adjoint dL/dH^(n) = H^(n) S^(n) - M^(n) computed by the
+    library (all N MTTKRPs at the same point, two passes over X).
+
+    Usage: ``CPLoss.apply(ctx, *factors)`` with ctx a ``Context`` over X."""
+
+    @staticmethod
+    def forward(fctx, ctx: Context, *factors):
+        ctx.set_factors([f.detach() for f in factors])
+        grads = [torch.empty_like(f) for f in factors]
+        loss = torch.empty(1, dtype=torch.float64, device=factors[0].device)
+        nncp_grad(ctx.ctx, grads, loss)
+        fctx.save_for_backward(*grads)
+        return loss.reshape(()).to(factors[0].dtype)
+
+    @staticmethod
+    def backward(fctx, g):
+        grads = fctx.saved_tensors
+        return (None, *[g.to(t.dtype) * t for t in grads])

@@ -1,0 +1,747 @@
+// Host side of the NNCP library: the C ABI declared in include/nncp.h, the
+// planner (root split, Khatri-Rao factoring, grids), the workspace carve-up,
+// the dimension-tree walk of Algorithm 3, the sweep of Algorithm 1 and the
+// projected-gradient driver.  All device work is launched on the context's
+// stream; nothing here allocates device memory.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nncp_internal.h"
+
+using namespace nncp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+const int kMagic = 0x4E4E4350;  // "NNCP"
+const size_t kAlign = 256;
+const size_t kLdsMax = 64 * 1024;
+
+size_t xsize(int dt) { return dt == NNCP_F64 ? 8 : dt == NNCP_F32 ? 4 : 2; }
+
+int64_t prod(const int64_t *d, int lo, int hi) {
+  int64_t p = 1;
+  for (int k = lo; k < hi; ++k) p *= d[k];
+  return p;
+}
+
+struct Layout {
+  int N, R, S, xdt, hdt;
+  int64_t dims[NNCP_MAX_MODES];
+  nncp_options opt;
+  GemmPlan gp[2];
+  int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
+  // byte offsets into the workspace
+  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_red, off_M, off_A, off_B,
+      off_part, off_kf, off_ks, off_pgdH, off_pgdG, total;
+};
+
+nncp_options default_options() {
+  nncp_options o;
+  o.split = 0;
+  o.krp_split = 1;
+  o.generic = 0;
+  o.eps_mu = 1e-16;
+  return o;
+}
+
+int check_dtypes(int xdt, int hdt) {
+  if (xdt == NNCP_F64 && hdt == NNCP_F64) return NNCP_OK;
+  if ((xdt == NNCP_F32 || xdt == NNCP_BF16 || xdt == NNCP_F16) && hdt == NNCP_F32) return NNCP_OK;
+  return fail(NNCP_E_DTYPE, "unsupported (x_dtype, h_dtype) = (%d, %d)", xdt, hdt);
+}
+
+// LDS bytes of the staged Khatri-Rao operand: rows of Pf elements, XOR-swizzled
+// when a row has a multiple of 16 16-byte chunks, else padded by one chunk.
+size_t stage_bytes(int Rpad, int64_t Pf, int es, int hl) {
+  const int64_t sv = 16 / es;
+  const int64_t ldk = ((Pf / sv) % 16 == 0) ? Pf : Pf + sv;
+  return (size_t)Rpad * (size_t)ldk * es * (hl ? 2 : 1);
+}
+
+// Plan one partial MTTKRP.
+void plan_side(Layout &L, int side) {
+  GemmPlan &p = L.gp[side];
+  memset(&p, 0, sizeof p);
+  const int N = L.N, S = L.S, R = L.R;
+  p.side = side;
+  p.m = prod(L.dims, 0, S);
+  p.k = prod(L.dims, S, N);
+  const int lo = side == 0 ? S : 0, hi = side == 0 ? N : S;
+  const int64_t red = prod(L.dims, lo, hi);
+  p.Rpad = (R + 15) / 16 * 16;
+  p.NT = p.Rpad / 16;
+  const bool is16 = L.xdt == NNCP_BF16 || L.xdt == NNCP_F16;
+  p.hl = is16 && L.opt.krp_split ? 1 : 0;
+  const int es = (int)xsize(L.xdt);
+  const int hs = (int)xsize(L.hdt);
+  const int VEC = 16 / es;
+  const int KL = is16 ? 8 : 1;
+  const int KSTEP = side == 0 ? 4 * KL : 4 * VEC;
+  const int MT = L.xdt == NNCP_F64 ? 1 : 2;
+  const int QV = is16 ? (p.NT <= 2 ? 8 : 4) : VEC;
+
+  bool mfma = !L.opt.generic && R <= 64;
+  if (side == 0 && p.m % QV != 0) mfma = false;
+  int64_t Pf = -1;
+  int fhi = -1;
+  if (mfma) {
+    int64_t best = -1;
+    int besthi = -1;
+    for (int c = lo + 1; c <= hi; ++c) {
+      const int64_t pf = prod(L.dims, lo, c);
+      if (pf % KSTEP != 0) continue;
+      const size_t need = stage_bytes(p.Rpad, pf, es, p.hl);
+      if (need > kLdsMax) break;
+      best = pf;
+      besthi = c;
+      if (pf >= 64) break;
+    }
+    if (best < 0) mfma = false;
+    Pf = best;
+    fhi = besthi;
+  }
+  p.mfma = mfma ? 1 : 0;
+  if (mfma) {
+    p.Pf = Pf;
+    p.Ps = red / Pf;
+    p.fast_lo = lo; p.fast_hi = fhi; p.slow_lo = fhi; p.slow_hi = hi;
+    const size_t stage = stage_bytes(p.Rpad, Pf, es, p.hl);
+    if (side == 1) {
+      const size_t redb = (size_t)3 * MT * p.NT * 4 * 64 * hs;
+      p.lds_bytes = std::max(stage, redb);
+      p.tiles = (p.k + 16 * MT - 1) / (16 * MT);
+      const int64_t steps = p.m / KSTEP;
+      int64_t ns = (2048 + p.tiles - 1) / p.tiles;
+      ns = std::min<int64_t>(ns, std::max<int64_t>(1, steps / 8));
+      ns = std::min<int64_t>(ns, 4096);
+      p.nsplit = (int)std::max<int64_t>(ns, 1);
+    } else {
+      p.lds_bytes = stage;
+      p.tiles = (p.m + 64 * QV - 1) / (64 * QV);
+      const int64_t steps = p.k / KSTEP;
+      int64_t ns = (1024 + p.tiles - 1) / p.tiles;
+      ns = std::min<int64_t>(ns, std::max<int64_t>(1, steps / 4));
+      ns = std::min<int64_t>(ns, 4096);
+      p.nsplit = (int)std::max<int64_t>(ns, 1);
+    }
+  } else {
+    p.Pf = red; p.Ps = 1;
+    p.fast_lo = lo; p.fast_hi = hi; p.slow_lo = hi; p.slow_hi = hi;
+    p.lds_bytes = 0;
+    if (side == 1) {
+      p.tiles = p.k;
+      int64_t ns = (1024 + p.k - 1) / p.k;
+      ns = std::min<int64_t>(ns, std::max<int64_t>(1, p.m / 256));
+      p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+    } else {
+      p.tiles = (p.m + 255) / 256;
+      int64_t ns = (1024 + p.tiles - 1) / p.tiles;
+      ns = std::min<int64_t>(ns, p.k);
+      p.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+    }
+  }
+}
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
+                const nncp_options *opt) {
+  if (N < 2 || N > NNCP_MAX_MODES) return fail(NNCP_E_INVAL, "N = %d outside [2, %d]", N, NNCP_MAX_MODES);
+  if (!dims) return fail(NNCP_E_INVAL, "dims is NULL");
+  if (R < 1) return fail(NNCP_E_INVAL, "R = %d < 1", R);
+  if (R > 256) return fail(NNCP_E_UNSUPPORTED, "R = %d > 256", R);
+  int rc = check_dtypes(xdt, hdt);
+  if (rc) return rc;
+  L.N = N; L.R = R; L.xdt = xdt; L.hdt = hdt;
+  L.opt = opt ? *opt : default_options();
+  if (!(L.opt.eps_mu >= 0.0)) return fail(NNCP_E_INVAL, "eps_mu must be >= 0");
+  int64_t total = 1;
+  for (int k = 0; k < N; ++k) {
+    if (dims[k] < 1) return fail(NNCP_E_INVAL, "dims[%d] = %lld < 1", k, (long long)dims[k]);
+    if (dims[k] > ((int64_t)1 << 31)) return fail(NNCP_E_UNSUPPORTED, "dims[%d] too large", k);
+    L.dims[k] = dims[k];
+    if (total > (((int64_t)1 << 40) / dims[k])) return fail(NNCP_E_UNSUPPORTED, "tensor has more than 2^40 entries");
+    total *= dims[k];
+  }
+  if (L.opt.split) {
+    if (L.opt.split < 1 || L.opt.split > N - 1) return fail(NNCP_E_INVAL, "split = %d outside [1, N-1]", L.opt.split);
+    L.S = L.opt.split;
+  } else {
+    // smallest S with prod(0..S-1) >= prod(S..N-1), clamped to [1, N-1]
+    L.S = N - 1;
+    for (int s = 1; s <= N - 1; ++s)
+      if (prod(L.dims, 0, s) >= prod(L.dims, s, N)) { L.S = s; break; }
+  }
+  plan_side(L, 0);
+  plan_side(L, 1);
+  const int S = L.S;
+  L.maxI = 0;
+  L.sumI = 0;
+  for (int k = 0; k < N; ++k) { L.maxI = std::max(L.maxI, L.dims[k]); L.sumI += L.dims[k]; }
+  const int64_t m = prod(L.dims, 0, S), kk = prod(L.dims, S, N);
+  L.nodeA = std::max(m, kk) * R;
+  L.nodeB = std::max(S > 1 ? prod(L.dims, 1, S) : 1, N - S > 1 ? prod(L.dims, S + 1, N) : 1) * R;
+  // partial buffers: GEMM splits and strided multi-TTV splits
+  int64_t part = 0;
+  for (int side = 0; side < 2; ++side) {
+    const GemmPlan &p = L.gp[side];
+    const int64_t rows = side == 1 ? p.k : p.m;
+    part = std::max(part, (int64_t)p.nsplit * rows * R);
+  }
+  for (int side = 0; side < 2; ++side) {
+    const int lo = side == 0 ? 0 : S, hi = side == 0 ? S : N;
+    for (int a = lo; a < hi - 1; ++a)
+      part = std::max(part, mttv_strided_part_elems(L.dims[a], L.dims + a + 1, hi - a - 1, R));
+  }
+  L.part_elems = part;
+  L.kfast_elems = 0;
+  L.kslow_elems = 0;
+  for (int side = 0; side < 2; ++side) {
+    const GemmPlan &p = L.gp[side];
+    if (!p.mfma) continue;
+    L.kfast_elems = std::max(L.kfast_elems, (int64_t)(p.hl ? 2 : 1) * p.Rpad * p.Pf);
+    L.kslow_elems = std::max(L.kslow_elems, (int64_t)p.Ps * p.Rpad);
+  }
+  const size_t hs = xsize(hdt), es = xsize(xdt);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  L.off_G = take(sizeof(double) * N * R * R);
+  L.off_Gt = take(sizeof(double) * N * R * R);
+  L.off_S = take(sizeof(double) * R * R);
+  L.off_scal = take(sizeof(double) * 64);
+  L.off_ones = take(sizeof(double) * R);
+  L.off_hhat = take(sizeof(double) * L.maxI * R);
+  L.off_red = take(sizeof(double) * 1024);
+  L.off_M = take(hs * L.maxI * R);
+  L.off_A = take(hs * L.nodeA);
+  L.off_B = take(hs * L.nodeB);
+  L.off_part = take(hs * L.part_elems);
+  L.off_kf = take(es * L.kfast_elems);
+  L.off_ks = take(hs * L.kslow_elems);
+  L.off_pgdH = take(hs * L.sumI * R);
+  L.off_pgdG = take(hs * L.sumI * R);
+  L.total = o;
+  return NNCP_OK;
+}
+
+}  // namespace
+
+// Event pairs of one timing category; events are created on first use and
+// reused after each read.
+struct TimerCat {
+  std::vector<hipEvent_t> ev;  // start, stop, start, stop, ...
+  size_t used = 0;
+  double ms = 0.0;
+  int64_t n = 0;
+};
+
+struct nncp_ctx {
+  int magic;
+  Layout L;
+  int timing = 0;
+  TimerCat timers[NNCP_TIMER_CATEGORIES];
+  const void *X;
+  void *H[NNCP_MAX_MODES];
+  double *lambda;
+  hipStream_t st;
+  char *ws;
+  double *G, *Gt, *S, *scal, *ones, *hhat, *red;
+  void *M, *nodeA, *nodeB, *part, *kf, *ks;
+  void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
+};
+
+namespace {
+
+int check_ctx(const nncp_ctx *c) {
+  if (!c || c->magic != kMagic) return fail(NNCP_E_STATE, "context is NULL or destroyed");
+  return NNCP_OK;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(NNCP_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Record a start event for category k (no-op unless timing is enabled).
+hipError_t tstart(nncp_ctx *c, int k) {
+  if (!c->timing) return hipSuccess;
+  TimerCat &t = c->timers[k];
+  if (t.used + 2 > t.ev.size()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    t.ev.push_back(a);
+    t.ev.push_back(b);
+  }
+  return hipEventRecord(t.ev[t.used], c->st);
+}
+
+hipError_t tstop(nncp_ctx *c, int k) {
+  if (!c->timing) return hipSuccess;
+  TimerCat &t = c->timers[k];
+  hipError_t e = hipEventRecord(t.ev[t.used + 1], c->st);
+  t.used += 2;
+  t.n += 1;
+  return e;
+}
+
+// fold recorded pairs into the totals (the stream must be synchronised)
+hipError_t tcollect(nncp_ctx *c) {
+  for (int k = 0; k < NNCP_TIMER_CATEGORIES; ++k) {
+    TimerCat &t = c->timers[k];
+    for (size_t i = 0; i + 1 < t.used; i += 2) {
+      float ms = 0.f;
+      hipError_t e = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]);
+      if (e != hipSuccess) return e;
+      t.ms += ms;
+    }
+    t.used = 0;
+  }
+  return hipSuccess;
+}
+
+#define TIMED(k, expr)                 \
+  do {                                 \
+    HIPCHK(tstart(c, (k)));            \
+    HIPCHK(expr);                      \
+    HIPCHK(tstop(c, (k)));             \
+  } while (0)
+
+FactorSet factors_of(const nncp_ctx *c, void *const *H) {
+  FactorSet F;
+  for (int n = 0; n < NNCP_MAX_MODES; ++n) F.H[n] = n < c->L.N ? H[n] : nullptr;
+  return F;
+}
+
+void *node_buf(nncp_ctx *c, int side, int a) {
+  const int lo = side == 0 ? 0 : c->L.S;
+  return ((a - lo) % 2 == 0) ? c->nodeA : c->nodeB;
+}
+
+// Root partial MTTKRP of one side into node[lo] (or into Mout if the subtree
+// has a single mode).
+int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout) {
+  const Layout &L = c->L;
+  const GemmPlan &p = L.gp[side];
+  const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
+  const bool leaf = hi - lo == 1;
+  if (p.mfma) TIMED(2, launch_krp_operands(L.xdt, p, L.R, L.dims, L.N, F, c->kf, c->ks, c->st));
+  void *node = leaf ? Mout : node_buf(c, side, lo);
+  const bool direct = p.nsplit == 1 && ((side == 0 && !leaf) || (side == 1 && leaf));
+  TIMED(side, launch_partial_mttkrp(L.xdt, p, L.R, c->X, L.dims, L.N, L.S, F, c->kf, c->ks,
+                                    direct ? node : c->part, c->st));
+  if (!direct) TIMED(3, launch_finalize(L.hdt, p, L.R, c->part, node, leaf ? 1 : 0, c->st));
+  return NNCP_OK;
+}
+
+// M^(n) through the dimension tree.  When from_root is false the node of
+// mode n-1 (same subtree) must hold the values left by the previous call and
+// H^(n-1) may have changed since (Gauss-Seidel order of Algorithm 1).
+int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_root) {
+  const Layout &L = c->L;
+  const int side = n < L.S ? 0 : 1;
+  const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
+  const int R = L.R;
+  int start;
+  if (from_root || n == lo) {
+    int rc = root_gemm(c, F, side, Mout);
+    if (rc) return rc;
+    if (hi - lo == 1) return NNCP_OK;
+    start = lo + 1;
+  } else {
+    start = n;
+  }
+  for (int a = start; a <= n; ++a) {
+    // node a = contiguous multi-TTV of node a-1 with H^(a-1)
+    const int64_t Ia = L.dims[a - 1];
+    const int64_t Q = prod(L.dims, a, hi);
+    const bool leaf = a == hi - 1;
+    void *out = leaf ? Mout : node_buf(c, side, a);
+    TIMED(3, launch_mttv_contig(L.hdt, node_buf(c, side, a - 1), Ia, Q, R, F.H[a - 1], out,
+                                leaf ? 1 : 0, c->st));
+  }
+  if (n < hi - 1) {
+    const void *Hq[NNCP_MAX_MODES];
+    for (int k = n + 1; k < hi; ++k) Hq[k - n - 1] = F.H[k];
+    TIMED(3, launch_mttv_strided(L.hdt, node_buf(c, side, n), L.dims[n], L.dims + n + 1,
+                                 hi - n - 1, Hq, R, Mout, c->part, L.part_elems, c->st));
+  }
+  return NNCP_OK;
+}
+
+int refresh_grams(nncp_ctx *c, const FactorSet &F, double *G) {
+  for (int n = 0; n < c->L.N; ++n)
+    HIPCHK(launch_gram(c->L.hdt, F.H[n], c->L.dims[n], c->L.R, G + (int64_t)n * c->L.R * c->L.R, c->st));
+  return NNCP_OK;
+}
+
+int update_mode(nncp_ctx *c, int algo, int n, const void *M, const double *S, double eps,
+                double *relerr_out, double *scal) {
+  const Layout &L = c->L;
+  UpdateArgs a;
+  a.algo = algo;
+  a.I = L.dims[n];
+  a.R = L.R;
+  a.N = L.N;
+  a.mode = n;
+  a.M = M;
+  a.S = S;
+  if (!S && L.R > 64) {
+    HIPCHK(launch_hadamard(c->G, L.N, L.R, n, c->S, c->st));
+    a.S = c->S;
+  }
+  a.G = c->G;
+  a.H = c->H[n];
+  a.lambda = c->lambda;
+  a.hhat = c->hhat;
+  a.eps = eps;
+  a.alpha = c->scal + 8;
+  a.relerr_out = relerr_out;
+  a.scal = scal;
+  TIMED(4, launch_update(L.hdt, a, c->st));
+  return NNCP_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *nncp_last_error(void) { return g_err.c_str(); }
+
+size_t nncp_workspace_size(int N, const int64_t *dims, int R, int x_dtype, int h_dtype,
+                           const nncp_options *opt) {
+  Layout L;
+  if (make_layout(L, N, dims, R, x_dtype, h_dtype, opt) != NNCP_OK) return 0;
+  return L.total;
+}
+
+int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, const void *X,
+              int h_dtype, void *const *H, double *lambda, void *workspace, size_t ws_bytes,
+              void *stream, const nncp_options *opt) {
+  if (!out) return fail(NNCP_E_INVAL, "ctx out-pointer is NULL");
+  *out = nullptr;
+  Layout L;
+  int rc = make_layout(L, N, dims, R, x_dtype, h_dtype, opt);
+  if (rc) return rc;
+  if (!X || !H || !lambda || !workspace) return fail(NNCP_E_INVAL, "NULL X, H, lambda or workspace");
+  if (!aligned16(X) || !aligned16(workspace) || !aligned16(lambda))
+    return fail(NNCP_E_INVAL, "X, lambda and workspace must be 16-byte aligned");
+  for (int n = 0; n < N; ++n) {
+    if (!H[n]) return fail(NNCP_E_INVAL, "H[%d] is NULL", n);
+    if (!aligned16(H[n])) return fail(NNCP_E_INVAL, "H[%d] must be 16-byte aligned", n);
+  }
+  if (ws_bytes < L.total)
+    return fail(NNCP_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+  nncp_ctx *c = new (std::nothrow) nncp_ctx();
+  if (!c) return fail(NNCP_E_INVAL, "out of host memory");
+  c->magic = kMagic;
+  c->L = L;
+  c->X = X;
+  for (int n = 0; n < NNCP_MAX_MODES; ++n) c->H[n] = n < N ? H[n] : nullptr;
+  c->lambda = lambda;
+  c->st = (hipStream_t)stream;
+  c->ws = (char *)workspace;
+  c->G = (double *)(c->ws + L.off_G);
+  c->Gt = (double *)(c->ws + L.off_Gt);
+  c->S = (double *)(c->ws + L.off_S);
+  c->scal = (double *)(c->ws + L.off_scal);
+  c->ones = (double *)(c->ws + L.off_ones);
+  c->hhat = (double *)(c->ws + L.off_hhat);
+  c->red = (double *)(c->ws + L.off_red);
+  c->M = c->ws + L.off_M;
+  c->nodeA = c->ws + L.off_A;
+  c->nodeB = c->ws + L.off_B;
+  c->part = c->ws + L.off_part;
+  c->kf = c->ws + L.off_kf;
+  c->ks = c->ws + L.off_ks;
+  {
+    const size_t hs = xsize(h_dtype);
+    size_t oh = L.off_pgdH, og = L.off_pgdG;
+    for (int n = 0; n < N; ++n) {
+      c->pgdH[n] = c->ws + oh;
+      c->pgdG[n] = c->ws + og;
+      oh += hs * L.dims[n] * R;
+      og += hs * L.dims[n] * R;
+    }
+  }
+  // ones (for lambda-free losses), Grams, alpha
+  {
+    double onesh[256];
+    for (int r = 0; r < R; ++r) onesh[r] = 1.0;
+    hipError_t e = hipMemcpyAsync(c->ones, onesh, sizeof(double) * R, hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(NNCP_E_HIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    }
+  }
+  FactorSet F = factors_of(c, c->H);
+  rc = refresh_grams(c, F, c->G);
+  if (!rc) {
+    hipError_t e = launch_sumsq(x_dtype, X, prod(L.dims, 0, N), c->red, c->scal + 8, c->st);
+    if (e != hipSuccess) rc = fail(NNCP_E_HIP, "sumsq: %s", hipGetErrorString(e));
+  }
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return NNCP_OK;
+}
+
+int nncp_set_factors(nncp_ctx *c, void *const *H, double *lambda) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!H) return fail(NNCP_E_INVAL, "H is NULL");
+  for (int n = 0; n < c->L.N; ++n)
+    if (!H[n] || !aligned16(H[n])) return fail(NNCP_E_INVAL, "H[%d] is NULL or misaligned", n);
+  if (lambda && !aligned16(lambda)) return fail(NNCP_E_INVAL, "lambda misaligned");
+  for (int n = 0; n < c->L.N; ++n) c->H[n] = H[n];
+  if (lambda) c->lambda = lambda;
+  return refresh_grams(c, factors_of(c, c->H), c->G);
+}
+
+int nncp_split(const nncp_ctx *c) {
+  if (check_ctx(c)) return NNCP_E_STATE;
+  return c->L.S;
+}
+
+int nncp_gemm_path(const nncp_ctx *c, int side) {
+  if (check_ctx(c)) return NNCP_E_STATE;
+  if (side < 0 || side > 1) return fail(NNCP_E_INVAL, "side must be 0 or 1");
+  return c->L.gp[side].mfma;
+}
+
+int nncp_mttkrp(nncp_ctx *c, int mode, void *M) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
+  if (!M) return fail(NNCP_E_INVAL, "M is NULL");
+  return mttkrp_tree(c, factors_of(c, c->H), mode, M, true);
+}
+
+int nncp_gram(nncp_ctx *c, int mode, double *G) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
+  const int R = c->L.R;
+  double *Gm = c->G + (int64_t)mode * R * R;
+  HIPCHK(launch_gram(c->L.hdt, c->H[mode], c->L.dims[mode], R, Gm, c->st));
+  if (G && G != Gm)
+    HIPCHK(hipMemcpyAsync(G, Gm, sizeof(double) * R * R, hipMemcpyDeviceToDevice, c->st));
+  return NNCP_OK;
+}
+
+int nncp_hadamard(nncp_ctx *c, int mode, double *S) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
+  if (!S) return fail(NNCP_E_INVAL, "S is NULL");
+  HIPCHK(launch_hadamard(c->G, c->L.N, c->L.R, mode, S, c->st));
+  return NNCP_OK;
+}
+
+static int update_api(nncp_ctx *c, int algo, int mode, const void *M, const double *S, double eps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
+  if (!M || !S) return fail(NNCP_E_INVAL, "M or S is NULL");
+  return update_mode(c, algo, mode, M, S, eps, nullptr, nullptr);
+}
+
+int nncp_update_mu(nncp_ctx *c, int mode, const void *M, const double *S, double eps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  return update_api(c, NNCP_MU, mode, M, S, eps < 0 ? c->L.opt.eps_mu : eps);
+}
+
+int nncp_update_hals(nncp_ctx *c, int mode, const void *M, const double *S) {
+  return update_api(c, NNCP_HALS, mode, M, S, 0.0);
+}
+
+int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const Layout &L = c->L;
+  const int n = L.N - 1;
+  rc = mttkrp_tree(c, factors_of(c, c->H), n, c->M, true);
+  if (rc) return rc;
+  HIPCHK(launch_loss(L.hdt, L.N, L.R, L.dims[n], c->M, c->H[n], c->lambda, c->G, c->scal + 8, loss,
+                     relerr, c->scal + 4, c->st));
+  return NNCP_OK;
+}
+
+int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (algo != NNCP_MU && algo != NNCP_HALS) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
+  const Layout &L = c->L;
+  const FactorSet F = factors_of(c, c->H);
+  for (int s = 0; s < nsweeps; ++s) {
+    for (int n = 0; n < L.N; ++n) {
+      rc = mttkrp_tree(c, F, n, c->M, false);
+      if (rc) return rc;
+      const bool last = n == L.N - 1;
+      rc = update_mode(c, algo, n, c->M, nullptr, L.opt.eps_mu,
+                       last && relerr_hist ? relerr_hist + s : nullptr, last ? c->scal : nullptr);
+      if (rc) return rc;
+    }
+  }
+  return NNCP_OK;
+}
+
+static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const *grads,
+                   double *loss) {
+  const Layout &L = c->L;
+  for (int n = 0; n < L.N; ++n) {
+    int rc = mttkrp_tree(c, F, n, c->M, false);
+    if (rc) return rc;
+    if (grads) {
+      const double *S = nullptr;
+      if (L.R > 64) {
+        HIPCHK(launch_hadamard(G, L.N, L.R, n, c->S, c->st));
+        S = c->S;
+      }
+      HIPCHK(launch_grad(L.hdt, L.dims[n], L.R, L.N, n, c->M, F.H[n], G, S, grads[n], c->st));
+    }
+  }
+  const int n = L.N - 1;
+  HIPCHK(launch_loss(L.hdt, L.N, L.R, L.dims[n], c->M, F.H[n], c->ones, G, c->scal + 8, loss,
+                     nullptr, c->scal + 4, c->st));
+  return NNCP_OK;
+}
+
+int nncp_grad(nncp_ctx *c, void *const *grads, double *loss) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!grads) return fail(NNCP_E_INVAL, "grads is NULL");
+  for (int n = 0; n < c->L.N; ++n)
+    if (!grads[n]) return fail(NNCP_E_INVAL, "grads[%d] is NULL", n);
+  return grad_at(c, factors_of(c, c->H), c->G, grads, loss);
+}
+
+int nncp_pgd(nncp_ctx *c, int nsteps, double armijo_c, int max_halvings, int power_iters,
+             double *loss_hist, double *eta_hist) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (nsteps < 0 || max_halvings < 0 || power_iters < 0 || !(armijo_c >= 0.0))
+    return fail(NNCP_E_INVAL, "bad PGD parameters");
+  if (c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "nncp_pgd supports R <= 64");
+  const Layout &L = c->L;
+  const int N = L.N, R = L.R;
+  const FactorSet F = factors_of(c, c->H);
+  const FactorSet Ft = factors_of(c, c->pgdH);
+  double *dL = c->scal + 16;    // loss at H
+  double *dLt = c->scal + 17;   // loss at the trial
+  double *deta = c->scal + 18;  // eta0
+  double *dd = c->scal + 24;    // per-mode ||H' - H||^2
+  for (int t = 0; t < nsteps; ++t) {
+    rc = grad_at(c, F, c->G, c->pgdG, dL);
+    if (rc) return rc;
+    HIPCHK(launch_pgd_eta(c->G, N, R, power_iters, deta, c->st));
+    double host[2];
+    HIPCHK(hipMemcpyAsync(&host[0], dL, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(&host[1], deta, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const double Lcur = host[0];
+    double eta = host[1], accepted = 0.0, Lnew = Lcur;
+    for (int h = 0; h <= max_halvings; ++h) {
+      for (int n = 0; n < N; ++n)
+        HIPCHK(launch_pgd_trial(L.hdt, L.dims[n] * R, c->H[n], c->pgdG[n], eta, c->pgdH[n], c->red,
+                                dd + n, c->st));
+      rc = refresh_grams(c, Ft, c->Gt);
+      if (rc) return rc;
+      rc = mttkrp_tree(c, Ft, N - 1, c->M, true);
+      if (rc) return rc;
+      HIPCHK(launch_loss(L.hdt, N, R, L.dims[N - 1], c->M, c->pgdH[N - 1], c->ones, c->Gt,
+                         c->scal + 8, dLt, nullptr, nullptr, c->st));
+      double hb[NNCP_MAX_MODES + 1];
+      HIPCHK(hipMemcpyAsync(hb, dd, sizeof(double) * N, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(hb + N, dLt, sizeof(double), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      double d = 0.0;
+      for (int n = 0; n < N; ++n) d += hb[n];
+      const double Lt = hb[N];
+      if (Lt <= Lcur - armijo_c * d / eta) {
+        accepted = eta;
+        Lnew = Lt;
+        const size_t hs = xsize(L.hdt);
+        for (int n = 0; n < N; ++n)
+          HIPCHK(hipMemcpyAsync(c->H[n], c->pgdH[n], hs * L.dims[n] * R, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(c->G, c->Gt, sizeof(double) * N * R * R, hipMemcpyDeviceToDevice, c->st));
+        break;
+      }
+      eta *= 0.5;
+    }
+    if (loss_hist) loss_hist[t] = Lnew;
+    if (eta_hist) eta_hist[t] = accepted;
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  return NNCP_OK;
+}
+
+int nncp_timers_enable(nncp_ctx *c, int on) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int k = 0; k < NNCP_TIMER_CATEGORIES; ++k) {
+    c->timers[k].used = 0;
+    c->timers[k].ms = 0.0;
+    c->timers[k].n = 0;
+  }
+  c->timing = on ? 1 : 0;
+  return NNCP_OK;
+}
+
+int nncp_timers_read(nncp_ctx *c, double *ms, int64_t *launches) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!ms || !launches) return fail(NNCP_E_INVAL, "NULL output array");
+  HIPCHK(hipStreamSynchronize(c->st));
+  HIPCHK(tcollect(c));
+  for (int k = 0; k < NNCP_TIMER_CATEGORIES; ++k) {
+    ms[k] = c->timers[k].ms;
+    launches[k] = c->timers[k].n;
+  }
+  return NNCP_OK;
+}
+
+int nncp_destroy(nncp_ctx *c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  for (int k = 0; k < NNCP_TIMER_CATEGORIES; ++k)
+    for (hipEvent_t e : c->timers[k].ev) (void)hipEventDestroy(e);
+  c->magic = 0;
+  delete c;
+  return NNCP_OK;
+}
+
+}  // extern "C"

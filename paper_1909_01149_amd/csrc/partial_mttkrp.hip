@@ -1,0 +1,744 @@
+// Partial MTTKRP: the two GEMMs at the root of the dimension tree
+// (Section 3.2.2, Algorithm 3, partial-MTTKRP lines), plus the partial
+// Khatri-Rao operand (Algorithm 3, partial-KRP lines) and the deterministic
+// split-reduction finalize.
+//
+// The tensor is read as a k x m row-major matrix Xr whose rows are the
+// contiguous mode-0..S-1 fibres (m = I_0 ... I_{S-1}, k = I_S ... I_{N-1}).
+//   left  (mode 0's subtree):  T^{0:S-1}(i, r)   = sum_j Xr[j, i] K^{S:N-1}(j, r)
+//   right (mode S's subtree):  T^{S:N-1}(j, r)   = sum_i Xr[j, i] K^{0:S-1}(i, r)
+// Both are 2 I R flops and one streaming pass over X; R is small, so they are
+// HBM-bound streaming reductions that use the matrix cores only to keep the
+// ALU cost per byte low (BF16/FP16 at R >= 32 needs more than the vector ALU
+// can give at full HBM rate).
+//
+// Khatri-Rao operand.  K(rho, r) = prod over the reduced modes of
+// H^(n)(digit_n(rho), r).  It is never formed in HBM: it factors as
+// Kfast(rho mod Pf, r) * Kslow(rho / Pf, r) with "fast" a prefix of the
+// reduced modes.  Kfast (Pf x Rpad) is staged once per workgroup in LDS in
+// the tensor's own type, optionally as a hi + lo pair so the operand carries
+// about 16 significant bits; each fast block's MFMA result is scaled by
+// Kslow before it is added to the running sum.  For FP16 each Kfast column is
+// scaled by a power of two into FP16's range and unscaled through Kslow.
+//
+// Matrix-core operand layouts (gfx950, wave64):
+//   16x16x32 BF16/FP16: lane l holds A[l%16][8(l/16) .. +8] and
+//                       B[8(l/16) .. +8][l%16]
+//   16x16x4 FP32/FP64:  lane l holds A[l%16][l/16] and B[l/16][l%16]
+//   result (all four):  lane l holds C[4(l/16) + v][l%16], v = 0..3
+// The order of the reduction index inside a step is free as long as A and B
+// agree, which lets every lane load 16 contiguous bytes of X.
+#include "nncp_internal.h"
+
+namespace nncp {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_d<bf16_t>(bf16_t v) { return (double)(float)v; }
+template <> __device__ __forceinline__ double to_d<f16_t>(f16_t v) { return (double)(float)v; }
+
+template <typename T> __device__ __forceinline__ T from_d(double v) { return (T)v; }
+template <> __device__ __forceinline__ bf16_t from_d<bf16_t>(double v) {
+  // double -> float is exact for the products formed here up to rounding;
+  // float -> bf16 rounds to nearest even.
+  return (bf16_t)(float)v;
+}
+template <> __device__ __forceinline__ f16_t from_d<f16_t>(double v) { return (f16_t)(float)v; }
+
+template <typename AT> struct CFrag;
+template <> struct CFrag<float> { typedef f32x4 T; };
+template <> struct CFrag<double> { typedef f64x4 T; };
+
+// one matrix-core step on a 16-byte A chunk and a 16-byte B chunk
+__device__ __forceinline__ void mma16(f32x4 &c, u32x4 a, u32x4 b, bf16_t *) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                              __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ void mma16(f32x4 &c, u32x4 a, u32x4 b, f16_t *) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                             __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+// FP32: the 16 bytes are 4 consecutive reduction indices, one MFMA each
+__device__ __forceinline__ void mma16(f32x4 &c, u32x4 a, u32x4 b, float *) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+}
+__device__ __forceinline__ double dbl_lo(u32x4 v) {
+  return __builtin_bit_cast(double, ((uint64_t)v.y << 32) | v.x);
+}
+__device__ __forceinline__ double dbl_hi(u32x4 v) {
+  return __builtin_bit_cast(double, ((uint64_t)v.w << 32) | v.z);
+}
+__device__ __forceinline__ void mma16(f64x4 &c, u32x4 a, u32x4 b, double *) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(dbl_lo(a), dbl_lo(b), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(dbl_hi(a), dbl_hi(b), c, 0, 0, 0);
+}
+
+// single-element MFMA (left kernel, FP32/FP64: one reduction index per lane)
+__device__ __forceinline__ void mma1(f32x4 &c, float a, float b) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ void mma1(f64x4 &c, double a, double b) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename CT> __device__ __forceinline__ void czero(CT &c) {
+  c[0] = 0; c[1] = 0; c[2] = 0; c[3] = 0;
+}
+
+// Result row held by lane group g in accumulator slot v: 4 g + v for the
+// FP32-accumulating instructions, g + 4 v for the FP64 one.
+template <typename AT> __device__ __forceinline__ int crow(int g, int v) {
+  return sizeof(AT) == 8 ? g + 4 * v : 4 * g + v;
+}
+
+// LDS position of Kfast element (r, p).  Rows are ldk elements long; the
+// 16-byte chunks of row r are XOR-swizzled with (r & swz) so that the 16
+// lanes reading the same chunk index of 16 different rows hit 16 different
+// bank groups (swz = 15 when a row has a multiple of 16 chunks, else 0 and
+// the row is padded by one chunk instead).
+template <typename XT>
+__device__ __forceinline__ int kidx(int r, int p, int ldk, int swz) {
+  constexpr int SV = 16 / (int)sizeof(XT);
+  return r * ldk + (((p / SV) ^ (r & swz)) * SV) + (p % SV);
+}
+
+// ---------------------------------------------------------------------------
+// Khatri-Rao operand: Kfast [hl][Rpad][Pf] in XT, Kslow [Ps][Rpad] in AT
+// ---------------------------------------------------------------------------
+
+struct KrpArgs {
+  const void *H[NNCP_MAX_MODES];
+  int64_t dims[NNCP_MAX_MODES];
+  int fast_lo, fast_hi, slow_lo, slow_hi;
+  int R, Rpad, hl, scale16;
+  int64_t Pf, Ps;
+};
+
+template <typename HT>
+__device__ double krp_entry(const KrpArgs &a, int lo, int hi, int64_t rho, int r) {
+  double p = 1.0;
+  const HT *const *H = (const HT *const *)a.H;
+  for (int n = lo; n < hi; ++n) {
+    const int64_t d = rho % a.dims[n];
+    rho /= a.dims[n];
+    p *= (double)H[n][d * a.R + r];
+  }
+  return p;
+}
+
+template <typename XT, typename HT>
+__global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict__ kfast,
+                                                      HT *__restrict__ kslow) {
+  const int r = blockIdx.x;
+  const bool live = r < a.R;
+  __shared__ double red[256];
+  double mx = 0.0;
+  if (live)
+    for (int64_t p = threadIdx.x; p < a.Pf; p += 256) {
+      const double v = krp_entry<HT>(a, a.fast_lo, a.fast_hi, p, r);
+      mx = fmax(mx, fabs(v));
+    }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mx = red[0];
+  int e = 0;
+  if (a.scale16 && mx > 0.0) {
+    int E;
+    frexp(mx, &E);  // mx = f 2^E, f in [0.5, 1)
+    e = 14 - E;     // max entry lands in [2^13, 2^14)
+  }
+  const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
+  for (int64_t p = threadIdx.x; p < a.Pf; p += 256) {
+    const double v = live ? krp_entry<HT>(a, a.fast_lo, a.fast_hi, p, r) * up : 0.0;
+    const XT hi = from_d<XT>(v);
+    kfast[(int64_t)r * a.Pf + p] = hi;
+    if (a.hl) kfast[((int64_t)a.Rpad + r) * a.Pf + p] = from_d<XT>(v - to_d<XT>(hi));
+  }
+  for (int64_t q = threadIdx.x; q < a.Ps; q += 256) {
+    const double w = live ? krp_entry<HT>(a, a.slow_lo, a.slow_hi, q, r) * down : 0.0;
+    kslow[q * a.Rpad + r] = (HT)w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// right partial MTTKRP on the matrix cores (reduction over the contiguous index)
+//
+// Workgroup = 4 waves on the same 16*MT rows of Xr; the workgroup's share of
+// the reduction (split blockIdx.y of nsplit) is cut into 4 contiguous pieces,
+// one per wave; the waves' sums are added through LDS in wave order.
+// out: [nsplit][k][R] partial sums (factor type).
+// ---------------------------------------------------------------------------
+
+template <typename XT, int MT, int NT, bool HL, bool SLOW, int U>
+__global__ __launch_bounds__(256) void k_gemm_right_mfma(
+    const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
+    const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int64_t steps_total, int nsplit,
+    int R, typename XTraits<XT>::AT *__restrict__ out) {
+  typedef typename XTraits<XT>::AT AT;
+  typedef typename CFrag<AT>::T CT;
+  constexpr int VEC = XTraits<XT>::VEC;
+  constexpr int KSTEP = 4 * VEC;
+  constexpr int RP = 16 * NT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  XT *sk = reinterpret_cast<XT *>(smem);
+  const int swz = ((Pf / VEC) % 16 == 0) ? 15 : 0;
+  const int ldk = swz ? Pf : Pf + VEC;
+
+  // stage Kfast (hi, then lo) into LDS
+  {
+    const int nv = Pf / VEC;
+    const int total = RP * nv * (HL ? 2 : 1);
+    for (int e = threadIdx.x; e < total; e += 256) {
+      const int h = e / (RP * nv);
+      const int rem = e - h * RP * nv;
+      const int r = rem / nv, v = rem - r * nv;
+      *reinterpret_cast<u32x4 *>(sk + h * RP * ldk + kidx<XT>(r, v * VEC, ldk, swz)) =
+          *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + v * VEC);
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, g = lane >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * (16 * MT);
+  const int64_t s_lo = steps_total * blockIdx.y / nsplit;
+  const int64_t s_hi = steps_total * (blockIdx.y + 1) / nsplit;
+  const int64_t w_lo = s_lo + (s_hi - s_lo) * wave / 4;
+  const int64_t w_hi = s_lo + (s_hi - s_lo) * (wave + 1) / 4;
+  const int spb = Pf / KSTEP;
+
+  const XT *xp[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    int64_t jr = j0 + 16 * mt + row;
+    if (jr > k - 1) jr = k - 1;
+    xp[mt] = X + jr * m + g * VEC;
+  }
+
+  CT acc[MT][NT], blk[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) { czero(acc[mt][nt]); czero(blk[mt][nt]); }
+
+  auto step = [&](const u32x4 *va, int64_t t) {
+    const int pf0 = (int)(t % spb) * KSTEP;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const XT *bp = sk + kidx<XT>(16 * nt + row, pf0 + g * VEC, ldk, swz);
+      const u32x4 vb = *reinterpret_cast<const u32x4 *>(bp);
+      u32x4 vbl;
+      if (HL) vbl = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        CT &c = SLOW ? blk[mt][nt] : acc[mt][nt];
+        mma16(c, va[mt], vb, (XT *)nullptr);
+        if (HL) mma16(c, va[mt], vbl, (XT *)nullptr);
+      }
+    }
+    if (SLOW && ((t + 1) % spb == 0 || t + 1 == w_hi)) {
+      const int64_t b = t / spb;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const AT s = kslow[b * RP + 16 * nt + row];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[mt][nt][v] += blk[mt][nt][v] * s;
+          czero(blk[mt][nt]);
+        }
+      }
+    }
+  };
+
+  int64_t t = w_lo;
+  for (; t + U <= w_hi; t += U) {
+    u32x4 va[U][MT];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        va[u][mt] = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4 *>(xp[mt] + (t + u) * KSTEP));
+#pragma unroll
+    for (int u = 0; u < U; ++u) step(va[u], t + u);
+  }
+  for (; t < w_hi; ++t) {
+    u32x4 va[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      va[mt] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(xp[mt] + t * KSTEP));
+    step(va, t);
+  }
+  if (!SLOW) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const AT s = kslow[16 * nt + row];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[mt][nt][v] *= s;
+    }
+  }
+
+  // add the four waves' sums in wave order
+  constexpr int NV = MT * NT * 4;
+  __syncthreads();
+  AT *red = reinterpret_cast<AT *>(smem);
+  if (wave > 0) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          red[((wave - 1) * NV + (mt * NT + nt) * 4 + v) * 64 + lane] = acc[mt][nt][v];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    AT *o = out + (int64_t)blockIdx.y * k * R;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int e = (mt * NT + nt) * 4 + v;
+          AT s = acc[mt][nt][v];
+          s += red[(0 * NV + e) * 64 + lane];
+          s += red[(1 * NV + e) * 64 + lane];
+          s += red[(2 * NV + e) * 64 + lane];
+          const int64_t j = j0 + 16 * mt + crow<AT>(g, v);
+          const int r = 16 * nt + row;
+          if (j < k && r < R) o[j * R + r] = s;
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// left partial MTTKRP on the matrix cores (reduction over rows of Xr)
+//
+// Each wave owns 16*QV consecutive columns i of Xr; lane (rho, g) loads QV
+// consecutive columns from KL rows.  For BF16/FP16 the KL x QV block is
+// transposed inside the lane (byte permutes) into QV A-operands of KL
+// reduction elements each; for FP32/FP64 (KL = 1) every loaded element is
+// an A-operand by itself.  out: [nsplit][R][m] (factor type), i.e. the node
+// layout of the paper (column block r contiguous).
+// ---------------------------------------------------------------------------
+
+template <int BYTES> struct LoadT;
+template <> struct LoadT<16> { typedef u32x4 T; };
+template <> struct LoadT<8> { typedef u32x2 T; };
+
+__device__ __forceinline__ uint32_t dw(const u32x4 &v, int i) { return v[i]; }
+__device__ __forceinline__ uint32_t dw(const u32x2 &v, int i) { return v[i]; }
+
+template <typename XT, int QV, int NT, bool HL, bool SLOW>
+__global__ __launch_bounds__(256) void k_gemm_left_mfma(
+    const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
+    const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int64_t steps_total, int nsplit,
+    int R, typename XTraits<XT>::AT *__restrict__ out) {
+  typedef typename XTraits<XT>::AT AT;
+  typedef typename CFrag<AT>::T CT;
+  constexpr int KL = XTraits<XT>::KL;
+  constexpr int KSTEP = 4 * KL;  // rows per step
+  constexpr int RP = 16 * NT;
+  constexpr int LB = QV * (int)sizeof(XT);
+  typedef typename LoadT<LB>::T LT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  XT *sk = reinterpret_cast<XT *>(smem);
+  constexpr int SVEC = 16 / (int)sizeof(XT);
+  const int swz = ((Pf / SVEC) % 16 == 0) ? 15 : 0;
+  const int ldk = swz ? Pf : Pf + SVEC;
+
+  {
+    const int nv = Pf / SVEC;
+    const int total = RP * nv * (HL ? 2 : 1);
+    for (int e = threadIdx.x; e < total; e += 256) {
+      const int h = e / (RP * nv);
+      const int rem = e - h * RP * nv;
+      const int r = rem / nv, v = rem - r * nv;
+      *reinterpret_cast<u32x4 *>(sk + h * RP * ldk + kidx<XT>(r, v * SVEC, ldk, swz)) =
+          *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + v * SVEC);
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rho = lane & 15, g = lane >> 4;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * QV);
+  const int64_t il = i0 + QV * rho;
+  const bool valid = il < m;
+  const XT *xp = X + (valid ? il : 0) + (int64_t)(g * KL) * m;
+  const int64_t s_lo = steps_total * blockIdx.y / nsplit;
+  const int64_t s_hi = steps_total * (blockIdx.y + 1) / nsplit;
+  const int spb = Pf / KSTEP;
+
+  CT acc[QV][NT], blk[QV][NT];
+#pragma unroll
+  for (int q = 0; q < QV; ++q)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) { czero(acc[q][nt]); czero(blk[q][nt]); }
+
+  for (int64_t t = s_lo; t < s_hi; ++t) {
+    LT raw[KL];
+#pragma unroll
+    for (int u = 0; u < KL; ++u)
+      raw[u] = __builtin_nontemporal_load(
+          reinterpret_cast<const LT *>(xp + (t * KSTEP + u) * m));
+    const int pf0 = (int)(t % spb) * KSTEP;
+    if constexpr (KL == 8) {
+      u32x4 vb[NT], vbl[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const XT *bp = sk + kidx<XT>(16 * nt + rho, pf0 + g * KL, ldk, swz);
+        vb[nt] = *reinterpret_cast<const u32x4 *>(bp);
+        if (HL) vbl[nt] = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
+      }
+#pragma unroll
+      for (int q = 0; q < QV; ++q) {
+        const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
+        u32x4 a;
+        a.x = __builtin_amdgcn_perm(dw(raw[1], q >> 1), dw(raw[0], q >> 1), sel);
+        a.y = __builtin_amdgcn_perm(dw(raw[3], q >> 1), dw(raw[2], q >> 1), sel);
+        a.z = __builtin_amdgcn_perm(dw(raw[5], q >> 1), dw(raw[4], q >> 1), sel);
+        a.w = __builtin_amdgcn_perm(dw(raw[7], q >> 1), dw(raw[6], q >> 1), sel);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          CT &c = SLOW ? blk[q][nt] : acc[q][nt];
+          mma16(c, a, vb[nt], (XT *)nullptr);
+          if (HL) mma16(c, a, vbl[nt], (XT *)nullptr);
+        }
+      }
+    } else {
+      AT b[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[nt] = (AT)sk[kidx<XT>(16 * nt + rho, pf0 + g, ldk, swz)];
+      const AT *xv = reinterpret_cast<const AT *>(&raw[0]);
+#pragma unroll
+      for (int q = 0; q < QV; ++q)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) mma1(SLOW ? blk[q][nt] : acc[q][nt], xv[q], b[nt]);
+    }
+    if (SLOW && ((t + 1) % spb == 0 || t + 1 == s_hi)) {
+      const int64_t bI = t / spb;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const AT s = kslow[bI * RP + 16 * nt + rho];
+#pragma unroll
+        for (int q = 0; q < QV; ++q) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[q][nt][v] += blk[q][nt][v] * s;
+          czero(blk[q][nt]);
+        }
+      }
+    }
+  }
+
+  AT *o = out + (int64_t)blockIdx.y * R * m;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int r = 16 * nt + rho;  // result column of this lane
+    const AT s = SLOW ? (AT)1 : kslow[16 * nt + rho];
+    if (r < R) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t ib = i0 + QV * crow<AT>(g, v);
+        if (ib < m) {
+          AT vals[QV];
+#pragma unroll
+          for (int q = 0; q < QV; ++q) vals[q] = acc[q][nt][v] * s;
+          AT *dst = o + (int64_t)r * m + ib;
+#pragma unroll
+          for (int q = 0; q < QV; ++q) dst[q] = vals[q];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// portable vector-ALU partial MTTKRPs (any shape, any R; used when the
+// matrix-core preconditions are not met, and as a forced path)
+// ---------------------------------------------------------------------------
+
+struct GenArgs {
+  const void *H[NNCP_MAX_MODES];
+  int64_t dims[NNCP_MAX_MODES];
+  int red_lo, red_hi;  // reduced modes [lo, hi)
+  int R;
+  int64_t m, k;
+  int nsplit;
+};
+
+template <typename HT>
+__device__ __forceinline__ void krp_row(const GenArgs &a, int64_t rho, int r0, int rc, HT *out) {
+  const HT *const *H = (const HT *const *)a.H;
+  for (int c = 0; c < rc; ++c) out[c] = (HT)1;
+  for (int n = a.red_lo; n < a.red_hi; ++n) {
+    const int64_t d = rho % a.dims[n];
+    rho /= a.dims[n];
+    const HT *h = H[n] + d * a.R + r0;
+    for (int c = 0; c < rc; ++c) out[c] *= h[c];
+  }
+}
+
+// right: block per (row j, split); threads stride over i; 16-column chunks.
+template <typename XT, typename HT>
+__global__ __launch_bounds__(256) void k_gemm_right_generic(const XT *__restrict__ X, GenArgs a,
+                                                            HT *__restrict__ out) {
+  constexpr int RC = 16;
+  __shared__ HT red[RC][257];
+  const int64_t j = blockIdx.x;
+  const int64_t lo = a.m * blockIdx.y / a.nsplit, hi = a.m * (blockIdx.y + 1) / a.nsplit;
+  const XT *xr = X + j * a.m;
+  for (int r0 = 0; r0 < a.R; r0 += RC) {
+    const int rc = min(RC, a.R - r0);
+    HT acc[RC];
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+      HT kv[RC];
+      krp_row<HT>(a, i, r0, rc, kv);
+      const HT x = (HT)to_d<XT>(xr[i]);
+      for (int c = 0; c < rc; ++c) acc[c] += x * kv[c];
+    }
+    for (int c = 0; c < RC; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s)
+        for (int c = 0; c < RC; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x < rc) out[((int64_t)blockIdx.y * a.k + j) * a.R + r0 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// left: thread per column i, loop over the split's rows j.
+template <typename XT, typename HT>
+__global__ __launch_bounds__(256) void k_gemm_left_generic(const XT *__restrict__ X, GenArgs a,
+                                                           HT *__restrict__ out) {
+  constexpr int RC = 16;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t lo = a.k * blockIdx.y / a.nsplit, hi = a.k * (blockIdx.y + 1) / a.nsplit;
+  if (i >= a.m) return;
+  for (int r0 = 0; r0 < a.R; r0 += RC) {
+    const int rc = min(RC, a.R - r0);
+    HT acc[RC];
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    for (int64_t j = lo; j < hi; ++j) {
+      HT kv[RC];
+      krp_row<HT>(a, j, r0, rc, kv);
+      const HT x = (HT)to_d<XT>(X[j * a.m + i]);
+      for (int c = 0; c < rc; ++c) acc[c] += x * kv[c];
+    }
+    for (int c = 0; c < rc; ++c) out[((int64_t)blockIdx.y * a.R + r0 + c) * a.m + i] = acc[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: add the split partials in split order
+//   right partials [s][rows][R]; left partials [s][R][rows]
+//   node output [r][rows]; leaf output (M) [rows][r]
+// ---------------------------------------------------------------------------
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_finalize(const HT *__restrict__ part, int64_t rows, int R,
+                                                  int nsplit, int part_rmajor, int leaf,
+                                                  HT *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * R) return;
+  int64_t row, r;
+  if (leaf) { row = e / R; r = e % R; } else { r = e / rows; row = e % rows; }
+  const int64_t src = part_rmajor ? r * rows + row : row * R + r;
+  HT s = part[src];
+  for (int q = 1; q < nsplit; ++q) s += part[(int64_t)q * rows * R + src];
+  out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static KrpArgs make_krp_args(const GemmPlan &p, int R, const int64_t *dims, const FactorSet &F,
+                             int N) {
+  KrpArgs a;
+  for (int n = 0; n < NNCP_MAX_MODES; ++n) {
+    a.H[n] = n < N ? F.H[n] : nullptr;
+    a.dims[n] = n < N ? dims[n] : 1;
+  }
+  a.fast_lo = p.fast_lo; a.fast_hi = p.fast_hi;
+  a.slow_lo = p.slow_lo; a.slow_hi = p.slow_hi;
+  a.R = R; a.Rpad = p.Rpad; a.hl = p.hl; a.scale16 = 0;
+  a.Pf = p.Pf; a.Ps = p.Ps;
+  return a;
+}
+
+hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t *dims, int N,
+                               const FactorSet &F, void *kfast, void *kslow, hipStream_t st) {
+  KrpArgs a = make_krp_args(p, R, dims, F, N);
+  dim3 grid(p.Rpad), block(256);
+  switch (xdt) {
+    case NNCP_BF16:
+      hipLaunchKernelGGL((k_krp_operands<bf16_t, float>), grid, block, 0, st, a, (bf16_t *)kfast, (float *)kslow);
+      break;
+    case NNCP_F16:
+      a.scale16 = 1;
+      hipLaunchKernelGGL((k_krp_operands<f16_t, float>), grid, block, 0, st, a, (f16_t *)kfast, (float *)kslow);
+      break;
+    case NNCP_F32:
+      hipLaunchKernelGGL((k_krp_operands<float, float>), grid, block, 0, st, a, (float *)kfast, (float *)kslow);
+      break;
+    case NNCP_F64:
+      hipLaunchKernelGGL((k_krp_operands<double, double>), grid, block, 0, st, a, (double *)kfast, (double *)kslow);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename XT, int MT, int NT, bool HL, bool SLOW>
+static void run_right(const GemmPlan &p, int R, const void *X, const void *kf, const void *ks,
+                      void *out, hipStream_t st) {
+  typedef typename XTraits<XT>::AT AT;
+  constexpr int KSTEP = 4 * XTraits<XT>::VEC;
+  dim3 grid((unsigned)p.tiles, p.nsplit), block(256);
+  hipLaunchKernelGGL((k_gemm_right_mfma<XT, MT, NT, HL, SLOW, 4>), grid, block, p.lds_bytes, st,
+                     (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf,
+                     (p.m / KSTEP), p.nsplit, R, (AT *)out);
+}
+
+template <typename XT, int QV, int NT, bool HL, bool SLOW>
+static void run_left(const GemmPlan &p, int R, const void *X, const void *kf, const void *ks,
+                     void *out, hipStream_t st) {
+  typedef typename XTraits<XT>::AT AT;
+  constexpr int KSTEP = 4 * XTraits<XT>::KL;
+  dim3 grid((unsigned)p.tiles, p.nsplit), block(256);
+  hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW>), grid, block, p.lds_bytes, st,
+                     (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf,
+                     (p.k / KSTEP), p.nsplit, R, (AT *)out);
+}
+
+// NT dispatch (1..4) with the template flags fixed
+#define NNCP_NT_SWITCH(NTV, CALL) \
+  switch (NTV) {                  \
+    case 1: { constexpr int NTC = 1; CALL; } break; \
+    case 2: { constexpr int NTC = 2; CALL; } break; \
+    case 3: { constexpr int NTC = 3; CALL; } break; \
+    case 4: { constexpr int NTC = 4; CALL; } break; \
+    default: return hipErrorInvalidValue;           \
+  }
+
+template <typename XT>
+static hipError_t dispatch_mfma(const GemmPlan &p, int R, const void *X, const void *kf,
+                                const void *ks, void *out, hipStream_t st) {
+  constexpr bool IS16 = sizeof(XT) == 2;
+  const bool slow = p.Ps > 1;
+  if (p.side == 1) {
+    constexpr int MT = sizeof(XT) == 8 ? 1 : 2;
+    if (IS16 && p.hl) {
+      if (slow) { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, IS16, true>(p, R, X, kf, ks, out, st))) }
+      else { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, IS16, false>(p, R, X, kf, ks, out, st))) }
+    } else {
+      if (slow) { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, false, true>(p, R, X, kf, ks, out, st))) }
+      else { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+    }
+  } else {
+    // columns per lane: 8 (16 B) for 16-bit types up to 32 columns of R, else 4
+    if constexpr (IS16) {
+      if (p.NT <= 2) {
+        if (p.hl) {
+          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 8, NTC, IS16, true>(p, R, X, kf, ks, out, st))) }
+          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 8, NTC, IS16, false>(p, R, X, kf, ks, out, st))) }
+        } else {
+          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 8, NTC, false, true>(p, R, X, kf, ks, out, st))) }
+          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 8, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+        }
+      } else {
+        if (p.hl) {
+          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, IS16, true>(p, R, X, kf, ks, out, st))) }
+          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, IS16, false>(p, R, X, kf, ks, out, st))) }
+        } else {
+          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, false, true>(p, R, X, kf, ks, out, st))) }
+          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+        }
+      }
+    } else {
+      constexpr int QV = 16 / sizeof(XT);
+      if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, QV, NTC, false, true>(p, R, X, kf, ks, out, st))) }
+      else { NNCP_NT_SWITCH(p.NT, (run_left<XT, QV, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename XT, typename HT>
+static hipError_t dispatch_generic(const GemmPlan &p, int R, const void *X, const int64_t *dims,
+                                   int N, int S, const FactorSet &F, void *out, hipStream_t st) {
+  GenArgs a;
+  for (int n = 0; n < NNCP_MAX_MODES; ++n) {
+    a.H[n] = n < N ? F.H[n] : nullptr;
+    a.dims[n] = n < N ? dims[n] : 1;
+  }
+  a.R = R; a.m = p.m; a.k = p.k; a.nsplit = p.nsplit;
+  if (p.side == 1) {
+    a.red_lo = 0; a.red_hi = S;
+    hipLaunchKernelGGL((k_gemm_right_generic<XT, HT>), dim3((unsigned)p.k, p.nsplit), dim3(256), 0, st,
+                       (const XT *)X, a, (HT *)out);
+  } else {
+    a.red_lo = S; a.red_hi = N;
+    hipLaunchKernelGGL((k_gemm_left_generic<XT, HT>), dim3((unsigned)((p.m + 255) / 256), p.nsplit),
+                       dim3(256), 0, st, (const XT *)X, a, (HT *)out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_partial_mttkrp(int xdt, const GemmPlan &p, int R, const void *X,
+                                 const int64_t *dims, int N, int S, const FactorSet &F,
+                                 const void *kfast, const void *kslow, void *out,
+                                 hipStream_t st) {
+  if (p.mfma) {
+    switch (xdt) {
+      case NNCP_BF16: return dispatch_mfma<bf16_t>(p, R, X, kfast, kslow, out, st);
+      case NNCP_F16: return dispatch_mfma<f16_t>(p, R, X, kfast, kslow, out, st);
+      case NNCP_F32: return dispatch_mfma<float>(p, R, X, kfast, kslow, out, st);
+      case NNCP_F64: return dispatch_mfma<double>(p, R, X, kfast, kslow, out, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (xdt) {
+    case NNCP_BF16: return dispatch_generic<bf16_t, float>(p, R, X, dims, N, S, F, out, st);
+    case NNCP_F16: return dispatch_generic<f16_t, float>(p, R, X, dims, N, S, F, out, st);
+    case NNCP_F32: return dispatch_generic<float, float>(p, R, X, dims, N, S, F, out, st);
+    case NNCP_F64: return dispatch_generic<double, double>(p, R, X, dims, N, S, F, out, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(int hdt, const GemmPlan &p, int R, const void *part, void *out,
+                           int leaf, hipStream_t st) {
+  const int64_t rows = p.side == 1 ? p.k : p.m;
+  const int rmajor = p.side == 0;
+  const int64_t n = rows * R;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL((k_finalize<double>), grid, block, 0, st, (const double *)part, rows, R,
+                       p.nsplit, rmajor, leaf, (double *)out);
+  else
+    hipLaunchKernelGGL((k_finalize<float>), grid, block, 0, st, (const float *)part, rows, R,
+                       p.nsplit, rmajor, leaf, (float *)out);
+  return hipGetLastError();
+}
+
+}  // namespace nncp

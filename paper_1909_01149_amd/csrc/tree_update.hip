@@ -1,0 +1,683 @@
+// Dimension-tree multi-TTVs (Section 3.2, Algorithm 3 multi-TTV lines), Gram
+// and Hadamard products (Algorithm 1), the per-mode factor update with
+// column normalisation and the relative-error identity (Eqs. eqn:muupd,
+// eqn:halsupd; Appendix A, Algorithm 4), the loss, the gradient of the loss
+// and the projected-gradient helpers.
+//
+// Node layout (as in the paper's Figure 3): a node T over modes a..b is
+// I_a x ... x I_b x R with column block r contiguous: entry (i_a, .., i_b, r)
+// at r * P + i_a + I_a (i_{a+1} + ...), P = I_a ... I_b.
+// Factors and M are I x R row-major.  Every reduction is done in a fixed order
+// (no atomics), so results are bitwise reproducible run to run.
+#include "nncp_internal.h"
+
+namespace nncp {
+
+template <typename T> __device__ __forceinline__ double to_dd(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_dd<bf16_t>(bf16_t v) { return (double)(float)v; }
+template <> __device__ __forceinline__ double to_dd<f16_t>(f16_t v) { return (double)(float)v; }
+
+// sum over the 64 lanes of a wave, fixed butterfly order
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// multi-TTV, contiguous reduction: out(q, r) = sum_i T[r][i + Ia q] H(i, r)
+// G lanes per output (G = power of two <= 64), outputs ordered (r, q).
+// ---------------------------------------------------------------------------
+template <typename HT>
+__global__ __launch_bounds__(256) void k_mttv_contig(const HT *__restrict__ T, int64_t Ia, int64_t Q,
+                                                     int R, const HT *__restrict__ H,
+                                                     HT *__restrict__ out, int leaf, int G) {
+  const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t o = gt / G;
+  const int sub = (int)(gt % G);
+  const int64_t total = Q * R;
+  const bool live = o < total;
+  const int64_t r = live ? o / Q : 0, q = live ? o % Q : 0;
+  HT acc = 0;
+  if (live) {
+    const HT *t = T + r * (Ia * Q) + Ia * q;
+    for (int64_t i = sub; i < Ia; i += G) acc += t[i] * H[i * R + r];
+  }
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (live && sub == 0) {
+    if (leaf) out[q * R + r] = acc;
+    else out[r * Q + q] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// multi-TTV, strided reduction keeping the first mode:
+//   part[z][i][r] = sum_{q in split z} T[r][i + Ia q] K(q, r),
+//   K(q, r) = prod_k H^(k)(digit_k(q), r) over the node's remaining modes.
+// Block = IT columns i x QS q-lanes; q-lanes added in order through LDS.
+// ---------------------------------------------------------------------------
+struct StridedArgs {
+  const void *H[NNCP_MAX_MODES];
+  int64_t qd[NNCP_MAX_MODES];
+  int nq;
+  int64_t Ia, Q;
+  int R, IT, QS, nsplit;
+};
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, StridedArgs a,
+                                                      HT *__restrict__ part) {
+  __shared__ HT red[256];
+  const int il = threadIdx.x % a.IT, qs = threadIdx.x / a.IT;
+  const int64_t i = (int64_t)blockIdx.x * a.IT + il;
+  const int r = blockIdx.y;
+  const int64_t z = blockIdx.z;
+  const int64_t q0 = a.Q * z / a.nsplit, q1 = a.Q * (z + 1) / a.nsplit;
+  HT acc = 0;
+  if (i < a.Ia) {
+    const HT *t = T + (int64_t)r * a.Ia * a.Q + i;
+    const HT *const *H = (const HT *const *)a.H;
+    for (int64_t q = q0 + qs; q < q1; q += a.QS) {
+      HT kv = 1;
+      int64_t rem = q;
+      for (int n = 0; n < a.nq; ++n) {
+        const int64_t d = rem % a.qd[n];
+        rem /= a.qd[n];
+        kv *= H[n][d * a.R + r];
+      }
+      acc += t[a.Ia * q] * kv;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (qs == 0 && i < a.Ia) {
+    HT s = red[il];
+    for (int k = 1; k < a.QS; ++k) s += red[k * a.IT + il];
+    part[(z * a.Ia + i) * a.R + r] = s;
+  }
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_sum_splits(const HT *__restrict__ part, int64_t n, int ns,
+                                                    HT *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  HT s = part[e];
+  for (int z = 1; z < ns; ++z) s += part[(int64_t)z * n + e];
+  out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Gram G = H^T H, FP64, one workgroup of 1024 threads: thread (pair p, slice s)
+// sums rows i = s (mod ns); slices are added in order through LDS.
+// ---------------------------------------------------------------------------
+template <typename HT>
+__device__ void gram_block(const HT *__restrict__ H, int64_t I, int R, double *__restrict__ G,
+                           double *lds /* >= 1024 doubles */) {
+  const int npairs = R * (R + 1) / 2;
+  int ns = 1;
+  while (ns * 2 * npairs <= 1024) ns *= 2;
+  for (int base = 0; base < npairs; base += 1024 / ns) {
+    const int pl = threadIdx.x / ns, s = threadIdx.x % ns;
+    const int p = base + pl;
+    double acc = 0.0;
+    int a = 0, b = 0;
+    if (pl < 1024 / ns && p < npairs) {
+      // pair index -> (a, b), a <= b
+      int rem = p;
+      a = 0;
+      while (rem >= R - a) { rem -= R - a; ++a; }
+      b = a + rem;
+      for (int64_t i = s; i < I; i += ns) acc += (double)H[i * R + a] * (double)H[i * R + b];
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    if (s == 0 && pl < 1024 / ns && p < npairs) {
+      double v = lds[threadIdx.x];
+      for (int k = 1; k < ns; ++k) v += lds[threadIdx.x + k];
+      G[a * R + b] = v;
+      G[b * R + a] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename HT>
+__global__ __launch_bounds__(1024) void k_gram(const HT *__restrict__ H, int64_t I, int R,
+                                               double *__restrict__ G) {
+  __shared__ double lds[1024];
+  gram_block<HT>(H, I, R, G, lds);
+}
+
+__global__ __launch_bounds__(256) void k_hadamard(const double *__restrict__ G, int N, int R,
+                                                  int mode, double *__restrict__ S) {
+  for (int e = threadIdx.x; e < R * R; e += 256) {
+    double s = 1.0;
+    for (int k = 0; k < N; ++k)
+      if (k != mode) s *= G[(int64_t)k * R * R + e];
+    S[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ||X||^2: grid-stride FP64 partial sums, then one block adds them in order
+// ---------------------------------------------------------------------------
+template <typename XT>
+__global__ __launch_bounds__(256) void k_sumsq_part(const XT *__restrict__ X, int64_t n,
+                                                    double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
+    const double v = to_dd<XT>(X[e]);
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ part, int np,
+                                                   double *__restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < np; e += 256) acc += part[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// per-mode update: one workgroup of 1024 threads
+//   Hhat = H diag(lambda);  MU or HALS on Hhat;  lambda = column norms;
+//   H = Hhat / lambda;  G^(mode) = H^T H;  and after the last mode
+//   beta = <M, Hhat>, gamma = lambda^T (S * G) lambda,
+//   relerr = sqrt(max(0, alpha - 2 beta + gamma) / alpha).
+// A row of Hhat is held by LPR lanes (LPR = power of two >= R, at most 64),
+// lane `sub` owning columns sub + LPR u, u < CPL.  HALS keeps the residual
+// g = M - Hhat S of the row and, column by column in order, broadcasts the
+// change of column r from its owner lane and updates g; this is the same
+// arithmetic as forming (Hhat S)(:, r) afresh from the latest Hhat.
+// ---------------------------------------------------------------------------
+template <typename HT, int CPL>
+__global__ __launch_bounds__(1024) void k_update(UpdateArgs a) {
+  __shared__ double sS[64 * 64];
+  __shared__ double wred[16][64];
+  __shared__ double lam_s[256];
+  __shared__ double lds[1024];
+  const int R = a.R;
+  const bool s_in_lds = R <= 64;
+  if (s_in_lds) {
+    for (int e = threadIdx.x; e < R * R; e += 1024) {
+      double s;
+      if (a.S) s = a.S[e];
+      else {
+        s = 1.0;
+        for (int k = 0; k < a.N; ++k)
+          if (k != a.mode) s *= a.G[(int64_t)k * R * R + e];
+      }
+      sS[e] = s;
+    }
+  }
+  for (int c = threadIdx.x; c < R; c += 1024) lam_s[c] = a.lambda[c];
+  __syncthreads();
+  const double *Sg = a.S;
+  auto Sv = [&](int c, int r) -> double { return s_in_lds ? sS[c * R + r] : Sg[c * R + r]; };
+
+  int LPR = 64;
+  if (CPL == 1) { LPR = 1; while (LPR < R) LPR *= 2; }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rpw = 64 / LPR;
+  const int sub = lane % LPR, grp = lane / LPR, base = grp * LPR;
+  const HT *M = (const HT *)a.M;
+  HT *H = (HT *)a.H;
+
+  double colsq[CPL], beta = 0.0;
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) colsq[u] = 0.0;
+
+  for (int64_t i0 = 0; i0 < a.I; i0 += 16 * rpw) {
+    const int64_t i = i0 + wave * rpw + grp;
+    const bool live = i < a.I;
+    double h[CPL], m[CPL], g[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int c = sub + LPR * u;
+      const bool ok = live && c < R;
+      h[u] = ok ? (double)H[i * R + c] * lam_s[c] : 0.0;
+      m[u] = ok ? (double)M[i * R + c] : 0.0;
+      g[u] = 0.0;
+    }
+    // g = (Hhat S)(i, :) for the lane's columns
+    for (int j = 0; j < R; ++j) {
+      const int uj = j / LPR;
+      double src = h[0];
+#pragma unroll
+      for (int u = 1; u < CPL; ++u)
+        if (uj == u) src = h[u];
+      const double hj = __shfl(src, base + (j % LPR), 64);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        const int c = sub + LPR * u;
+        if (c < R) g[u] += hj * Sv(j, c);
+      }
+    }
+    if (a.algo == NNCP_MU) {
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) h[u] = h[u] * m[u] / (g[u] + a.eps);
+    } else {
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) g[u] = m[u] - g[u];
+      for (int r = 0; r < R; ++r) {
+        const double d = Sv(r, r);
+        if (!(d > 0.0)) continue;
+        const int ur = r / LPR, owner = base + (r % LPR);
+        double hs = h[0], gs = g[0];
+#pragma unroll
+        for (int u = 1; u < CPL; ++u)
+          if (ur == u) { hs = h[u]; gs = g[u]; }
+        const double hr = __shfl(hs, owner, 64), gr = __shfl(gs, owner, 64);
+        double v = hr + gr / d;
+        v = v > 0.0 ? v : 0.0;
+        const double delta = v - hr;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          const int c = sub + LPR * u;
+          if (c < R) g[u] -= delta * Sv(r, c);
+          if (u == ur && sub == (r % LPR)) h[u] = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int c = sub + LPR * u;
+      if (live && c < R) {
+        a.hhat[i * R + c] = h[u];
+        colsq[u] += h[u] * h[u];
+        beta += m[u] * h[u];
+      }
+    }
+  }
+  // column sums of squares: across the row groups of a wave, then waves in order
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    for (int off = LPR; off < 64; off *= 2) colsq[u] += __shfl_xor(colsq[u], off, 64);
+  }
+  for (int u = 0; u < CPL; ++u) {
+    if (grp == 0) wred[wave][sub] = colsq[u];
+    __syncthreads();
+    if (threadIdx.x < LPR) {
+      const int c = threadIdx.x + LPR * u;
+      double s = 0.0;
+      for (int w = 0; w < 16; ++w) s += wred[w][threadIdx.x];
+      if (c < R) lam_s[c] = sqrt(s);
+    }
+    __syncthreads();
+  }
+  {
+    const double v = wave_sum(beta);
+    if (lane == 0) wred[wave][0] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < 16; ++w) s += wred[w][0];
+      beta = s;
+    }
+    __syncthreads();
+  }
+  // normalise (each lane re-reads the Hhat entries it wrote)
+  for (int64_t i0 = 0; i0 < a.I; i0 += 16 * rpw) {
+    const int64_t i = i0 + wave * rpw + grp;
+    if (i >= a.I) continue;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int c = sub + LPR * u;
+      if (c < R) {
+        const double l = lam_s[c];
+        H[i * R + c] = (HT)(l > 0.0 ? a.hhat[i * R + c] / l : 0.0);
+      }
+    }
+  }
+  for (int c = threadIdx.x; c < R; c += 1024) a.lambda[c] = lam_s[c];
+  __syncthreads();
+  double *Gm = a.G + (int64_t)a.mode * R * R;
+  gram_block<HT>(H, a.I, R, Gm, lds);
+  __syncthreads();
+  if (a.relerr_out || a.scal) {
+    double gsum = 0.0;
+    for (int r = threadIdx.x; r < R; r += 1024) {
+      double s = 0.0;
+      for (int c = 0; c < R; ++c) s += lam_s[c] * Sv(r, c) * Gm[r * R + c];
+      gsum += lam_s[r] * s;
+    }
+    const double v = wave_sum(gsum);
+    if (lane == 0) wred[wave][1] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double gamma = 0.0;
+      for (int w = 0; w < 16; ++w) gamma += wred[w][1];
+      const double alpha = a.alpha ? a.alpha[0] : 0.0;
+      const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+      if (a.scal) {
+        a.scal[0] = beta;
+        a.scal[1] = gamma;
+        a.scal[2] = e2;
+      }
+      if (a.relerr_out) a.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// loss of [[lambda; H]] given M^(N-1) at the current factors
+// ---------------------------------------------------------------------------
+template <typename HT>
+__global__ __launch_bounds__(1024) void k_loss(int N, int R, int64_t In, const HT *__restrict__ M,
+                                               const HT *__restrict__ H,
+                                               const double *__restrict__ lambda,
+                                               const double *__restrict__ G,
+                                               const double *__restrict__ alpha, double *loss,
+                                               double *relerr, double *scal) {
+  __shared__ double wred[16][2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double beta = 0.0;
+  for (int64_t e = threadIdx.x; e < In * R; e += 1024)
+    beta += (double)M[e] * (double)H[e] * lambda[e % R];
+  double gamma = 0.0;
+  for (int e = threadIdx.x; e < R * R; e += 1024) {
+    double s = 1.0;
+    for (int k = 0; k < N; ++k) s *= G[(int64_t)k * R * R + e];
+    gamma += lambda[e / R] * s * lambda[e % R];
+  }
+  beta = wave_sum(beta);
+  gamma = wave_sum(gamma);
+  if (lane == 0) { wred[wave][0] = beta; wred[wave][1] = gamma; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0, g = 0.0;
+    for (int w = 0; w < 16; ++w) { b += wred[w][0]; g += wred[w][1]; }
+    const double al = alpha[0];
+    const double r2 = al - 2.0 * b + g;
+    if (loss) loss[0] = 0.5 * r2;
+    if (relerr) relerr[0] = sqrt((r2 > 0.0 ? r2 : 0.0) / al);
+    if (scal) { scal[0] = b; scal[1] = g; scal[2] = r2 / al; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gradient of 0.5 ||X - [[H]]||^2 for one mode: grad = H S - M
+// ---------------------------------------------------------------------------
+template <typename HT>
+__global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
+                                              const HT *__restrict__ M, const HT *__restrict__ H,
+                                              const double *__restrict__ G,
+                                              const double *__restrict__ Sg, HT *__restrict__ grad) {
+  // S in LDS for R <= 64, else read from the global Hadamard product Sg
+  __shared__ double sS[64 * 64];
+  const bool lds = R <= 64;
+  if (lds) {
+    for (int e = threadIdx.x; e < R * R; e += 256) {
+      double s = 1.0;
+      for (int k = 0; k < N; ++k)
+        if (k != mode) s *= G[(int64_t)k * R * R + e];
+      sS[e] = s;
+    }
+  }
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * R) return;
+  const int64_t i = e / R;
+  const int r = (int)(e % R);
+  double s = 0.0;
+  for (int c = 0; c < R; ++c) s += (double)H[i * R + c] * (lds ? sS[c * R + r] : Sg[c * R + r]);
+  grad[e] = (HT)(s - (double)M[e]);
+}
+
+// ---------------------------------------------------------------------------
+// projected gradient helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pgd_eta(const double *__restrict__ G, int N, int R,
+                                                 int iters, double *__restrict__ eta) {
+  extern __shared__ double sh[];
+  double *S = sh;              // R*R
+  double *v = sh + R * R;      // R
+  double *w = v + R;           // R
+  __shared__ double red[256];
+  double lmax = 0.0;
+  for (int n = 0; n < N; ++n) {
+    for (int e = threadIdx.x; e < R * R; e += 256) {
+      double s = 1.0;
+      for (int k = 0; k < N; ++k)
+        if (k != n) s *= G[(int64_t)k * R * R + e];
+      S[e] = s;
+    }
+    for (int i = threadIdx.x; i < R; i += 256) v[i] = 1.0 / sqrt((double)R);
+    __syncthreads();
+    bool zero = false;
+    for (int t = 0; t < iters && !zero; ++t) {
+      double part = 0.0;
+      for (int i = threadIdx.x; i < R; i += 256) {
+        double s = 0.0;
+        for (int j = 0; j < R; ++j) s += S[i * R + j] * v[j];
+        w[i] = s;
+        part += s * s;
+      }
+      red[threadIdx.x] = part;
+      __syncthreads();
+      for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+      }
+      const double nrm = sqrt(red[0]);
+      __syncthreads();
+      if (!(nrm > 0.0)) { zero = true; break; }
+      for (int i = threadIdx.x; i < R; i += 256) v[i] = w[i] / nrm;
+      __syncthreads();
+    }
+    double part = 0.0;
+    for (int i = threadIdx.x; i < R; i += 256) {
+      double s = 0.0;
+      for (int j = 0; j < R; ++j) s += S[i * R + j] * v[j];
+      part += v[i] * s;
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (red[0] > lmax) lmax = red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) eta[0] = lmax > 0.0 ? 1.0 / lmax : 1.0;
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_pgd_trial(int64_t n, const HT *__restrict__ H,
+                                                   const HT *__restrict__ g, double eta,
+                                                   HT *__restrict__ Hn, double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
+    const double h = (double)H[e];
+    double v = h - eta * (double)g[e];
+    v = v > 0.0 ? v : 0.0;
+    const HT vn = (HT)v;
+    Hn[e] = vn;
+    const double d = (double)vn - h;
+    acc += d * d;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R, const void *H,
+                              void *out, int leaf, hipStream_t st) {
+  int G = 1;
+  while (G < 64 && G < Ia) G *= 2;
+  const int64_t threads = Q * R * G;
+  dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_mttv_contig<double>, grid, block, 0, st, (const double *)T, Ia, Q, R,
+                       (const double *)H, (double *)out, leaf, G);
+  else
+    hipLaunchKernelGGL(k_mttv_contig<float>, grid, block, 0, st, (const float *)T, Ia, Q, R,
+                       (const float *)H, (float *)out, leaf, G);
+  return hipGetLastError();
+}
+
+static void strided_shape(int64_t Ia, int64_t Q, int R, int &IT, int &QS, int &ns, int64_t &gx) {
+  IT = 1;
+  while (IT < 256 && IT < Ia) IT *= 2;
+  QS = 256 / IT;
+  gx = (Ia + IT - 1) / IT;
+  int64_t want = (2048 + gx * R - 1) / (gx * R);
+  int64_t maxs = (Q + QS - 1) / QS;
+  if (want > maxs) want = maxs;
+  if (want < 1) want = 1;
+  if (want > 4096) want = 4096;
+  ns = (int)want;
+}
+
+int64_t mttv_strided_part_elems(int64_t Ia, const int64_t *qdims, int nq, int R) {
+  int64_t Q = 1;
+  for (int k = 0; k < nq; ++k) Q *= qdims[k];
+  int IT, QS, ns;
+  int64_t gx;
+  strided_shape(Ia, Q, R, IT, QS, ns, gx);
+  return (int64_t)ns * Ia * R;
+}
+
+hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
+                               const void *const *Hq, int R, void *M, void *part,
+                               int64_t part_elems, hipStream_t st) {
+  StridedArgs a;
+  int64_t Q = 1;
+  for (int k = 0; k < NNCP_MAX_MODES; ++k) {
+    a.H[k] = k < nq ? Hq[k] : nullptr;
+    a.qd[k] = k < nq ? qdims[k] : 1;
+    if (k < nq) Q *= qdims[k];
+  }
+  a.nq = nq; a.Ia = Ia; a.Q = Q; a.R = R;
+  int64_t gx;
+  strided_shape(Ia, Q, R, a.IT, a.QS, a.nsplit, gx);
+  if ((int64_t)a.nsplit * Ia * R > part_elems) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, R, a.nsplit), block(256);
+  const int64_t n = Ia * R;
+  dim3 g2((unsigned)((n + 255) / 256));
+  if (hdt == NNCP_F64) {
+    hipLaunchKernelGGL(k_mttv_strided<double>, grid, block, 0, st, (const double *)T, a, (double *)part);
+    hipLaunchKernelGGL(k_sum_splits<double>, g2, dim3(256), 0, st, (const double *)part, n, a.nsplit, (double *)M);
+  } else {
+    hipLaunchKernelGGL(k_mttv_strided<float>, grid, block, 0, st, (const float *)T, a, (float *)part);
+    hipLaunchKernelGGL(k_sum_splits<float>, g2, dim3(256), 0, st, (const float *)part, n, a.nsplit, (float *)M);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(int hdt, const void *H, int64_t I, int R, double *G, hipStream_t st) {
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_gram<double>, dim3(1), dim3(1024), 0, st, (const double *)H, I, R, G);
+  else
+    hipLaunchKernelGGL(k_gram<float>, dim3(1), dim3(1024), 0, st, (const float *)H, I, R, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_hadamard(const double *G, int N, int R, int mode, double *S, hipStream_t st) {
+  hipLaunchKernelGGL(k_hadamard, dim3(1), dim3(256), 0, st, G, N, R, mode, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(int xdt, const void *X, int64_t n, double *part, double *out,
+                        hipStream_t st) {
+  const int nb = 1024;
+  dim3 grid(nb), block(256);
+  switch (xdt) {
+    case NNCP_F64: hipLaunchKernelGGL(k_sumsq_part<double>, grid, block, 0, st, (const double *)X, n, part); break;
+    case NNCP_F32: hipLaunchKernelGGL(k_sumsq_part<float>, grid, block, 0, st, (const float *)X, n, part); break;
+    case NNCP_BF16: hipLaunchKernelGGL(k_sumsq_part<bf16_t>, grid, block, 0, st, (const bf16_t *)X, n, part); break;
+    case NNCP_F16: hipLaunchKernelGGL(k_sumsq_part<f16_t>, grid, block, 0, st, (const f16_t *)X, n, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, part, nb, out);
+  return hipGetLastError();
+}
+
+template <typename HT>
+static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
+  dim3 grid(1), block(1024);
+  if (a.R <= 64) hipLaunchKernelGGL((k_update<HT, 1>), grid, block, 0, st, a);
+  else if (a.R <= 128) hipLaunchKernelGGL((k_update<HT, 2>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((k_update<HT, 4>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st) {
+  return hdt == NNCP_F64 ? update_dispatch<double>(a, st) : update_dispatch<float>(a, st);
+}
+
+hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const void *H,
+                       const double *lambda, const double *G, const double *alpha, double *loss,
+                       double *relerr, double *scal, hipStream_t st) {
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_loss<double>, dim3(1), dim3(1024), 0, st, N, R, In, (const double *)M,
+                       (const double *)H, lambda, G, alpha, loss, relerr, scal);
+  else
+    hipLaunchKernelGGL(k_loss<float>, dim3(1), dim3(1024), 0, st, N, R, In, (const float *)M,
+                       (const float *)H, lambda, G, alpha, loss, relerr, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M, const void *H,
+                       const double *G, const double *S, void *grad, hipStream_t st) {
+  const int64_t n = I * R;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (R > 64 && !S) return hipErrorInvalidValue;
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_grad<double>, grid, block, 0, st, I, R, N, mode, (const double *)M,
+                       (const double *)H, G, S, (double *)grad);
+  else
+    hipLaunchKernelGGL(k_grad<float>, grid, block, 0, st, I, R, N, mode, (const float *)M,
+                       (const float *)H, G, S, (float *)grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_pgd_eta(const double *G, int N, int R, int iters, double *eta, hipStream_t st) {
+  if (R > 64) return hipErrorInvalidValue;
+  const size_t sh = sizeof(double) * (R * R + 2 * R);
+  hipLaunchKernelGGL(k_pgd_eta, dim3(1), dim3(256), sh, st, G, N, R, iters, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_pgd_trial(int hdt, int64_t n, const void *H, const void *g, double eta, void *Hn,
+                            double *part, double *d_out, hipStream_t st) {
+  const int nb = 256;
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_pgd_trial<double>, dim3(nb), dim3(256), 0, st, n, (const double *)H,
+                       (const double *)g, eta, (double *)Hn, part);
+  else
+    hipLaunchKernelGGL(k_pgd_trial<float>, dim3(nb), dim3(256), 0, st, n, (const float *)H,
+                       (const float *)g, eta, (float *)Hn, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, part, nb, d_out);
+  return hipGetLastError();
+}
+
+}  // namespace nncp

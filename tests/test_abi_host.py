@@ -1,0 +1,93 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/nncp.h, and rejects invalid arguments before launching
+anything (these calls never reach the GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nncp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nncp_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1909_01149_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1909_01149_amd import build
+        build.build()
+    return binding
+
+
+def test_every_declared_symbol_is_exported(B):
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def test_binding_module_has_the_c_names(B):
+    import paper_1909_01149_amd as pkg
+    for n in _declared():
+        if n == "nncp_last_error":
+            continue
+        assert callable(getattr(pkg, n)), n
+
+
+def test_workspace_size_validation(B):
+    L = B.lib()
+    dims = (ctypes.c_int64 * 3)(8, 8, 8)
+    ok = L.nncp_workspace_size(3, dims, 4, B.NNCP_F32, B.NNCP_F32, None)
+    assert ok > 0
+    assert L.nncp_workspace_size(1, dims, 4, B.NNCP_F32, B.NNCP_F32, None) == 0
+    assert b"N = 1" in L.nncp_last_error()
+    assert L.nncp_workspace_size(3, dims, 0, B.NNCP_F32, B.NNCP_F32, None) == 0
+    assert L.nncp_workspace_size(3, dims, 4, B.NNCP_BF16, B.NNCP_BF16, None) == 0
+    assert b"unsupported" in L.nncp_last_error()
+    assert L.nncp_workspace_size(3, dims, 4, B.NNCP_F64, B.NNCP_F32, None) == 0
+    assert L.nncp_workspace_size(3, dims, 300, B.NNCP_F32, B.NNCP_F32, None) == 0
+    bad = (ctypes.c_int64 * 3)(8, 0, 8)
+    assert L.nncp_workspace_size(3, bad, 4, B.NNCP_F32, B.NNCP_F32, None) == 0
+    o = B.nncp_options(5, 1, 0, 1e-16)   # split outside [1, N-1]
+    assert L.nncp_workspace_size(3, dims, 4, B.NNCP_F32, B.NNCP_F32, ctypes.byref(o)) == 0
+
+
+def test_init_rejects_before_launch(B):
+    L = B.lib()
+    dims = (ctypes.c_int64 * 3)(8, 8, 8)
+    ctx = ctypes.c_void_p()
+    H = (ctypes.c_void_p * 3)(16, 32, 48)
+    # NULL X
+    rc = L.nncp_init(ctypes.byref(ctx), 3, dims, 4, B.NNCP_F32, None, B.NNCP_F32, H,
+                     ctypes.c_void_p(64), ctypes.c_void_p(256), 1 << 30, None, None)
+    assert rc == B.NNCP_E_INVAL
+    # bad dtype pair
+    rc = L.nncp_init(ctypes.byref(ctx), 3, dims, 4, B.NNCP_F16, ctypes.c_void_p(256), B.NNCP_F64, H,
+                     ctypes.c_void_p(64), ctypes.c_void_p(256), 1 << 30, None, None)
+    assert rc == B.NNCP_E_DTYPE
+    # misaligned X
+    rc = L.nncp_init(ctypes.byref(ctx), 3, dims, 4, B.NNCP_F32, ctypes.c_void_p(258), B.NNCP_F32, H,
+                     ctypes.c_void_p(64), ctypes.c_void_p(256), 1 << 30, None, None)
+    assert rc == B.NNCP_E_INVAL and b"aligned" in L.nncp_last_error()
+    # workspace too small
+    rc = L.nncp_init(ctypes.byref(ctx), 3, dims, 4, B.NNCP_F32, ctypes.c_void_p(256), B.NNCP_F32, H,
+                     ctypes.c_void_p(64), ctypes.c_void_p(256), 16, None, None)
+    assert rc == B.NNCP_E_WORKSPACE
+    assert not ctx.value
+
+
+def test_calls_on_null_context_fail(B):
+    L = B.lib()
+    assert L.nncp_mttkrp(None, 0, ctypes.c_void_p(16)) == B.NNCP_E_STATE
+    assert L.nncp_sweep(None, 0, 1, None) == B.NNCP_E_STATE
+    assert L.nncp_destroy(None) == B.NNCP_E_STATE
+    assert L.nncp_split(None) == B.NNCP_E_STATE
