@@ -49,8 +49,8 @@ struct Layout {
   GemmPlan gp[2];
   int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
   // byte offsets into the workspace
-  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_red, off_M, off_A, off_B,
-      off_part, off_kf, off_ks, off_pgdH, off_pgdG, total;
+  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_red, off_M, off_A,
+      off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, total;
 };
 
 nncp_options default_options() {
@@ -102,17 +102,27 @@ void plan_side(Layout &L, int side) {
   if (side == 0 && p.m % QV != 0) mfma = false;
   int64_t Pf = -1;
   int fhi = -1;
+  int64_t W = -1;
   if (mfma) {
+    // fast prefix: the shortest prefix of the reduced modes whose size is a
+    // multiple of the step and at least 64.  The right kernel stages all of
+    // it in LDS; the left kernel stages a window W that divides it.
     int64_t best = -1;
     int besthi = -1;
     for (int c = lo + 1; c <= hi; ++c) {
       const int64_t pf = prod(L.dims, lo, c);
       if (pf % KSTEP != 0) continue;
-      const size_t need = stage_bytes(p.Rpad, pf, es, p.hl);
-      if (need > kLdsMax) break;
+      if (side == 1 && stage_bytes(p.Rpad, pf, es, p.hl) > kLdsMax) break;
       best = pf;
       besthi = c;
       if (pf >= 64) break;
+    }
+    if (best >= 0) {
+      W = best;
+      if (side == 0)
+        while (stage_bytes(p.Rpad, W, es, p.hl) > kLdsMax && W % 2 == 0 && (W / 2) % KSTEP == 0)
+          W /= 2;
+      if (stage_bytes(p.Rpad, W, es, p.hl) > kLdsMax) best = -1;
     }
     if (best < 0) mfma = false;
     Pf = best;
@@ -121,15 +131,18 @@ void plan_side(Layout &L, int side) {
   p.mfma = mfma ? 1 : 0;
   if (mfma) {
     p.Pf = Pf;
+    p.W = W;
     p.Ps = red / Pf;
     p.fast_lo = lo; p.fast_hi = fhi; p.slow_lo = fhi; p.slow_hi = hi;
-    const size_t stage = stage_bytes(p.Rpad, Pf, es, p.hl);
+    const size_t stage = stage_bytes(p.Rpad, W, es, p.hl);
     if (side == 1) {
       const size_t redb = (size_t)3 * MT * p.NT * 4 * 64 * hs;
       p.lds_bytes = std::max(stage, redb);
       p.tiles = (p.k + 16 * MT - 1) / (16 * MT);
       const int64_t steps = p.m / KSTEP;
-      int64_t ns = (2048 + p.tiles - 1) / p.tiles;
+      // about two workgroups per CU in total: each one stages the Khatri-Rao
+      // operand once, so fewer, longer workgroups re-stage less per byte of X
+      int64_t ns = (512 + p.tiles - 1) / p.tiles;
       ns = std::min<int64_t>(ns, std::max<int64_t>(1, steps / 8));
       ns = std::min<int64_t>(ns, 4096);
       p.nsplit = (int)std::max<int64_t>(ns, 1);
@@ -137,13 +150,15 @@ void plan_side(Layout &L, int side) {
       p.lds_bytes = stage;
       p.tiles = (p.m + 64 * QV - 1) / (64 * QV);
       const int64_t steps = p.k / KSTEP;
-      int64_t ns = (1024 + p.tiles - 1) / p.tiles;
+      // no split (T written straight into the node) when the columns alone
+      // give enough workgroups; otherwise split the rows
+      int64_t ns = p.tiles >= 384 ? 1 : (768 + p.tiles - 1) / p.tiles;
       ns = std::min<int64_t>(ns, std::max<int64_t>(1, steps / 4));
       ns = std::min<int64_t>(ns, 4096);
       p.nsplit = (int)std::max<int64_t>(ns, 1);
     }
   } else {
-    p.Pf = red; p.Ps = 1;
+    p.Pf = red; p.Ps = 1; p.W = red;
     p.fast_lo = lo; p.fast_hi = hi; p.slow_lo = hi; p.slow_hi = hi;
     p.lds_bytes = 0;
     if (side == 1) {
@@ -229,6 +244,7 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_scal = take(sizeof(double) * 64);
   L.off_ones = take(sizeof(double) * R);
   L.off_hhat = take(sizeof(double) * L.maxI * R);
+  L.off_upart = take(sizeof(double) * update_part_elems(L.maxI, R));
   L.off_red = take(sizeof(double) * 1024);
   L.off_M = take(hs * L.maxI * R);
   L.off_A = take(hs * L.nodeA);
@@ -263,7 +279,7 @@ struct nncp_ctx {
   double *lambda;
   hipStream_t st;
   char *ws;
-  double *G, *Gt, *S, *scal, *ones, *hhat, *red;
+  double *G, *Gt, *S, *scal, *ones, *hhat, *upart, *red;
   void *M, *nodeA, *nodeB, *part, *kf, *ks;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
 };
@@ -415,6 +431,7 @@ int update_mode(nncp_ctx *c, int algo, int n, const void *M, const double *S, do
   a.H = c->H[n];
   a.lambda = c->lambda;
   a.hhat = c->hhat;
+  a.part = c->upart;
   a.eps = eps;
   a.alpha = c->scal + 8;
   a.relerr_out = relerr_out;
@@ -474,6 +491,7 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->scal = (double *)(c->ws + L.off_scal);
   c->ones = (double *)(c->ws + L.off_ones);
   c->hhat = (double *)(c->ws + L.off_hhat);
+  c->upart = (double *)(c->ws + L.off_upart);
   c->red = (double *)(c->ws + L.off_red);
   c->M = c->ws + L.off_M;
   c->nodeA = c->ws + L.off_A;

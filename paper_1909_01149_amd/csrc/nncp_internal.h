@@ -62,6 +62,7 @@ struct GemmPlan {
   int mfma;          // 1 = matrix-core kernel, 0 = vector-ALU kernel
   int64_t m, k;      // Xr is k x m
   int64_t Pf, Ps;    // fast / slow sizes of the reduced index (Pf * Ps = reduced length)
+  int64_t W;         // left kernel: fast indices staged in LDS at a time (W divides Pf)
   int NT;            // 16-column tiles (Rpad = 16 * NT)
   int Rpad;
   int hl;            // hi+lo Khatri-Rao operand
@@ -131,6 +132,7 @@ struct UpdateArgs {
   void *H;              // factor (hdt), in/out
   double *lambda;       // R, in/out
   double *hhat;         // I x R FP64 scratch
+  double *part;         // per-workgroup partials, update_part_elems(I, R) doubles
   double eps;
   // error after a sweep (mode N-1 only): alpha, out pointers (may be NULL)
   const double *alpha;
@@ -138,6 +140,7 @@ struct UpdateArgs {
   double *scal;         // [0]=beta [1]=gamma [2]=raw relerr^2
 };
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st);
+int64_t update_part_elems(int64_t I, int R);
 
 // loss of [[lambda; H]] from M^(N-1): loss = 0.5 (alpha - 2 beta + gamma)
 hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const void *H,

@@ -261,17 +261,34 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
     }
   };
 
+  // batches of U steps, the next batch's loads issued before the current
+  // batch is consumed (the last batch re-reads itself instead of running past
+  // the wave's range)
   int64_t t = w_lo;
-  for (; t + U <= w_hi; t += U) {
-    u32x4 va[U][MT];
+  const int64_t nb = (w_hi - w_lo) / U;
+  if (nb > 0) {
+    u32x4 cur[U][MT], nxt[U][MT];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        va[u][mt] = __builtin_nontemporal_load(
+        cur[u][mt] = __builtin_nontemporal_load(
             reinterpret_cast<const u32x4 *>(xp[mt] + (t + u) * KSTEP));
+    for (int64_t bI = 0; bI < nb; ++bI, t += U) {
+      const int64_t tn = bI + 1 < nb ? t + U : t;
 #pragma unroll
-    for (int u = 0; u < U; ++u) step(va[u], t + u);
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          nxt[u][mt] = __builtin_nontemporal_load(
+              reinterpret_cast<const u32x4 *>(xp[mt] + (tn + u) * KSTEP));
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(cur[u], t + u);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) cur[u][mt] = nxt[u][mt];
+    }
   }
   for (; t < w_hi; ++t) {
     u32x4 va[MT];
@@ -346,8 +363,8 @@ __device__ __forceinline__ uint32_t dw(const u32x2 &v, int i) { return v[i]; }
 template <typename XT, int QV, int NT, bool HL, bool SLOW>
 __global__ __launch_bounds__(256) void k_gemm_left_mfma(
     const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
-    const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int64_t steps_total, int nsplit,
-    int R, typename XTraits<XT>::AT *__restrict__ out) {
+    const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int W, int64_t steps_total,
+    int nsplit, int R, typename XTraits<XT>::AT *__restrict__ out) {
   typedef typename XTraits<XT>::AT AT;
   typedef typename CFrag<AT>::T CT;
   constexpr int KL = XTraits<XT>::KL;
@@ -358,21 +375,23 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
   extern __shared__ __align__(16) unsigned char smem[];
   XT *sk = reinterpret_cast<XT *>(smem);
   constexpr int SVEC = 16 / (int)sizeof(XT);
-  const int swz = ((Pf / SVEC) % 16 == 0) ? 15 : 0;
-  const int ldk = swz ? Pf : Pf + SVEC;
-
-  {
-    const int nv = Pf / SVEC;
+  // LDS holds a window of W fast indices (W divides Pf); every wave walks the
+  // same rows, so the window is re-staged between two barriers when the rows
+  // cross into the next window (once per workgroup when W == Pf)
+  const int swz = ((W / SVEC) % 16 == 0) ? 15 : 0;
+  const int ldk = swz ? W : W + SVEC;
+  auto stage = [&](int wbase) {
+    const int nv = W / SVEC;
     const int total = RP * nv * (HL ? 2 : 1);
     for (int e = threadIdx.x; e < total; e += 256) {
       const int h = e / (RP * nv);
       const int rem = e - h * RP * nv;
       const int r = rem / nv, v = rem - r * nv;
       *reinterpret_cast<u32x4 *>(sk + h * RP * ldk + kidx<XT>(r, v * SVEC, ldk, swz)) =
-          *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + v * SVEC);
+          *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + wbase + v * SVEC);
     }
-  }
-  __syncthreads();
+  };
+  int cur_w = -1;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rho = lane & 15, g = lane >> 4;
@@ -390,59 +409,87 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) { czero(acc[q][nt]); czero(blk[q][nt]); }
 
-  for (int64_t t = s_lo; t < s_hi; ++t) {
-    LT raw[KL];
+  // Steps are taken in batches of SB (SB * KL rows per lane: 8 loads), the
+  // next batch loaded before the current one is consumed.  Steps past the end
+  // of the range re-load the last valid step and are not computed.
+  constexpr int SB = KL == 8 ? 1 : 8;
+  LT raw[SB * KL], nxt[SB * KL];
+  auto load_batch = [&](LT *dst, int64_t t0) {
 #pragma unroll
-    for (int u = 0; u < KL; ++u)
-      raw[u] = __builtin_nontemporal_load(
-          reinterpret_cast<const LT *>(xp + (t * KSTEP + u) * m));
-    const int pf0 = (int)(t % spb) * KSTEP;
-    if constexpr (KL == 8) {
-      u32x4 vb[NT], vbl[NT];
+    for (int b = 0; b < SB; ++b) {
+      const int64_t tt = t0 + b < s_hi ? t0 + b : s_hi - 1;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const XT *bp = sk + kidx<XT>(16 * nt + rho, pf0 + g * KL, ldk, swz);
-        vb[nt] = *reinterpret_cast<const u32x4 *>(bp);
-        if (HL) vbl[nt] = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
+      for (int u = 0; u < KL; ++u)
+        dst[b * KL + u] = __builtin_nontemporal_load(
+            reinterpret_cast<const LT *>(xp + (tt * KSTEP + u) * m));
+    }
+  };
+  if (s_lo < s_hi) load_batch(raw, s_lo);
+  for (int64_t t0 = s_lo; t0 < s_hi; t0 += SB) {
+    load_batch(nxt, t0 + SB < s_hi ? t0 + SB : t0);
+#pragma unroll
+    for (int b = 0; b < SB; ++b) {
+      const int64_t t = t0 + b;
+      if (t >= s_hi) break;
+      const LT *rw = raw + b * KL;
+      const int pfa = (int)(t % spb) * KSTEP;
+      const int wi = pfa / W;
+      if (wi != cur_w) {
+        __syncthreads();
+        stage(wi * W);
+        __syncthreads();
+        cur_w = wi;
       }
-#pragma unroll
-      for (int q = 0; q < QV; ++q) {
-        const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
-        u32x4 a;
-        a.x = __builtin_amdgcn_perm(dw(raw[1], q >> 1), dw(raw[0], q >> 1), sel);
-        a.y = __builtin_amdgcn_perm(dw(raw[3], q >> 1), dw(raw[2], q >> 1), sel);
-        a.z = __builtin_amdgcn_perm(dw(raw[5], q >> 1), dw(raw[4], q >> 1), sel);
-        a.w = __builtin_amdgcn_perm(dw(raw[7], q >> 1), dw(raw[6], q >> 1), sel);
+      const int pf0 = pfa - wi * W;
+      if constexpr (KL == 8) {
+        u32x4 vb[NT], vbl[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          CT &c = SLOW ? blk[q][nt] : acc[q][nt];
-          mma16(c, a, vb[nt], (XT *)nullptr);
-          if (HL) mma16(c, a, vbl[nt], (XT *)nullptr);
+          const XT *bp = sk + kidx<XT>(16 * nt + rho, pf0 + g * KL, ldk, swz);
+          vb[nt] = *reinterpret_cast<const u32x4 *>(bp);
+          if (HL) vbl[nt] = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
         }
-      }
-    } else {
-      AT b[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[nt] = (AT)sk[kidx<XT>(16 * nt + rho, pf0 + g, ldk, swz)];
-      const AT *xv = reinterpret_cast<const AT *>(&raw[0]);
-#pragma unroll
-      for (int q = 0; q < QV; ++q)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) mma1(SLOW ? blk[q][nt] : acc[q][nt], xv[q], b[nt]);
-    }
-    if (SLOW && ((t + 1) % spb == 0 || t + 1 == s_hi)) {
-      const int64_t bI = t / spb;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const AT s = kslow[bI * RP + 16 * nt + rho];
 #pragma unroll
         for (int q = 0; q < QV; ++q) {
+          const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
+          u32x4 a;
+          a.x = __builtin_amdgcn_perm(dw(rw[1], q >> 1), dw(rw[0], q >> 1), sel);
+          a.y = __builtin_amdgcn_perm(dw(rw[3], q >> 1), dw(rw[2], q >> 1), sel);
+          a.z = __builtin_amdgcn_perm(dw(rw[5], q >> 1), dw(rw[4], q >> 1), sel);
+          a.w = __builtin_amdgcn_perm(dw(rw[7], q >> 1), dw(rw[6], q >> 1), sel);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[q][nt][v] += blk[q][nt][v] * s;
-          czero(blk[q][nt]);
+          for (int nt = 0; nt < NT; ++nt) {
+            CT &c = SLOW ? blk[q][nt] : acc[q][nt];
+            mma16(c, a, vb[nt], (XT *)nullptr);
+            if (HL) mma16(c, a, vbl[nt], (XT *)nullptr);
+          }
+        }
+      } else {
+        AT bb[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bb[nt] = (AT)sk[kidx<XT>(16 * nt + rho, pf0 + g, ldk, swz)];
+        const AT *xv = reinterpret_cast<const AT *>(rw);
+#pragma unroll
+        for (int q = 0; q < QV; ++q)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) mma1(SLOW ? blk[q][nt] : acc[q][nt], xv[q], bb[nt]);
+      }
+      if (SLOW && ((t + 1) % spb == 0 || t + 1 == s_hi)) {
+        const int64_t bI = t / spb;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const AT sc = kslow[bI * RP + 16 * nt + rho];
+#pragma unroll
+          for (int q = 0; q < QV; ++q) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[q][nt][v] += blk[q][nt][v] * sc;
+            czero(blk[q][nt]);
+          }
         }
       }
     }
+#pragma unroll
+    for (int u = 0; u < SB * KL; ++u) raw[u] = nxt[u];
   }
 
   AT *o = out + (int64_t)blockIdx.y * R * m;
@@ -626,7 +673,7 @@ static void run_left(const GemmPlan &p, int R, const void *X, const void *kf, co
   constexpr int KSTEP = 4 * XTraits<XT>::KL;
   dim3 grid((unsigned)p.tiles, p.nsplit), block(256);
   hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW>), grid, block, p.lds_bytes, st,
-                     (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf,
+                     (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf, (int)p.W,
                      (p.k / KSTEP), p.nsplit, R, (AT *)out);
 }
 

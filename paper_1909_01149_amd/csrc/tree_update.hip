@@ -50,6 +50,40 @@ __global__ __launch_bounds__(256) void k_mttv_contig(const HT *__restrict__ T, i
   }
 }
 
+// Same reduction for 64 <= Ia <= 8192 with Ia % 4 == 0: a workgroup owns one
+// column r (H(:, r) staged in LDS once) and a range of q; one wave per output,
+// lanes stream T[r][Ia q ..] with 16-byte loads.
+template <typename HT>
+__global__ __launch_bounds__(256) void k_mttv_contig_wide(const HT *__restrict__ T, int64_t Ia,
+                                                          int64_t Q, int R, const HT *__restrict__ H,
+                                                          HT *__restrict__ out, int leaf,
+                                                          int64_t qper) {
+  __shared__ HT hs[8192];
+  constexpr int V = 16 / (int)sizeof(HT);
+  typedef HT vt __attribute__((ext_vector_type(V)));
+  const int r = blockIdx.x;
+  for (int64_t i = threadIdx.x; i < Ia; i += 256) hs[i] = H[i * R + r];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q0 = (int64_t)blockIdx.y * qper;
+  const int64_t q1 = q0 + qper < Q ? q0 + qper : Q;
+  const HT *Tr = T + (int64_t)r * Ia * Q;
+  for (int64_t q = q0 + wave; q < q1; q += 4) {
+    const vt *t = reinterpret_cast<const vt *>(Tr + Ia * q);
+    HT acc = 0;
+    for (int64_t c = lane; c < Ia / V; c += 64) {
+      const vt x = t[c];
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc += x[e] * hs[c * V + e];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      if (leaf) out[q * R + r] = acc;
+      else out[(int64_t)r * Q + q] = acc;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // multi-TTV, strided reduction keeping the first mode:
 //   part[z][i][r] = sum_{q in split z} T[r][i + Ia q] K(q, r),
@@ -68,24 +102,33 @@ template <typename HT>
 __global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, StridedArgs a,
                                                       HT *__restrict__ part) {
   __shared__ HT red[256];
+  __shared__ HT kq[1024];
   const int il = threadIdx.x % a.IT, qs = threadIdx.x / a.IT;
   const int64_t i = (int64_t)blockIdx.x * a.IT + il;
   const int r = blockIdx.y;
   const int64_t z = blockIdx.z;
   const int64_t q0 = a.Q * z / a.nsplit, q1 = a.Q * (z + 1) / a.nsplit;
+  const HT *const *H = (const HT *const *)a.H;
+  const HT *t = T + (int64_t)r * a.Ia * a.Q + (i < a.Ia ? i : 0);
   HT acc = 0;
-  if (i < a.Ia) {
-    const HT *t = T + (int64_t)r * a.Ia * a.Q + i;
-    const HT *const *H = (const HT *const *)a.H;
-    for (int64_t q = q0 + qs; q < q1; q += a.QS) {
+  for (int64_t c0 = q0; c0 < q1; c0 += 1024) {
+    const int cn = (int)(q1 - c0 < 1024 ? q1 - c0 : 1024);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cn; e += 256) {
       HT kv = 1;
-      int64_t rem = q;
+      int64_t rem = c0 + e;
       for (int n = 0; n < a.nq; ++n) {
         const int64_t d = rem % a.qd[n];
         rem /= a.qd[n];
         kv *= H[n][d * a.R + r];
       }
-      acc += t[a.Ia * q] * kv;
+      kq[e] = kv;
+    }
+    __syncthreads();
+    if (i < a.Ia) {
+      int e = qs;
+#pragma unroll 4
+      for (; e < cn; e += a.QS) acc += t[a.Ia * (c0 + e)] * kq[e];
     }
   }
   red[threadIdx.x] = acc;
@@ -108,31 +151,41 @@ __global__ __launch_bounds__(256) void k_sum_splits(const HT *__restrict__ part,
 }
 
 // ---------------------------------------------------------------------------
-// Gram G = H^T H, FP64, one workgroup of 1024 threads: thread (pair p, slice s)
-// sums rows i = s (mod ns); slices are added in order through LDS.
+// Gram G = H^T H, FP64, one workgroup of 1024 threads.  Rows are staged in LDS
+// in chunks of CH rows (coalesced loads, converted to FP64 once); thread
+// (pair p, slice s) accumulates the chunk rows i = s (mod ns) from LDS; the
+// slices are added in order at the end.
 // ---------------------------------------------------------------------------
 template <typename HT>
 __device__ void gram_block(const HT *__restrict__ H, int64_t I, int R, double *__restrict__ G,
-                           double *lds /* >= 1024 doubles */) {
+                           double *lds /* >= 1024 doubles */, double *chunk /* >= 4096 doubles */) {
   const int npairs = R * (R + 1) / 2;
   int ns = 1;
   while (ns * 2 * npairs <= 1024) ns *= 2;
-  for (int base = 0; base < npairs; base += 1024 / ns) {
+  const int per_round = 1024 / ns;
+  const int CH = 4096 / R;  // rows per LDS chunk
+  for (int base = 0; base < npairs; base += per_round) {
     const int pl = threadIdx.x / ns, s = threadIdx.x % ns;
     const int p = base + pl;
-    double acc = 0.0;
+    const bool live = pl < per_round && p < npairs;
     int a = 0, b = 0;
-    if (pl < 1024 / ns && p < npairs) {
-      // pair index -> (a, b), a <= b
+    if (live) {
       int rem = p;
-      a = 0;
       while (rem >= R - a) { rem -= R - a; ++a; }
       b = a + rem;
-      for (int64_t i = s; i < I; i += ns) acc += (double)H[i * R + a] * (double)H[i * R + b];
+    }
+    double acc = 0.0;
+    for (int64_t i0 = 0; i0 < I; i0 += CH) {
+      const int rows = (int)(I - i0 < CH ? I - i0 : CH);
+      __syncthreads();
+      for (int e = threadIdx.x; e < rows * R; e += 1024) chunk[e] = (double)H[i0 * R + e];
+      __syncthreads();
+      if (live)
+        for (int i = s; i < rows; i += ns) acc += chunk[i * R + a] * chunk[i * R + b];
     }
     lds[threadIdx.x] = acc;
     __syncthreads();
-    if (s == 0 && pl < 1024 / ns && p < npairs) {
+    if (s == 0 && live) {
       double v = lds[threadIdx.x];
       for (int k = 1; k < ns; ++k) v += lds[threadIdx.x + k];
       G[a * R + b] = v;
@@ -146,7 +199,8 @@ template <typename HT>
 __global__ __launch_bounds__(1024) void k_gram(const HT *__restrict__ H, int64_t I, int R,
                                                double *__restrict__ G) {
   __shared__ double lds[1024];
-  gram_block<HT>(H, I, R, G, lds);
+  __shared__ double chunk[4096];
+  gram_block<HT>(H, I, R, G, lds, chunk);
 }
 
 __global__ __launch_bounds__(256) void k_hadamard(const double *__restrict__ G, int N, int R,
@@ -196,27 +250,40 @@ __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
-// per-mode update: one workgroup of 1024 threads
-//   Hhat = H diag(lambda);  MU or HALS on Hhat;  lambda = column norms;
-//   H = Hhat / lambda;  G^(mode) = H^T H;  and after the last mode
-//   beta = <M, Hhat>, gamma = lambda^T (S * G) lambda,
-//   relerr = sqrt(max(0, alpha - 2 beta + gamma) / alpha).
+// per-mode update, in two launches:
+//   k_update_rows    (one workgroup per 4*rpw rows): Hhat = H diag(lambda);
+//                    MU or HALS on each row; Hhat (FP64) stored; per-workgroup
+//                    column sums of squares and <M, Hhat> partials
+//   k_update_finish  (one workgroup): lambda = column norms (partials added in
+//                    workgroup order); H = Hhat / lambda; G^(mode) = H^T H;
+//                    after the last mode beta, gamma and the relative error.
 // A row of Hhat is held by LPR lanes (LPR = power of two >= R, at most 64),
 // lane `sub` owning columns sub + LPR u, u < CPL.  HALS keeps the residual
 // g = M - Hhat S of the row and, column by column in order, broadcasts the
 // change of column r from its owner lane and updates g; this is the same
 // arithmetic as forming (Hhat S)(:, r) afresh from the latest Hhat.
 // ---------------------------------------------------------------------------
+int update_rows_per_block(int R) { (void)R; return 4; }
+
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One row per wave: lane c owns columns c + 64 u (u < CPL).
 template <typename HT, int CPL>
-__global__ __launch_bounds__(1024) void k_update(UpdateArgs a) {
+__global__ __launch_bounds__(256) void k_update_rows(UpdateArgs a) {
   __shared__ double sS[64 * 64];
-  __shared__ double wred[16][64];
   __shared__ double lam_s[256];
-  __shared__ double lds[1024];
+  __shared__ double hrow[4][256];
+  __shared__ double wred[4][256];
+  __shared__ double bred[4];
   const int R = a.R;
   const bool s_in_lds = R <= 64;
   if (s_in_lds) {
-    for (int e = threadIdx.x; e < R * R; e += 1024) {
+    for (int e = threadIdx.x; e < R * R; e += 256) {
       double s;
       if (a.S) s = a.S[e];
       else {
@@ -227,136 +294,124 @@ __global__ __launch_bounds__(1024) void k_update(UpdateArgs a) {
       sS[e] = s;
     }
   }
-  for (int c = threadIdx.x; c < R; c += 1024) lam_s[c] = a.lambda[c];
+  for (int c = threadIdx.x; c < R; c += 256) lam_s[c] = a.lambda[c];
   __syncthreads();
   const double *Sg = a.S;
   auto Sv = [&](int c, int r) -> double { return s_in_lds ? sS[c * R + r] : Sg[c * R + r]; };
 
-  int LPR = 64;
-  if (CPL == 1) { LPR = 1; while (LPR < R) LPR *= 2; }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rpw = 64 / LPR;
-  const int sub = lane % LPR, grp = lane / LPR, base = grp * LPR;
   const HT *M = (const HT *)a.M;
-  HT *H = (HT *)a.H;
-
-  double colsq[CPL], beta = 0.0;
+  const HT *H = (const HT *)a.H;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  const bool live = i < a.I;
+  double h[CPL], m[CPL], g[CPL];
 #pragma unroll
-  for (int u = 0; u < CPL; ++u) colsq[u] = 0.0;
-
-  for (int64_t i0 = 0; i0 < a.I; i0 += 16 * rpw) {
-    const int64_t i = i0 + wave * rpw + grp;
-    const bool live = i < a.I;
-    double h[CPL], m[CPL], g[CPL];
+  for (int u = 0; u < CPL; ++u) {
+    const int c = lane + 64 * u;
+    const bool ok = live && c < R;
+    h[u] = ok ? (double)H[i * R + c] * lam_s[c] : 0.0;
+    m[u] = ok ? (double)M[i * R + c] : 0.0;
+    if (c < R) hrow[wave][c] = h[u];
+  }
+  // g = (Hhat S)(i, :) from the row in LDS (independent reads, no chain)
 #pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int c = sub + LPR * u;
-      const bool ok = live && c < R;
-      h[u] = ok ? (double)H[i * R + c] * lam_s[c] : 0.0;
-      m[u] = ok ? (double)M[i * R + c] : 0.0;
-      g[u] = 0.0;
-    }
-    // g = (Hhat S)(i, :) for the lane's columns
-    for (int j = 0; j < R; ++j) {
-      const int uj = j / LPR;
-      double src = h[0];
+  for (int u = 0; u < CPL; ++u) {
+    const int c = lane + 64 * u;
+    double acc = 0.0;
+    if (c < R)
+      for (int j = 0; j < R; ++j) acc += hrow[wave][j] * Sv(j, c);
+    g[u] = acc;
+  }
+  if (a.algo == NNCP_MU) {
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) h[u] = h[u] * m[u] / (g[u] + a.eps);
+  } else {
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) g[u] = m[u] - g[u];
+    for (int r = 0; r < R; ++r) {
+      const double d = Sv(r, r);
+      if (!(d > 0.0)) continue;
+      const int ur = r >> 6, owner = r & 63;
+      double hs = h[0], gs = g[0];
 #pragma unroll
       for (int u = 1; u < CPL; ++u)
-        if (uj == u) src = h[u];
-      const double hj = __shfl(src, base + (j % LPR), 64);
+        if (ur == u) { hs = h[u]; gs = g[u]; }
+      const double hr = bcast(hs, owner), gr = bcast(gs, owner);
+      double v = hr + gr / d;
+      v = v > 0.0 ? v : 0.0;
+      const double delta = v - hr;
 #pragma unroll
       for (int u = 0; u < CPL; ++u) {
-        const int c = sub + LPR * u;
-        if (c < R) g[u] += hj * Sv(j, c);
-      }
-    }
-    if (a.algo == NNCP_MU) {
-#pragma unroll
-      for (int u = 0; u < CPL; ++u) h[u] = h[u] * m[u] / (g[u] + a.eps);
-    } else {
-#pragma unroll
-      for (int u = 0; u < CPL; ++u) g[u] = m[u] - g[u];
-      for (int r = 0; r < R; ++r) {
-        const double d = Sv(r, r);
-        if (!(d > 0.0)) continue;
-        const int ur = r / LPR, owner = base + (r % LPR);
-        double hs = h[0], gs = g[0];
-#pragma unroll
-        for (int u = 1; u < CPL; ++u)
-          if (ur == u) { hs = h[u]; gs = g[u]; }
-        const double hr = __shfl(hs, owner, 64), gr = __shfl(gs, owner, 64);
-        double v = hr + gr / d;
-        v = v > 0.0 ? v : 0.0;
-        const double delta = v - hr;
-#pragma unroll
-        for (int u = 0; u < CPL; ++u) {
-          const int c = sub + LPR * u;
-          if (c < R) g[u] -= delta * Sv(r, c);
-          if (u == ur && sub == (r % LPR)) h[u] = v;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int c = sub + LPR * u;
-      if (live && c < R) {
-        a.hhat[i * R + c] = h[u];
-        colsq[u] += h[u] * h[u];
-        beta += m[u] * h[u];
+        const int c = lane + 64 * u;
+        if (c < R) g[u] -= delta * Sv(r, c);
+        if (u == ur && lane == owner) h[u] = v;
       }
     }
   }
-  // column sums of squares: across the row groups of a wave, then waves in order
+  double beta = 0.0;
 #pragma unroll
   for (int u = 0; u < CPL; ++u) {
-    for (int off = LPR; off < 64; off *= 2) colsq[u] += __shfl_xor(colsq[u], off, 64);
-  }
-  for (int u = 0; u < CPL; ++u) {
-    if (grp == 0) wred[wave][sub] = colsq[u];
-    __syncthreads();
-    if (threadIdx.x < LPR) {
-      const int c = threadIdx.x + LPR * u;
-      double s = 0.0;
-      for (int w = 0; w < 16; ++w) s += wred[w][threadIdx.x];
-      if (c < R) lam_s[c] = sqrt(s);
+    const int c = lane + 64 * u;
+    double sq = 0.0;
+    if (live && c < R) {
+      a.hhat[i * R + c] = h[u];
+      sq = h[u] * h[u];
+      beta += m[u] * h[u];
     }
-    __syncthreads();
+    if (c < R) wred[wave][c] = sq;
   }
-  {
-    const double v = wave_sum(beta);
-    if (lane == 0) wred[wave][0] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < 16; ++w) s += wred[w][0];
-      beta = s;
-    }
-    __syncthreads();
+  beta = wave_sum(beta);
+  if (lane == 0) bred[wave] = beta;
+  __syncthreads();
+  // per-workgroup partials (the 4 rows added in wave order)
+  double *cpart = a.part + (int64_t)blockIdx.x * (R + 1);
+  for (int c = threadIdx.x; c < R; c += 256)
+    cpart[c] = wred[0][c] + wred[1][c] + wred[2][c] + wred[3][c];
+  if (threadIdx.x == 0) cpart[R] = bred[0] + bred[1] + bred[2] + bred[3];
+}
+
+template <typename HT>
+__global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblocks) {
+  __shared__ double wred[16][2];
+  __shared__ double lam_s[256];
+  __shared__ double lds[1024];
+  __shared__ double chunk[4096];
+  __shared__ double beta_s;
+  const int R = a.R;
+  for (int c = threadIdx.x; c < R; c += 1024) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += a.part[(int64_t)b * (R + 1) + c];
+    lam_s[c] = sqrt(s);
   }
-  // normalise (each lane re-reads the Hhat entries it wrote)
-  for (int64_t i0 = 0; i0 < a.I; i0 += 16 * rpw) {
-    const int64_t i = i0 + wave * rpw + grp;
-    if (i >= a.I) continue;
-#pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int c = sub + LPR * u;
-      if (c < R) {
-        const double l = lam_s[c];
-        H[i * R + c] = (HT)(l > 0.0 ? a.hhat[i * R + c] / l : 0.0);
-      }
-    }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += a.part[(int64_t)b * (R + 1) + R];
+    beta_s = s;
+  }
+  __syncthreads();
+  HT *H = (HT *)a.H;
+  for (int64_t e = threadIdx.x; e < a.I * R; e += 1024) {
+    const double l = lam_s[e % R];
+    H[e] = (HT)(l > 0.0 ? a.hhat[e] / l : 0.0);
   }
   for (int c = threadIdx.x; c < R; c += 1024) a.lambda[c] = lam_s[c];
   __syncthreads();
   double *Gm = a.G + (int64_t)a.mode * R * R;
-  gram_block<HT>(H, a.I, R, Gm, lds);
+  gram_block<HT>(H, a.I, R, Gm, lds, chunk);
   __syncthreads();
   if (a.relerr_out || a.scal) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double gsum = 0.0;
-    for (int r = threadIdx.x; r < R; r += 1024) {
-      double s = 0.0;
-      for (int c = 0; c < R; ++c) s += lam_s[c] * Sv(r, c) * Gm[r * R + c];
-      gsum += lam_s[r] * s;
+    for (int e = threadIdx.x; e < R * R; e += 1024) {
+      const int r = e / R, c = e % R;
+      double s;
+      if (a.S) s = a.S[e];
+      else {
+        s = 1.0;
+        for (int k = 0; k < a.N; ++k)
+          if (k != a.mode) s *= a.G[(int64_t)k * R * R + e];
+      }
+      gsum += lam_s[r] * s * Gm[e] * lam_s[c];
     }
     const double v = wave_sum(gsum);
     if (lane == 0) wred[wave][1] = v;
@@ -364,6 +419,7 @@ __global__ __launch_bounds__(1024) void k_update(UpdateArgs a) {
     if (threadIdx.x == 0) {
       double gamma = 0.0;
       for (int w = 0; w < 16; ++w) gamma += wred[w][1];
+      const double beta = beta_s;
       const double alpha = a.alpha ? a.alpha[0] : 0.0;
       const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
       if (a.scal) {
@@ -531,6 +587,21 @@ __global__ __launch_bounds__(256) void k_pgd_trial(int64_t n, const HT *__restri
 
 hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R, const void *H,
                               void *out, int leaf, hipStream_t st) {
+  const int V = hdt == NNCP_F64 ? 2 : 4;
+  if (Ia >= 64 && Ia <= 8192 && Ia % V == 0 && (hdt != NNCP_F64 || Ia <= 4096)) {
+    // about 2048 workgroups, at least 4 outputs (one per wave) each
+    int64_t qper = (Q * R + 2047) / 2048;
+    if (qper < 4) qper = 4;
+    const int64_t gy = (Q + qper - 1) / qper;
+    dim3 grid((unsigned)R, (unsigned)gy), block(256);
+    if (hdt == NNCP_F64)
+      hipLaunchKernelGGL(k_mttv_contig_wide<double>, grid, block, 0, st, (const double *)T, Ia, Q,
+                         R, (const double *)H, (double *)out, leaf, qper);
+    else
+      hipLaunchKernelGGL(k_mttv_contig_wide<float>, grid, block, 0, st, (const float *)T, Ia, Q,
+                         R, (const float *)H, (float *)out, leaf, qper);
+    return hipGetLastError();
+  }
   int G = 1;
   while (G < 64 && G < Ia) G *= 2;
   const int64_t threads = Q * R * G;
@@ -549,7 +620,7 @@ static void strided_shape(int64_t Ia, int64_t Q, int R, int &IT, int &QS, int &n
   while (IT < 256 && IT < Ia) IT *= 2;
   QS = 256 / IT;
   gx = (Ia + IT - 1) / IT;
-  int64_t want = (2048 + gx * R - 1) / (gx * R);
+  int64_t want = (512 + gx * R - 1) / (gx * R);
   int64_t maxs = (Q + QS - 1) / QS;
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
@@ -623,15 +694,23 @@ hipError_t launch_sumsq(int xdt, const void *X, int64_t n, double *part, double 
 
 template <typename HT>
 static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
-  dim3 grid(1), block(1024);
-  if (a.R <= 64) hipLaunchKernelGGL((k_update<HT, 1>), grid, block, 0, st, a);
-  else if (a.R <= 128) hipLaunchKernelGGL((k_update<HT, 2>), grid, block, 0, st, a);
-  else hipLaunchKernelGGL((k_update<HT, 4>), grid, block, 0, st, a);
+  const int rpb = update_rows_per_block(a.R);
+  const int nb = (int)((a.I + rpb - 1) / rpb);
+  dim3 grid(nb), block(256);
+  if (a.R <= 64) hipLaunchKernelGGL((k_update_rows<HT, 1>), grid, block, 0, st, a);
+  else if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((k_update_finish<HT>), dim3(1), dim3(1024), 0, st, a, nb);
   return hipGetLastError();
 }
 
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st) {
   return hdt == NNCP_F64 ? update_dispatch<double>(a, st) : update_dispatch<float>(a, st);
+}
+
+int64_t update_part_elems(int64_t I, int R) {
+  const int rpb = update_rows_per_block(R);
+  return ((I + rpb - 1) / rpb) * (int64_t)(R + 1);
 }
 
 hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const void *H,
