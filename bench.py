@@ -10,7 +10,10 @@ factors, for two forms of the same problem on the same GPU:
   fp32  FP32 tensor, FP32 matrix-core partial MTTKRP
   bf16  the tensor rounded once to BF16, BF16 matrix-core partial MTTKRP with
         FP32 accumulation (the reported `value`)
-Inputs are resident in HBM before timing starts.  Prints one JSON line.
+Inputs are resident in HBM before timing starts.  The reported rate times the
+sweeps replayed as one HIP graph; per-kernel times (for the roofline) come
+from HIP events around every launch in a second timed pass of the same
+sweeps with plain launches.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -61,7 +64,9 @@ def read_traffic(kernel: str):
 
 
 def run_form(nn, torch, X, H0, steps, warmup, algo):
-    """Warm up, reset to the start factors, then time `steps` sweeps."""
+    """Warm up; time `steps` sweeps from the start factors replayed as a HIP
+    graph (the reported rate); then time the same sweeps again with plain
+    launches and per-launch HIP events (the per-kernel times)."""
     dev = X.device
     H = [h.clone() for h in H0]
     lam = torch.ones(H0[0].shape[1], dtype=torch.float64, device=dev)
@@ -69,25 +74,42 @@ def run_form(nn, torch, X, H0, steps, warmup, algo):
     if warmup > 0:
         ctx.sweep(algo, warmup)
     torch.cuda.synchronize()
-    for f, h0 in zip(ctx.factors, H0):
-        f.copy_(h0)
-    ctx.lam.fill_(1.0)
-    ctx.set_factors(ctx.factors, ctx.lam)
-    rel = torch.empty(max(1, steps), dtype=torch.float64, device=dev)
-    ctx.timers_enable(True)
+
+    def reset():
+        for f, h0 in zip(ctx.factors, H0):
+            f.copy_(h0)
+        ctx.lam.fill_(1.0)
+        ctx.refresh_grams()
+        torch.cuda.synchronize()
+
+    n = max(1, steps)
+    rel = torch.empty(n, dtype=torch.float64, device=dev)
+    reset()
+    ctx.capture(algo, n, rel)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
-    ctx.sweep(algo, steps, rel)
+    ctx.sweep(algo, n, rel)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    # same sweeps, plain launches with per-launch events
+    rel2 = torch.empty(n, dtype=torch.float64, device=dev)
+    reset()
+    ctx.timers_enable(True)
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    ctx.sweep(algo, n, rel2)
+    f1.record()
+    torch.cuda.synchronize()
+    ms_eager = f0.elapsed_time(f1)
     cat_ms, cat_n = ctx.timers_read()
     ctx.timers_enable(False)
-    return ctx, dict(ms=ms, wall_s=wall, relerr=rel.cpu().tolist()[:steps], cat_ms=cat_ms,
-                     cat_n=cat_n)
+    same = bool(torch.equal(rel, rel2))
+    return ctx, dict(ms=ms, wall_s=wall, ms_eager_timed=ms_eager, relerr=rel.cpu().tolist()[:steps],
+                     graph_equals_eager=same, cat_ms=cat_ms, cat_n=cat_n)
 
 
 def gemm_bytes(dims, R, xbytes, side):
@@ -115,7 +137,101 @@ def cpu_baseline(X32, H0, algo_oracle, nthreads):
                        f"tensor in FP64, {dt:.2f} s on {nthreads} host threads")
 
 
+# ---------------------------------------------------------------------------
+# counter summaries for profiles/ (run on the CSVs that rocprofv3 wrote)
+# ---------------------------------------------------------------------------
+
+COPY_PROBE_BYTES = 1 << 28
+KERNEL_PATTERNS = {
+    # (kernel file name, substring tests on the demangled / mangled name)
+    "bf16_gemm_right": lambda n: "k_gemm_right_mfma" in n and not any(
+        t in n for t in ("<float", "<double", "_Float16", "DF16_")),
+    "bf16_gemm_left": lambda n: "k_gemm_left_mfma" in n and ("DF16b" in n or "__bf16" in n),
+    "fp32_gemm_right": lambda n: "k_gemm_right_mfma<float" in n,
+    "fp32_gemm_left": lambda n: "k_gemm_left_mfma<float" in n,
+}
+
+
+def _read_counter_csv(path, counter):
+    import csv
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    return {int(r["Dispatch_Id"]): (r["Kernel_Name"], float(r["Counter_Value"])) for r in rows}
+
+
+def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write):
+    """Write profiles/traffic_<kernel>.txt: HBM bytes per launch from FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for
+    the --copy-probe device copy of COPY_PROBE_BYTES (found as the copy dispatch
+    that writes exactly that many bytes; the two runs dispatch the same kernels
+    in the same order, so dispatch ids match)."""
+    import statistics
+    fe = _read_counter_csv(fetch_csv, "FETCH_SIZE")
+    wr = _read_counter_csv(write_csv, "WRITE_SIZE")
+    probe = [d for d, (n, v) in wr.items() if "copyBuffer" in n and abs(v * 1024 - COPY_PROBE_BYTES) < 1]
+    if len(probe) != 1:
+        raise SystemExit(f"copy probe dispatch not found uniquely: {probe}")
+    d0 = probe[0]
+    f_read = COPY_PROBE_BYTES / (fe[d0][1] * 1024)
+    f_write = COPY_PROBE_BYTES / (wr[d0][1] * 1024)
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    for kname, test in KERNEL_PATTERNS.items():
+        ids = [d for d, (n, _) in fe.items() if test(n) and d in wr]
+        if not ids:
+            continue
+        fkib = statistics.mean(fe[d][1] for d in ids)
+        wkib = statistics.mean(wr[d][1] for d in ids)
+        hbm = (fkib * f_read + wkib * f_write) * 1024
+        with open(os.path.join(ROOT, "profiles", f"traffic_{kname}.txt"), "w") as fh:
+            fh.write(f"# HBM traffic per launch of the {kname.replace('_', ' ')} partial MTTKRP kernel\n")
+            fh.write("# workload: 512x512x512, R=32, HALS (bench.py default workload)\n")
+            fh.write(f"# fetch run: {cmd_fetch}\n# write run: {cmd_write}\n")
+            fh.write(f"# summarised with: python bench.py --summarize-counters <fetch csv> <write csv>\n")
+            fh.write(f"# calibration: the --copy-probe device copy of {COPY_PROBE_BYTES} bytes reads "
+                     f"{fe[d0][1]:.1f} KiB FETCH_SIZE and {wr[d0][1]:.1f} KiB WRITE_SIZE\n")
+            fh.write(f"dispatches = {len(ids)}\n")
+            fh.write(f"fetch_kib_per_dispatch = {fkib:.1f}\nwrite_kib_per_dispatch = {wkib:.1f}\n")
+            fh.write(f"read_scale = {f_read:.5f}\nwrite_scale = {f_write:.5f}\n")
+            fh.write(f"hbm_bytes_per_launch = {hbm:.0f}\n")
+            fh.write(f"kernel_source_sha = {source_sha()}\n")
+        print(f"{kname}: {len(ids)} dispatches, {hbm / 2**20:.1f} MiB per launch")
+
+
+def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt"):
+    """Write profiles/<out_name>: the library's kernels from a rocprofv3
+    --kernel-trace --stats run (calls, average and total duration)."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# rocprofv3 kernel statistics, 512x512x512 R=32 HALS workload (FP32 and BF16 forms)",
+             f"# command: {cmd}",
+             f"# summarised with: python bench.py --summarize-trace <kernel_stats.csv>",
+             f"# kernel_source_sha = {source_sha()}",
+             f"{'calls':>6} {'avg_us':>9} {'total_us':>10}  kernel"]
+    for r in rows:
+        name = r["Name"]
+        if "nncp" not in name:
+            continue
+        short = name.replace("nncp::", "").split("(")[0]
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e3:10.1f}  {short}")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
+        summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "
+                        "gpurun_out/prof -o bench -- python3 bench.py --steps 10 --warmup 2 "
+                        "--no-cpu-baseline")
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        fetch_csv, write_csv = sys.argv[2], sys.argv[3]
+        cmd_f = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
+                 "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe")
+        cmd_w = cmd_f.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_fetch", "pmc_write").replace("-o f", "-o w")
+        summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -142,7 +258,7 @@ def main():
     torch.cuda.synchronize()
 
     if args.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        src = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
@@ -221,10 +337,13 @@ def main():
                    "tensor_dtype": "bf16", "accumulate": "fp32", "factors": "fp32",
                    "krp_operand": "bf16 hi+lo", "parallelism": "single GPU"},
         "fp32_form": {"sweeps_per_s": sweeps_fp32, "ms_per_step": f["ms"] / steps,
-                      "final_relerr": f["relerr"][-1] if f["relerr"] else None},
+                      "final_relerr": f["relerr"][-1] if f["relerr"] else None,
+                      "ms_per_step_eager_timed": f["ms_eager_timed"] / steps},
         "bf16_form": {"sweeps_per_s": sweeps_bf16,
                       "final_relerr": b["relerr"][-1] if b["relerr"] else None,
-                      "final_relerr_vs_fp32_tensor": rel_bf16_vs_fp32},
+                      "final_relerr_vs_fp32_tensor": rel_bf16_vs_fp32,
+                      "ms_per_step_eager_timed": b["ms_eager_timed"] / steps},
+        "graph_replay_equals_eager": bool(b["graph_equals_eager"] and f["graph_equals_eager"]),
         "bf16_speedup_over_fp32": sweeps_bf16 / sweeps_fp32,
         "mttkrp": mt,
         "category_ms_per_sweep": {form: {CAT_NAMES[k]: res[form]["cat_ms"][k] / steps for k in range(5)}

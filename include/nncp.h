@@ -92,6 +92,9 @@ typedef struct nncp_options {
                        instead of the matrix-core ones [0].                    */
   double eps_mu;    /* MU denominator guard (Eq. eqn:muupd: "a small value is
                        added to the denominator") [1e-16].                     */
+  int graphs;       /* 1 = nncp_sweep replays its launches as a HIP graph
+                       (captured once per (algo, nsweeps, relerr_hist) and
+                       factor binding), 0 = plain launches [1].                */
 } nncp_options;
 
 typedef struct nncp_ctx nncp_ctx;
@@ -174,8 +177,17 @@ int nncp_cp_loss(nncp_ctx *ctx, double *loss, double *relerr);
  * across modes as in Algorithm 3 (two passes over X per sweep).  After mode
  * N-1 the relative error is formed from that mode's M and Hhat (Algorithm 4):
  *   relerr_hist  nsweeps FP64: relative error after each sweep (may be NULL)
+ * With options.graphs (the default) and timers off, the launches are captured
+ * once on a private stream into a HIP graph and replayed on the context's
+ * stream; the first call with a new (algo, nsweeps, relerr_hist) pays the
+ * capture.  The graph holds kernel launches only.
  */
 int nncp_sweep(nncp_ctx *ctx, int algo, int nsweeps, double *relerr_hist);
+
+/* Capture (without running) the graph that nncp_sweep(ctx, algo, nsweeps,
+ * relerr_hist) replays, so that the first such call does not pay for the
+ * capture.  NNCP_E_INVAL if graphs are off or nsweeps < 1. */
+int nncp_sweep_capture(nncp_ctx *ctx, int algo, int nsweeps, double *relerr_hist);
 
 /*
  * Gradient of L = 0.5 ||X - [[H]]||^2 (lambda treated as all ones, no

@@ -9,4 +9,5 @@ from .binding import (  # noqa: F401
     EXPORTS, LIB_PATH, lib, nncp_cp_loss, nncp_destroy, nncp_gemm_path, nncp_grad, nncp_gram,
     nncp_hadamard, nncp_init, nncp_mttkrp, nncp_pgd, nncp_set_factors, nncp_split, nncp_sweep,
     nncp_update_hals, nncp_update_mu, nncp_workspace_size, nncp_timers_enable, nncp_timers_read,
+    nncp_sweep_capture,
 )

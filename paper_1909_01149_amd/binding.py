@@ -32,7 +32,7 @@ EXPORTS = [
     "nncp_workspace_size", "nncp_init", "nncp_set_factors", "nncp_mttkrp", "nncp_gram",
     "nncp_hadamard", "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep",
     "nncp_grad", "nncp_pgd", "nncp_destroy", "nncp_last_error", "nncp_split",
-    "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read",
+    "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read", "nncp_sweep_capture",
 ]
 NNCP_TIMER_CATEGORIES = 5
 
@@ -48,7 +48,7 @@ class NNCPError(RuntimeError):
 
 class nncp_options(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int), ("krp_split", ctypes.c_int), ("generic", ctypes.c_int),
-                ("eps_mu", ctypes.c_double)]
+                ("eps_mu", ctypes.c_double), ("graphs", ctypes.c_int)]
 
 
 _lib = None
@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
     L.nncp_update_hals.argtypes = [vp, ci, vp, dp]
     L.nncp_cp_loss.argtypes = [vp, dp, dp]
     L.nncp_sweep.argtypes = [vp, ci, ci, dp]
+    L.nncp_sweep_capture.argtypes = [vp, ci, ci, dp]
     L.nncp_grad.argtypes = [vp, ctypes.POINTER(vp), dp]
     L.nncp_pgd.argtypes = [vp, ci, cd, ci, ci, ctypes.POINTER(cd), ctypes.POINTER(cd)]
     L.nncp_destroy.argtypes = [vp]
@@ -89,7 +90,8 @@ def lib() -> ctypes.CDLL:
     for name in ("nncp_timers_enable", "nncp_timers_read",
                  "nncp_init", "nncp_set_factors", "nncp_mttkrp", "nncp_gram", "nncp_hadamard",
                  "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep", "nncp_grad",
-                 "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path"):
+                 "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path",
+                 "nncp_sweep_capture"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -110,8 +112,8 @@ def _dims(dims):
     return arr
 
 
-def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16):
-    return nncp_options(int(split), int(krp_split), int(generic), float(eps_mu))
+def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16, graphs=1):
+    return nncp_options(int(split), int(krp_split), int(generic), float(eps_mu), int(graphs))
 
 
 def _ptr_array(ts):
@@ -178,6 +180,10 @@ def nncp_sweep(ctx, algo, nsweeps, relerr_hist=None):
     return _check(lib().nncp_sweep(ctx, int(algo), int(nsweeps), _ptr(relerr_hist)))
 
 
+def nncp_sweep_capture(ctx, algo, nsweeps, relerr_hist=None):
+    return _check(lib().nncp_sweep_capture(ctx, int(algo), int(nsweeps), _ptr(relerr_hist)))
+
+
 def nncp_grad(ctx, grads, loss=None):
     return _check(lib().nncp_grad(ctx, _ptr_array(grads), _ptr(loss)))
 
@@ -222,7 +228,8 @@ class Context:
     """Holds X, the factors, lambda and the workspace (torch tensors on one
     GPU) for an nncp context.  Factors are updated in place."""
 
-    def __init__(self, X, factors, lam=None, *, split=0, krp_split=1, generic=0, eps_mu=1e-16):
+    def __init__(self, X, factors, lam=None, *, split=0, krp_split=1, generic=0, eps_mu=1e-16,
+                 graphs=1):
         if not X.is_cuda:
             raise ValueError("X must be a GPU tensor")
         self.dims = [int(f.shape[0]) for f in factors]
@@ -232,7 +239,8 @@ class Context:
         dev = X.device
         self.lam = (lam.to(device=dev, dtype=torch.float64).contiguous() if lam is not None
                     else torch.ones(self.R, dtype=torch.float64, device=dev))
-        self.opts = dict(split=split, krp_split=krp_split, generic=generic, eps_mu=eps_mu)
+        self.opts = dict(split=split, krp_split=krp_split, generic=generic, eps_mu=eps_mu,
+                         graphs=graphs)
         nbytes = nncp_workspace_size(self.dims, self.R, _DT[X.dtype], _DT[self.factors[0].dtype],
                                      **self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -291,6 +299,15 @@ class Context:
             relerr_hist = torch.empty(max(1, nsweeps), dtype=torch.float64, device=self.X.device)
         nncp_sweep(self.ctx, algo, nsweeps, relerr_hist)
         return relerr_hist
+
+    def capture(self, algo: int, nsweeps: int, relerr_hist):
+        nncp_sweep_capture(self.ctx, algo, nsweeps, relerr_hist)
+
+    def refresh_grams(self):
+        """Recompute the context's Gram matrices after the factor tensors were
+        overwritten in place (same buffers, so captured graphs stay valid)."""
+        for n in range(self.N):
+            nncp_gram(self.ctx, n, None)
 
     def grad(self, grads=None, loss=None):
         if grads is None:

@@ -59,6 +59,7 @@ nncp_options default_options() {
   o.krp_split = 1;
   o.generic = 0;
   o.eps_mu = 1e-16;
+  o.graphs = 1;
   return o;
 }
 
@@ -269,11 +270,22 @@ struct TimerCat {
   int64_t n = 0;
 };
 
+// A captured multi-sweep launch sequence, replayed while its key matches.
+struct SweepGraph {
+  hipGraphExec_t exec = nullptr;
+  int algo = -1, nsweeps = -1;
+  double *hist = nullptr;
+  uint64_t binding = 0;
+};
+
 struct nncp_ctx {
   int magic;
   Layout L;
   int timing = 0;
   TimerCat timers[NNCP_TIMER_CATEGORIES];
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  SweepGraph graph;
+  uint64_t binding = 1;       // bumped when factor / lambda pointers change
   const void *X;
   void *H[NNCP_MAX_MODES];
   double *lambda;
@@ -350,6 +362,15 @@ FactorSet factors_of(const nncp_ctx *c, void *const *H) {
   return F;
 }
 
+// Where a computed M^(n) lives: msplit == 1 means p is M itself; otherwise p
+// holds msplit row-major partial copies, mstride apart, that the consumer adds
+// in order (the same order the split-sum kernels use).
+struct MRef {
+  const void *p;
+  int msplit;
+  int64_t mstride;
+};
+
 void *node_buf(nncp_ctx *c, int side, int a) {
   const int lo = side == 0 ? 0 : c->L.S;
   return ((a - lo) % 2 == 0) ? c->nodeA : c->nodeB;
@@ -357,7 +378,7 @@ void *node_buf(nncp_ctx *c, int side, int a) {
 
 // Root partial MTTKRP of one side into node[lo] (or into Mout if the subtree
 // has a single mode).
-int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout) {
+int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout, MRef *defer) {
   const Layout &L = c->L;
   const GemmPlan &p = L.gp[side];
   const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
@@ -367,21 +388,31 @@ int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout) {
   const bool direct = p.nsplit == 1 && ((side == 0 && !leaf) || (side == 1 && leaf));
   TIMED(side, launch_partial_mttkrp(L.xdt, p, L.R, c->X, L.dims, L.N, L.S, F, c->kf, c->ks,
                                     direct ? node : c->part, c->st));
-  if (!direct) TIMED(3, launch_finalize(L.hdt, p, L.R, c->part, node, leaf ? 1 : 0, c->st));
+  if (defer) *defer = MRef{Mout, 1, 0};
+  if (!direct) {
+    // right partials of a single-mode subtree are already row-major copies of M
+    if (defer && leaf && side == 1) {
+      *defer = MRef{c->part, p.nsplit, p.k * L.R};
+      return NNCP_OK;
+    }
+    TIMED(3, launch_finalize(L.hdt, p, L.R, c->part, node, leaf ? 1 : 0, c->st));
+  }
   return NNCP_OK;
 }
 
 // M^(n) through the dimension tree.  When from_root is false the node of
 // mode n-1 (same subtree) must hold the values left by the previous call and
 // H^(n-1) may have changed since (Gauss-Seidel order of Algorithm 1).
-int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_root) {
+int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_root,
+                MRef *defer = nullptr) {
   const Layout &L = c->L;
   const int side = n < L.S ? 0 : 1;
   const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
   const int R = L.R;
   int start;
+  if (defer) *defer = MRef{Mout, 1, 0};
   if (from_root || n == lo) {
-    int rc = root_gemm(c, F, side, Mout);
+    int rc = root_gemm(c, F, side, Mout, hi - lo == 1 ? defer : nullptr);
     if (rc) return rc;
     if (hi - lo == 1) return NNCP_OK;
     start = lo + 1;
@@ -400,8 +431,11 @@ int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_ro
   if (n < hi - 1) {
     const void *Hq[NNCP_MAX_MODES];
     for (int k = n + 1; k < hi; ++k) Hq[k - n - 1] = F.H[k];
+    int ns = 1;
     TIMED(3, launch_mttv_strided(L.hdt, node_buf(c, side, n), L.dims[n], L.dims + n + 1,
-                                 hi - n - 1, Hq, R, Mout, c->part, L.part_elems, c->st));
+                                 hi - n - 1, Hq, R, defer ? nullptr : Mout, c->part,
+                                 L.part_elems, c->st, &ns));
+    if (defer) *defer = MRef{c->part, ns, L.dims[n] * R};
   }
   return NNCP_OK;
 }
@@ -412,8 +446,8 @@ int refresh_grams(nncp_ctx *c, const FactorSet &F, double *G) {
   return NNCP_OK;
 }
 
-int update_mode(nncp_ctx *c, int algo, int n, const void *M, const double *S, double eps,
-                double *relerr_out, double *scal) {
+int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double eps,
+                double *relerr_out, double *scal, double *S_next = nullptr) {
   const Layout &L = c->L;
   UpdateArgs a;
   a.algo = algo;
@@ -421,8 +455,12 @@ int update_mode(nncp_ctx *c, int algo, int n, const void *M, const double *S, do
   a.R = L.R;
   a.N = L.N;
   a.mode = n;
-  a.M = M;
+  a.M = M.p;
+  a.msplit = M.msplit;
+  a.mstride = M.mstride;
   a.S = S;
+  a.S_next = S_next;
+  a.next_mode = (n + 1) % L.N;
   if (!S && L.R > 64) {
     HIPCHK(launch_hadamard(c->G, L.N, L.R, n, c->S, c->st));
     a.S = c->S;
@@ -543,6 +581,7 @@ int nncp_set_factors(nncp_ctx *c, void *const *H, double *lambda) {
   if (lambda && !aligned16(lambda)) return fail(NNCP_E_INVAL, "lambda misaligned");
   for (int n = 0; n < c->L.N; ++n) c->H[n] = H[n];
   if (lambda) c->lambda = lambda;
+  ++c->binding;
   return refresh_grams(c, factors_of(c, c->H), c->G);
 }
 
@@ -591,7 +630,7 @@ static int update_api(nncp_ctx *c, int algo, int mode, const void *M, const doub
   if (rc) return rc;
   if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
   if (!M || !S) return fail(NNCP_E_INVAL, "M or S is NULL");
-  return update_mode(c, algo, mode, M, S, eps, nullptr, nullptr);
+  return update_mode(c, algo, mode, MRef{M, 1, 0}, S, eps, nullptr, nullptr);
 }
 
 int nncp_update_mu(nncp_ctx *c, int mode, const void *M, const double *S, double eps) {
@@ -616,24 +655,90 @@ int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
   return NNCP_OK;
 }
 
+static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
+  const Layout &L = c->L;
+  const FactorSet F = factors_of(c, c->H);
+  // S^(0) here; every update then leaves S of the next mode in c->S
+  HIPCHK(launch_hadamard(c->G, L.N, L.R, 0, c->S, c->st));
+  for (int s = 0; s < nsweeps; ++s) {
+    for (int n = 0; n < L.N; ++n) {
+      MRef M;
+      int rc = mttkrp_tree(c, F, n, c->M, false, &M);
+      if (rc) return rc;
+      const bool last = n == L.N - 1;
+      rc = update_mode(c, algo, n, M, c->S, L.opt.eps_mu,
+                       last && relerr_hist ? relerr_hist + s : nullptr, last ? c->scal : nullptr,
+                       c->S);
+      if (rc) return rc;
+    }
+  }
+  return NNCP_OK;
+}
+
+static void drop_graph(nncp_ctx *c) {
+  if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
+  c->graph = SweepGraph();
+}
+
+// Capture the launches of nsweeps sweeps on the private stream and
+// instantiate them (kernels only: the sweep records no memset or copy).
+static int build_graph(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
+  drop_graph(c);
+  if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  hipStream_t user = c->st;
+  c->st = c->cap;
+  hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->st = user;
+    return fail(NNCP_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  int rc = sweep_launches(c, algo, nsweeps, relerr_hist);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap, &g);
+  c->st = user;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(NNCP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(NNCP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  c->graph.exec = ex;
+  c->graph.algo = algo;
+  c->graph.nsweeps = nsweeps;
+  c->graph.hist = relerr_hist;
+  c->graph.binding = c->binding;
+  return NNCP_OK;
+}
+
 int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (algo != NNCP_MU && algo != NNCP_HALS) return fail(NNCP_E_INVAL, "algo %d", algo);
   if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
-  const Layout &L = c->L;
-  const FactorSet F = factors_of(c, c->H);
-  for (int s = 0; s < nsweeps; ++s) {
-    for (int n = 0; n < L.N; ++n) {
-      rc = mttkrp_tree(c, F, n, c->M, false);
-      if (rc) return rc;
-      const bool last = n == L.N - 1;
-      rc = update_mode(c, algo, n, c->M, nullptr, L.opt.eps_mu,
-                       last && relerr_hist ? relerr_hist + s : nullptr, last ? c->scal : nullptr);
-      if (rc) return rc;
-    }
+  if (nsweeps == 0) return NNCP_OK;
+  // Eager launches while timing (each launch is bracketed by events) or when
+  // graphs are switched off; otherwise replay a cached graph of the sweeps.
+  if (c->timing || !c->L.opt.graphs) return sweep_launches(c, algo, nsweeps, relerr_hist);
+  const SweepGraph &g = c->graph;
+  if (!(g.exec && g.algo == algo && g.nsweeps == nsweeps && g.hist == relerr_hist &&
+        g.binding == c->binding)) {
+    rc = build_graph(c, algo, nsweeps, relerr_hist);
+    if (rc) return rc;
   }
+  HIPCHK(hipGraphLaunch(c->graph.exec, c->st));
   return NNCP_OK;
+}
+
+int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (algo != NNCP_MU && algo != NNCP_HALS) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (nsweeps < 1) return fail(NNCP_E_INVAL, "nsweeps %d < 1", nsweeps);
+  if (!c->L.opt.graphs) return fail(NNCP_E_INVAL, "graphs are switched off for this context");
+  return build_graph(c, algo, nsweeps, relerr_hist);
 }
 
 static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const *grads,
@@ -757,6 +862,8 @@ int nncp_destroy(nncp_ctx *c) {
   if (rc) return rc;
   for (int k = 0; k < NNCP_TIMER_CATEGORIES; ++k)
     for (hipEvent_t e : c->timers[k].ev) (void)hipEventDestroy(e);
+  drop_graph(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   c->magic = 0;
   delete c;
   return NNCP_OK;

@@ -106,9 +106,11 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
 
 // Multi-TTV, strided reduction keeping the node's first mode:
 //   M(i, r) = sum_q T[r][i + Ia q] * prod_{k in modes} H^(k)(digit_k(q), r)
+// When M is NULL the split partials are left in `part` ([nsplit][Ia][R]) for
+// the consumer to add; *nsplit_out receives their count.
 hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
                                const void *const *Hq, int R, void *M, void *part,
-                               int64_t part_elems, hipStream_t st);
+                               int64_t part_elems, hipStream_t st, int *nsplit_out);
 int64_t mttv_strided_part_elems(int64_t Ia, const int64_t *qdims, int nq, int R);
 
 // Gram G = H^T H (FP64) for one factor; single workgroup.
@@ -126,8 +128,12 @@ struct UpdateArgs {
   int64_t I;            // rows
   int R;
   int N, mode;
-  const void *M;        // I x R (hdt)
+  const void *M;        // I x R (hdt), or msplit partial copies of it
+  int msplit;           // M = sum_{s < msplit} M[s * mstride ...], added in order
+  int64_t mstride;
   const double *S;      // R x R, or NULL: form from G
+  double *S_next;       // if not NULL: receives the Hadamard product of the
+  int next_mode;        //   Grams other than next_mode, after G^(mode) is new
   double *G;            // N x R x R Grams (G[mode] rewritten)
   void *H;              // factor (hdt), in/out
   double *lambda;       // R, in/out

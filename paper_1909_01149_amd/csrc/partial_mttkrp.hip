@@ -87,6 +87,12 @@ __device__ __forceinline__ void mma1(f64x4 &c, double a, double b) {
   c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// streaming loads of X through the global (not flat) address space
+template <typename VT> __device__ __forceinline__ VT gload(const void *p) {
+  typedef const __attribute__((address_space(1))) VT gvt;
+  return __builtin_nontemporal_load((gvt *)p);
+}
+
 template <typename CT> __device__ __forceinline__ void czero(CT &c) {
   c[0] = 0; c[1] = 0; c[2] = 0; c[3] = 0;
 }
@@ -231,11 +237,26 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) { czero(acc[mt][nt]); czero(blk[mt][nt]); }
 
-  auto step = [&](const u32x4 *va, int64_t t) {
-    const int pf0 = (int)(t % spb) * KSTEP;
+  // Position in the fast block (pf) and fast-block index (bI) advance with
+  // the steps; only the wave's starting position needs a division.
+  int pf = (int)(w_lo % spb) * KSTEP;
+  int64_t bI = w_lo / spb;
+  auto flush = [&]() {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const XT *bp = sk + kidx<XT>(16 * nt + row, pf0 + g * VEC, ldk, swz);
+      const AT s = kslow[bI * RP + 16 * nt + row];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[mt][nt][v] += blk[mt][nt][v] * s;
+        czero(blk[mt][nt]);
+      }
+    }
+  };
+  auto step = [&](const u32x4 *va) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const XT *bp = sk + kidx<XT>(16 * nt + row, pf + g * VEC, ldk, swz);
       const u32x4 vb = *reinterpret_cast<const u32x4 *>(bp);
       u32x4 vbl;
       if (HL) vbl = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
@@ -246,24 +267,19 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
         if (HL) mma16(c, va[mt], vbl, (XT *)nullptr);
       }
     }
-    if (SLOW && ((t + 1) % spb == 0 || t + 1 == w_hi)) {
-      const int64_t b = t / spb;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const AT s = kslow[b * RP + 16 * nt + row];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[mt][nt][v] += blk[mt][nt][v] * s;
-          czero(blk[mt][nt]);
-        }
-      }
+    pf += KSTEP;
+    if (pf == Pf) {
+      if (SLOW) flush();
+      pf = 0;
+      ++bI;
     }
   };
 
   // batches of U steps, the next batch's loads issued before the current
   // batch is consumed (the last batch re-reads itself instead of running past
   // the wave's range)
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) xp[mt] += w_lo * KSTEP;
   int64_t t = w_lo;
   const int64_t nb = (w_hi - w_lo) / U;
   if (nb > 0) {
@@ -272,18 +288,18 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        cur[u][mt] = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4 *>(xp[mt] + (t + u) * KSTEP));
-    for (int64_t bI = 0; bI < nb; ++bI, t += U) {
-      const int64_t tn = bI + 1 < nb ? t + U : t;
+        cur[u][mt] = gload<u32x4>(xp[mt] + u * KSTEP);
+    for (int64_t b = 0; b < nb; ++b, t += U) {
+      const int adv = b + 1 < nb ? U * KSTEP : 0;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          nxt[u][mt] = __builtin_nontemporal_load(
-              reinterpret_cast<const u32x4 *>(xp[mt] + (tn + u) * KSTEP));
+          nxt[u][mt] = gload<u32x4>(xp[mt] + adv + u * KSTEP);
 #pragma unroll
-      for (int u = 0; u < U; ++u) step(cur[u], t + u);
+      for (int u = 0; u < U; ++u) step(cur[u]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) xp[mt] += U * KSTEP;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -293,10 +309,14 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
   for (; t < w_hi; ++t) {
     u32x4 va[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      va[mt] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(xp[mt] + t * KSTEP));
-    step(va, t);
+    for (int mt = 0; mt < MT; ++mt) {
+      va[mt] = gload<u32x4>(xp[mt]);
+      xp[mt] += KSTEP;
+    }
+    step(va);
   }
+  // a fast block cut by the end of the wave's range
+  if (SLOW && pf != 0) flush();
   if (!SLOW) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
@@ -420,11 +440,14 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
       const int64_t tt = t0 + b < s_hi ? t0 + b : s_hi - 1;
 #pragma unroll
       for (int u = 0; u < KL; ++u)
-        dst[b * KL + u] = __builtin_nontemporal_load(
-            reinterpret_cast<const LT *>(xp + (tt * KSTEP + u) * m));
+        dst[b * KL + u] = gload<LT>(xp + (tt * KSTEP + u) * m);
     }
   };
   if (s_lo < s_hi) load_batch(raw, s_lo);
+  // position in the fast block, window index and block index, advanced with
+  // the steps (one division at the start)
+  int pfa = (int)(s_lo % spb) * KSTEP;
+  int64_t bI = s_lo / spb;
   for (int64_t t0 = s_lo; t0 < s_hi; t0 += SB) {
     load_batch(nxt, t0 + SB < s_hi ? t0 + SB : t0);
 #pragma unroll
@@ -432,8 +455,7 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
       const int64_t t = t0 + b;
       if (t >= s_hi) break;
       const LT *rw = raw + b * KL;
-      const int pfa = (int)(t % spb) * KSTEP;
-      const int wi = pfa / W;
+      const int wi = W == Pf ? 0 : pfa / W;
       if (wi != cur_w) {
         __syncthreads();
         stage(wi * W);
@@ -474,8 +496,9 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) mma1(SLOW ? blk[q][nt] : acc[q][nt], xv[q], bb[nt]);
       }
-      if (SLOW && ((t + 1) % spb == 0 || t + 1 == s_hi)) {
-        const int64_t bI = t / spb;
+      pfa += KSTEP;
+      const bool wrap = pfa == Pf;
+      if (SLOW && (wrap || t + 1 == s_hi)) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           const AT sc = kslow[bI * RP + 16 * nt + rho];
@@ -486,6 +509,10 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
             czero(blk[q][nt]);
           }
         }
+      }
+      if (wrap) {
+        pfa = 0;
+        ++bI;
       }
     }
 #pragma unroll
@@ -608,8 +635,19 @@ __global__ __launch_bounds__(256) void k_finalize(const HT *__restrict__ part, i
   int64_t row, r;
   if (leaf) { row = e / R; r = e % R; } else { r = e / rows; row = e % rows; }
   const int64_t src = part_rmajor ? r * rows + row : row * R + r;
-  HT s = part[src];
-  for (int q = 1; q < nsplit; ++q) s += part[(int64_t)q * rows * R + src];
+  const HT *p = part + src;
+  const int64_t stride = rows * R;
+  // added in split order; loads issued eight at a time
+  HT s = p[0];
+  int q = 1;
+  for (; q + 8 <= nsplit; q += 8) {
+    HT v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < nsplit; ++q) s += p[(int64_t)q * stride];
   out[e] = s;
 }
 

@@ -17,6 +17,24 @@ template <typename T> __device__ __forceinline__ double to_dd(T v) { return (dou
 template <> __device__ __forceinline__ double to_dd<bf16_t>(bf16_t v) { return (double)(float)v; }
 template <> __device__ __forceinline__ double to_dd<f16_t>(f16_t v) { return (double)(float)v; }
 
+
+// sum_{s < ns} p[s * stride] added in order s = 0, 1, ...; the loads are
+// issued eight at a time so they overlap
+template <typename HT>
+__device__ __forceinline__ HT ordered_split_sum(const HT *__restrict__ p, int ns, int64_t stride) {
+  HT acc = p[0];
+  int sp = 1;
+  for (; sp + 8 <= ns; sp += 8) {
+    HT v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(sp + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; sp < ns; ++sp) acc += p[(int64_t)sp * stride];
+  return acc;
+}
+
 // sum over the 64 lanes of a wave, fixed butterfly order
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -145,9 +163,27 @@ __global__ __launch_bounds__(256) void k_sum_splits(const HT *__restrict__ part,
                                                     HT *__restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
-  HT s = part[e];
-  for (int z = 1; z < ns; ++z) s += part[(int64_t)z * n + e];
-  out[e] = s;
+  out[e] = ordered_split_sum(part + e, ns, n);
+}
+
+
+// acc + sum over rows i = s, s+ns, ... < rows of chunk[i][x] * chunk[i][y], in
+// row order; eight rows' operands are read before their products are added
+__device__ __forceinline__ double gram_rows(const double *chunk, int R, int x, int y, int s,
+                                            int rows, int ns, double acc) {
+  int i = s;
+  for (; i + 7 * ns < rows; i += 8 * ns) {
+    double u[8], w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      u[k] = chunk[(i + k * ns) * R + x];
+      w[k] = chunk[(i + k * ns) * R + y];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += u[k] * w[k];
+  }
+  for (; i < rows; i += ns) acc += chunk[i * R + x] * chunk[i * R + y];
+  return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -178,10 +214,21 @@ __device__ void gram_block(const HT *__restrict__ H, int64_t I, int R, double *_
     for (int64_t i0 = 0; i0 < I; i0 += CH) {
       const int rows = (int)(I - i0 < CH ? I - i0 : CH);
       __syncthreads();
-      for (int e = threadIdx.x; e < rows * R; e += 1024) chunk[e] = (double)H[i0 * R + e];
+      {
+        const int ne = rows * R;
+        int e = threadIdx.x;
+        for (; e + 3 * 1024 < ne; e += 4 * 1024) {
+          HT v0 = H[i0 * R + e], v1 = H[i0 * R + e + 1024], v2 = H[i0 * R + e + 2048],
+             v3 = H[i0 * R + e + 3072];
+          chunk[e] = (double)v0;
+          chunk[e + 1024] = (double)v1;
+          chunk[e + 2048] = (double)v2;
+          chunk[e + 3072] = (double)v3;
+        }
+        for (; e < ne; e += 1024) chunk[e] = (double)H[i0 * R + e];
+      }
       __syncthreads();
-      if (live)
-        for (int i = s; i < rows; i += ns) acc += chunk[i * R + a] * chunk[i * R + b];
+      if (live) acc = gram_rows(chunk, R, a, b, s, rows, ns, acc);
     }
     lds[threadIdx.x] = acc;
     __syncthreads();
@@ -276,50 +323,91 @@ __device__ __forceinline__ double bcast(double v, int lane) {
 template <typename HT, int CPL>
 __global__ __launch_bounds__(256) void k_update_rows(UpdateArgs a) {
   __shared__ double sS[64 * 64];
-  __shared__ double lam_s[256];
   __shared__ double hrow[4][256];
   __shared__ double wred[4][256];
   __shared__ double bred[4];
+  __shared__ double sdiag[256];
   const int R = a.R;
   const bool s_in_lds = R <= 64;
-  if (s_in_lds) {
-    for (int e = threadIdx.x; e < R * R; e += 256) {
-      double s;
-      if (a.S) s = a.S[e];
-      else {
-        s = 1.0;
-        for (int k = 0; k < a.N; ++k)
-          if (k != a.mode) s *= a.G[(int64_t)k * R * R + e];
-      }
-      sS[e] = s;
-    }
-  }
-  for (int c = threadIdx.x; c < R; c += 256) lam_s[c] = a.lambda[c];
-  __syncthreads();
-  const double *Sg = a.S;
-  auto Sv = [&](int c, int r) -> double { return s_in_lds ? sS[c * R + r] : Sg[c * R + r]; };
-
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const HT *M = (const HT *)a.M;
   const HT *H = (const HT *)a.H;
   const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   const bool live = i < a.I;
-  double h[CPL], m[CPL], g[CPL];
+  // every global load is issued before its first use: S (or the Grams it is
+  // formed from), lambda, the row of H and the row of M
+  double sv[16];
+  if (s_in_lds) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      double v = 0.0;
+      if (e < R * R) {
+        if (a.S) v = a.S[e];
+        else {
+          v = 1.0;
+          for (int q = 0; q < a.N; ++q)
+            if (q != a.mode) v *= a.G[(int64_t)q * R * R + e];
+        }
+      }
+      sv[k] = v;
+    }
+  }
+  double hraw[CPL], lamv[CPL];
+  HT mraw[CPL];
 #pragma unroll
   for (int u = 0; u < CPL; ++u) {
     const int c = lane + 64 * u;
     const bool ok = live && c < R;
-    h[u] = ok ? (double)H[i * R + c] * lam_s[c] : 0.0;
-    m[u] = ok ? (double)M[i * R + c] : 0.0;
+    hraw[u] = ok ? (double)H[i * R + c] : 0.0;
+    lamv[u] = c < R ? a.lambda[c] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int c = lane + 64 * u;
+    mraw[u] = (live && c < R) ? ordered_split_sum(M + i * R + c, a.msplit, a.mstride) : (HT)0;
+  }
+  if (s_in_lds) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < R * R) sS[e] = sv[k];
+    }
+  }
+  __syncthreads();
+  const double *Sg = a.S;
+  auto Sv = [&](int c, int r) -> double { return s_in_lds ? sS[c * R + r] : Sg[c * R + r]; };
+  // HALS divisors S(r, r), read once
+  for (int c = threadIdx.x; c < R; c += 256) sdiag[c] = Sv(c, c);
+  double h[CPL], m[CPL], g[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int c = lane + 64 * u;
+    h[u] = hraw[u] * lamv[u];
+    m[u] = (double)mraw[u];
     if (c < R) hrow[wave][c] = h[u];
   }
-  // g = (Hhat S)(i, :) from the row in LDS (independent reads, no chain)
+  __syncthreads();
+  // g = (Hhat S)(i, :) from the row in LDS, j in order, eight j's operands
+  // read before their products are added
 #pragma unroll
   for (int u = 0; u < CPL; ++u) {
     const int c = lane + 64 * u;
     double acc = 0.0;
-    if (c < R)
-      for (int j = 0; j < R; ++j) acc += hrow[wave][j] * Sv(j, c);
+    if (c < R) {
+      int j = 0;
+      for (; j + 8 <= R; j += 8) {
+        double hv[8], sv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          hv[k] = hrow[wave][j + k];
+          sv[k] = Sv(j + k, c);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += hv[k] * sv[k];
+      }
+      for (; j < R; ++j) acc += hrow[wave][j] * Sv(j, c);
+    }
     g[u] = acc;
   }
   if (a.algo == NNCP_MU) {
@@ -329,7 +417,7 @@ __global__ __launch_bounds__(256) void k_update_rows(UpdateArgs a) {
 #pragma unroll
     for (int u = 0; u < CPL; ++u) g[u] = m[u] - g[u];
     for (int r = 0; r < R; ++r) {
-      const double d = Sv(r, r);
+      const double d = sdiag[r];
       if (!(d > 0.0)) continue;
       const int ur = r >> 6, owner = r & 63;
       double hs = h[0], gs = g[0];
@@ -376,42 +464,127 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
   __shared__ double lam_s[256];
   __shared__ double lds[1024];
   __shared__ double chunk[4096];
-  __shared__ double beta_s;
   const int R = a.R;
-  for (int c = threadIdx.x; c < R; c += 1024) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += a.part[(int64_t)b * (R + 1) + c];
-    lam_s[c] = sqrt(s);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t IR = a.I * R;
+  // Hhat entries e = threadIdx.x + 1024 k, k < 16, loaded before anything
+  // else (entries past 16384 are read chunk by chunk below)
+  double hpre[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t e = threadIdx.x + 1024 * k;
+    hpre[k] = e < IR ? a.hhat[e] : 0.0;
   }
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += a.part[(int64_t)b * (R + 1) + R];
-    beta_s = s;
+  // column norms and beta: one wave per column, lanes over the workgroup
+  // partials, then a fixed butterfly
+  for (int c = wave; c <= R; c += 16) {
+    double sum = 0.0;
+    for (int b = lane; b < nblocks; b += 64) sum += a.part[(int64_t)b * (R + 1) + c];
+    sum = wave_sum(sum);
+    if (lane == 0) {
+      if (c < R) lam_s[c] = sqrt(sum);
+      else wred[0][0] = sum;
+    }
   }
   __syncthreads();
-  HT *H = (HT *)a.H;
-  for (int64_t e = threadIdx.x; e < a.I * R; e += 1024) {
-    const double l = lam_s[e % R];
-    H[e] = (HT)(l > 0.0 ? a.hhat[e] / l : 0.0);
-  }
+  const double beta = wred[0][0];
   for (int c = threadIdx.x; c < R; c += 1024) a.lambda[c] = lam_s[c];
-  __syncthreads();
+  HT *H = (HT *)a.H;
   double *Gm = a.G + (int64_t)a.mode * R * R;
-  gram_block<HT>(H, a.I, R, Gm, lds, chunk);
+  if (R <= 64) {
+    // normalise rows chunk by chunk; each normalised (stored) chunk also feeds
+    // the Gram straight from LDS.  Pairs (x, y), x <= y, in at most 3 rounds.
+    const int npairs = R * (R + 1) / 2;
+    int ns = 1;
+    while (ns * 2 * npairs <= 1024) ns *= 2;
+    const int per_round = 1024 / ns;
+    const int rounds = (npairs + per_round - 1) / per_round;
+    const int pl = threadIdx.x / ns, sl = threadIdx.x % ns;
+    int px[3], py[3];
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int p = k * per_round + pl, x = 0;
+      px[k] = py[k] = -1;
+      if (k < rounds && p < npairs) {
+        while (p >= R - x) { p -= R - x; ++x; }
+        px[k] = x;
+        py[k] = x + p;
+      }
+    }
+    const int CH = 4096 / R;
+    for (int64_t i0 = 0; i0 < a.I; i0 += CH) {
+      const int rows = (int)(a.I - i0 < CH ? a.I - i0 : CH);
+      const int ne = rows * R;
+      __syncthreads();
+      {
+        // ne <= 4096: at most four entries per thread; chunk c of 4096
+        // entries is registers 4c..4c+3 of the prefetch when c < 4
+        double hv4[4];
+        const int cidx = (int)(i0 * R / 4096);
+        if (CH * R == 4096 && cidx < 4) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (q == cidx) hv4[k] = hpre[4 * q + k];
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + 1024 * k;
+            hv4[k] = e < ne ? a.hhat[i0 * R + e] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int e = threadIdx.x + 1024 * k;
+          if (e < ne) {
+            const double l = lam_s[e % R];
+            const HT hv = (HT)(l > 0.0 ? hv4[k] / l : 0.0);
+            H[i0 * R + e] = hv;
+            chunk[e] = (double)hv;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (px[k] >= 0) acc[k] = gram_rows(chunk, R, px[k], py[k], sl, rows, ns, acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      __syncthreads();
+      lds[threadIdx.x] = acc[k];
+      __syncthreads();
+      if (sl == 0 && px[k] >= 0) {
+        double v = lds[threadIdx.x];
+        for (int q = 1; q < ns; ++q) v += lds[threadIdx.x + q];
+        Gm[px[k] * R + py[k]] = v;
+        Gm[py[k] * R + px[k]] = v;
+      }
+    }
+  } else {
+    for (int64_t e = threadIdx.x; e < a.I * R; e += 1024) {
+      const double l = lam_s[e % R];
+      H[e] = (HT)(l > 0.0 ? a.hhat[e] / l : 0.0);
+    }
+    __syncthreads();
+    gram_block<HT>(H, a.I, R, Gm, lds, chunk);
+  }
   __syncthreads();
   if (a.relerr_out || a.scal) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double gsum = 0.0;
     for (int e = threadIdx.x; e < R * R; e += 1024) {
       const int r = e / R, c = e % R;
-      double s;
-      if (a.S) s = a.S[e];
+      double sv;
+      if (a.S) sv = a.S[e];
       else {
-        s = 1.0;
+        sv = 1.0;
         for (int k = 0; k < a.N; ++k)
-          if (k != a.mode) s *= a.G[(int64_t)k * R * R + e];
+          if (k != a.mode) sv *= a.G[(int64_t)k * R * R + e];
       }
-      gsum += lam_s[r] * s * Gm[e] * lam_s[c];
+      gsum += lam_s[r] * sv * Gm[e] * lam_s[c];
     }
     const double v = wave_sum(gsum);
     if (lane == 0) wred[wave][1] = v;
@@ -419,7 +592,6 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
     if (threadIdx.x == 0) {
       double gamma = 0.0;
       for (int w = 0; w < 16; ++w) gamma += wred[w][1];
-      const double beta = beta_s;
       const double alpha = a.alpha ? a.alpha[0] : 0.0;
       const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
       if (a.scal) {
@@ -428,6 +600,17 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
         a.scal[2] = e2;
       }
       if (a.relerr_out) a.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
+    }
+  }
+  if (a.S_next) {
+    // S for the next mode (every Gram is current now); written after gamma
+    // has used S of this mode, which may live in the same buffer
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * R; e += 1024) {
+      double v = 1.0;
+      for (int q = 0; q < a.N; ++q)
+        if (q != a.next_mode) v *= a.G[(int64_t)q * R * R + e];
+      a.S_next[e] = v;
     }
   }
 }
@@ -639,7 +822,7 @@ int64_t mttv_strided_part_elems(int64_t Ia, const int64_t *qdims, int nq, int R)
 
 hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
                                const void *const *Hq, int R, void *M, void *part,
-                               int64_t part_elems, hipStream_t st) {
+                               int64_t part_elems, hipStream_t st, int *nsplit_out) {
   StridedArgs a;
   int64_t Q = 1;
   for (int k = 0; k < NNCP_MAX_MODES; ++k) {
@@ -654,12 +837,15 @@ hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t
   dim3 grid((unsigned)gx, R, a.nsplit), block(256);
   const int64_t n = Ia * R;
   dim3 g2((unsigned)((n + 255) / 256));
+  if (nsplit_out) *nsplit_out = a.nsplit;
   if (hdt == NNCP_F64) {
     hipLaunchKernelGGL(k_mttv_strided<double>, grid, block, 0, st, (const double *)T, a, (double *)part);
-    hipLaunchKernelGGL(k_sum_splits<double>, g2, dim3(256), 0, st, (const double *)part, n, a.nsplit, (double *)M);
+    if (M)
+      hipLaunchKernelGGL(k_sum_splits<double>, g2, dim3(256), 0, st, (const double *)part, n, a.nsplit, (double *)M);
   } else {
     hipLaunchKernelGGL(k_mttv_strided<float>, grid, block, 0, st, (const float *)T, a, (float *)part);
-    hipLaunchKernelGGL(k_sum_splits<float>, g2, dim3(256), 0, st, (const float *)part, n, a.nsplit, (float *)M);
+    if (M)
+      hipLaunchKernelGGL(k_sum_splits<float>, g2, dim3(256), 0, st, (const float *)part, n, a.nsplit, (float *)M);
   }
   return hipGetLastError();
 }

@@ -57,7 +57,7 @@ def test_workspace_size_validation(B):
     assert L.nncp_workspace_size(3, dims, 300, B.NNCP_F32, B.NNCP_F32, None) == 0
     bad = (ctypes.c_int64 * 3)(8, 0, 8)
     assert L.nncp_workspace_size(3, bad, 4, B.NNCP_F32, B.NNCP_F32, None) == 0
-    o = B.nncp_options(5, 1, 0, 1e-16)   # split outside [1, N-1]
+    o = B.nncp_options(5, 1, 0, 1e-16, 1)   # split outside [1, N-1]
     assert L.nncp_workspace_size(3, dims, 4, B.NNCP_F32, B.NNCP_F32, ctypes.byref(o)) == 0
 
 
