@@ -49,8 +49,8 @@ struct Layout {
   GemmPlan gp[2];
   int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
   // byte offsets into the workspace
-  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_red, off_M, off_A,
-      off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, total;
+  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart, off_ticket,
+      off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, total;
 };
 
 nncp_options default_options() {
@@ -92,6 +92,9 @@ void plan_side(Layout &L, int side) {
   const bool is16 = L.xdt == NNCP_BF16 || L.xdt == NNCP_F16;
   p.hl = is16 && L.opt.krp_split ? 1 : 0;
   const int es = (int)xsize(L.xdt);
+  // tensors up to 1 GiB are read with normal loads (much of them is still in
+  // the last-level cache for the next product); larger ones are streamed
+  p.nt_loads = (double)p.m * (double)p.k * es > (double)(1ull << 30) ? 1 : 0;
   const int hs = (int)xsize(L.hdt);
   const int VEC = 16 / es;
   const int KL = is16 ? 8 : 1;
@@ -246,6 +249,8 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_ones = take(sizeof(double) * R);
   L.off_hhat = take(sizeof(double) * L.maxI * R);
   L.off_upart = take(sizeof(double) * update_part_elems(L.maxI, R));
+  L.off_gpart = take(R <= 64 ? sizeof(double) * norm_gpart_elems(R) : 0);
+  L.off_ticket = take(sizeof(unsigned));
   L.off_red = take(sizeof(double) * 1024);
   L.off_M = take(hs * L.maxI * R);
   L.off_A = take(hs * L.nodeA);
@@ -291,7 +296,8 @@ struct nncp_ctx {
   double *lambda;
   hipStream_t st;
   char *ws;
-  double *G, *Gt, *S, *scal, *ones, *hhat, *upart, *red;
+  double *G, *Gt, *S, *scal, *ones, *hhat, *upart, *gpart, *red;
+  unsigned *ticket;
   void *M, *nodeA, *nodeB, *part, *kf, *ks;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
 };
@@ -461,7 +467,7 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.S = S;
   a.S_next = S_next;
   a.next_mode = (n + 1) % L.N;
-  if (!S && L.R > 64) {
+  if (!S) {
     HIPCHK(launch_hadamard(c->G, L.N, L.R, n, c->S, c->st));
     a.S = c->S;
   }
@@ -470,6 +476,8 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.lambda = c->lambda;
   a.hhat = c->hhat;
   a.part = c->upart;
+  a.gpart = c->gpart;
+  a.ticket = c->ticket;
   a.eps = eps;
   a.alpha = c->scal + 8;
   a.relerr_out = relerr_out;
@@ -530,6 +538,8 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->ones = (double *)(c->ws + L.off_ones);
   c->hhat = (double *)(c->ws + L.off_hhat);
   c->upart = (double *)(c->ws + L.off_upart);
+  c->gpart = (double *)(c->ws + L.off_gpart);
+  c->ticket = (unsigned *)(c->ws + L.off_ticket);
   c->red = (double *)(c->ws + L.off_red);
   c->M = c->ws + L.off_M;
   c->nodeA = c->ws + L.off_A;
@@ -552,6 +562,8 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
     double onesh[256];
     for (int r = 0; r < R; ++r) onesh[r] = 1.0;
     hipError_t e = hipMemcpyAsync(c->ones, onesh, sizeof(double) * R, hipMemcpyHostToDevice, c->st);
+    // the finish kernel's ticket counter starts at zero and is left at zero
+    if (e == hipSuccess) e = hipMemsetAsync(c->ticket, 0, sizeof(unsigned), c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
       delete c;

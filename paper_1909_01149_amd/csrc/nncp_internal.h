@@ -66,6 +66,7 @@ struct GemmPlan {
   int NT;            // 16-column tiles (Rpad = 16 * NT)
   int Rpad;
   int hl;            // hi+lo Khatri-Rao operand
+  int nt_loads;      // left kernel: non-temporal loads of X (large tensors)
   int nsplit;        // split of the reduction across workgroups
   int64_t tiles;     // output tiles (grid.x)
   size_t lds_bytes;  // dynamic LDS of the MFMA kernel
@@ -131,7 +132,7 @@ struct UpdateArgs {
   const void *M;        // I x R (hdt), or msplit partial copies of it
   int msplit;           // M = sum_{s < msplit} M[s * mstride ...], added in order
   int64_t mstride;
-  const double *S;      // R x R, or NULL: form from G
+  const double *S;      // R x R (the Hadamard product of the Grams other than mode)
   double *S_next;       // if not NULL: receives the Hadamard product of the
   int next_mode;        //   Grams other than next_mode, after G^(mode) is new
   double *G;            // N x R x R Grams (G[mode] rewritten)
@@ -139,6 +140,8 @@ struct UpdateArgs {
   double *lambda;       // R, in/out
   double *hhat;         // I x R FP64 scratch
   double *part;         // per-workgroup partials, update_part_elems(I, R) doubles
+  double *gpart;        // R <= 64: per-slice Gram tiles, norm_gpart_elems(R) doubles
+  unsigned *ticket;     // R <= 64: zero before the first launch; left at zero
   double eps;
   // error after a sweep (mode N-1 only): alpha, out pointers (may be NULL)
   const double *alpha;
@@ -146,6 +149,11 @@ struct UpdateArgs {
   double *scal;         // [0]=beta [1]=gamma [2]=raw relerr^2
 };
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st);
+// workgroups of the finish kernel (R <= 64) and the rows each one normalises
+constexpr int kNormWG = 16;
+int norm_workgroups(int64_t I, int64_t *rows_per_wg);
+// doubles of per-slice Gram tiles the finish kernel needs (R <= 64)
+int norm_gpart_elems(int R);
 int64_t update_part_elems(int64_t I, int R);
 
 // loss of [[lambda; H]] from M^(N-1): loss = 0.5 (alpha - 2 beta + gamma)

@@ -87,10 +87,18 @@ __device__ __forceinline__ void mma1(f64x4 &c, double a, double b) {
   c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// streaming loads of X through the global (not flat) address space
+// loads of X through the global (not flat) address space: gload marks them
+// non-temporal, gload_c leaves them to the normal cache policy.  Normal loads
+// let a tensor that fits the last-level cache stay there between the left
+// and the right product; for much larger tensors the left kernel streams
+// with non-temporal loads (measured faster there).
 template <typename VT> __device__ __forceinline__ VT gload(const void *p) {
   typedef const __attribute__((address_space(1))) VT gvt;
   return __builtin_nontemporal_load((gvt *)p);
+}
+template <typename VT> __device__ __forceinline__ VT gload_c(const void *p) {
+  typedef const __attribute__((address_space(1))) VT gvt;
+  return *(gvt *)p;
 }
 
 template <typename CT> __device__ __forceinline__ void czero(CT &c) {
@@ -288,14 +296,14 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        cur[u][mt] = gload<u32x4>(xp[mt] + u * KSTEP);
+        cur[u][mt] = gload_c<u32x4>(xp[mt] + u * KSTEP);
     for (int64_t b = 0; b < nb; ++b, t += U) {
       const int adv = b + 1 < nb ? U * KSTEP : 0;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          nxt[u][mt] = gload<u32x4>(xp[mt] + adv + u * KSTEP);
+          nxt[u][mt] = gload_c<u32x4>(xp[mt] + adv + u * KSTEP);
 #pragma unroll
       for (int u = 0; u < U; ++u) step(cur[u]);
 #pragma unroll
@@ -310,7 +318,7 @@ __global__ __launch_bounds__(256) void k_gemm_right_mfma(
     u32x4 va[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      va[mt] = gload<u32x4>(xp[mt]);
+      va[mt] = gload_c<u32x4>(xp[mt]);
       xp[mt] += KSTEP;
     }
     step(va);
@@ -380,7 +388,7 @@ template <> struct LoadT<8> { typedef u32x2 T; };
 __device__ __forceinline__ uint32_t dw(const u32x4 &v, int i) { return v[i]; }
 __device__ __forceinline__ uint32_t dw(const u32x2 &v, int i) { return v[i]; }
 
-template <typename XT, int QV, int NT, bool HL, bool SLOW>
+template <typename XT, int QV, int NT, bool HL, bool SLOW, bool NTL>
 __global__ __launch_bounds__(256) void k_gemm_left_mfma(
     const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
     const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int W, int64_t steps_total,
@@ -440,7 +448,8 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
       const int64_t tt = t0 + b < s_hi ? t0 + b : s_hi - 1;
 #pragma unroll
       for (int u = 0; u < KL; ++u)
-        dst[b * KL + u] = gload<LT>(xp + (tt * KSTEP + u) * m);
+        if constexpr (NTL) dst[b * KL + u] = gload<LT>(xp + (tt * KSTEP + u) * m);
+        else dst[b * KL + u] = gload_c<LT>(xp + (tt * KSTEP + u) * m);
     }
   };
   if (s_lo < s_hi) load_batch(raw, s_lo);
@@ -710,9 +719,14 @@ static void run_left(const GemmPlan &p, int R, const void *X, const void *kf, co
   typedef typename XTraits<XT>::AT AT;
   constexpr int KSTEP = 4 * XTraits<XT>::KL;
   dim3 grid((unsigned)p.tiles, p.nsplit), block(256);
-  hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW>), grid, block, p.lds_bytes, st,
-                     (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf, (int)p.W,
-                     (p.k / KSTEP), p.nsplit, R, (AT *)out);
+  if (p.nt_loads)
+    hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW, true>), grid, block, p.lds_bytes, st,
+                       (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf, (int)p.W,
+                       (p.k / KSTEP), p.nsplit, R, (AT *)out);
+  else
+    hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW, false>), grid, block, p.lds_bytes, st,
+                       (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf, (int)p.W,
+                       (p.k / KSTEP), p.nsplit, R, (AT *)out);
 }
 
 // NT dispatch (1..4) with the template flags fixed

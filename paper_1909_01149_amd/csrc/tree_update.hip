@@ -35,6 +35,20 @@ __device__ __forceinline__ HT ordered_split_sum(const HT *__restrict__ p, int ns
   return acc;
 }
 
+// Same sum with every load issued before the first add when ns <= 32.
+template <typename HT>
+__device__ __forceinline__ HT ordered_split_sum_wide(const HT *__restrict__ p, int ns, int64_t stride) {
+  if (ns > 32) return ordered_split_sum(p, ns, stride);
+  HT v[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) v[k] = k < ns ? p[(int64_t)k * stride] : (HT)0;
+  HT acc = v[0];
+#pragma unroll
+  for (int k = 1; k < 32; ++k)
+    if (k < ns) acc += v[k];
+  return acc;
+}
+
 // sum over the 64 lanes of a wave, fixed butterfly order
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -319,40 +333,22 @@ __device__ __forceinline__ double bcast(double v, int lane) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// One row per wave: lane c owns columns c + 64 u (u < CPL).
+// One row per wave, R > 64: lane c owns columns c + 64 u (u < CPL); S is
+// read from global memory (L2-resident).
 template <typename HT, int CPL>
 __global__ __launch_bounds__(256) void k_update_rows(UpdateArgs a) {
-  __shared__ double sS[64 * 64];
   __shared__ double hrow[4][256];
   __shared__ double wred[4][256];
   __shared__ double bred[4];
   __shared__ double sdiag[256];
   const int R = a.R;
-  const bool s_in_lds = R <= 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const HT *M = (const HT *)a.M;
   const HT *H = (const HT *)a.H;
   const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   const bool live = i < a.I;
-  // every global load is issued before its first use: S (or the Grams it is
-  // formed from), lambda, the row of H and the row of M
-  double sv[16];
-  if (s_in_lds) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = threadIdx.x + 256 * k;
-      double v = 0.0;
-      if (e < R * R) {
-        if (a.S) v = a.S[e];
-        else {
-          v = 1.0;
-          for (int q = 0; q < a.N; ++q)
-            if (q != a.mode) v *= a.G[(int64_t)q * R * R + e];
-        }
-      }
-      sv[k] = v;
-    }
-  }
+  // every global load is issued before its first use: lambda, the row of H
+  // and the row of M
   double hraw[CPL], lamv[CPL];
   HT mraw[CPL];
 #pragma unroll
@@ -365,18 +361,10 @@ __global__ __launch_bounds__(256) void k_update_rows(UpdateArgs a) {
 #pragma unroll
   for (int u = 0; u < CPL; ++u) {
     const int c = lane + 64 * u;
-    mraw[u] = (live && c < R) ? ordered_split_sum(M + i * R + c, a.msplit, a.mstride) : (HT)0;
+    mraw[u] = (live && c < R) ? ordered_split_sum_wide(M + i * R + c, a.msplit, a.mstride) : (HT)0;
   }
-  if (s_in_lds) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = threadIdx.x + 256 * k;
-      if (e < R * R) sS[e] = sv[k];
-    }
-  }
-  __syncthreads();
   const double *Sg = a.S;
-  auto Sv = [&](int c, int r) -> double { return s_in_lds ? sS[c * R + r] : Sg[c * R + r]; };
+  auto Sv = [&](int c, int r) -> double { return Sg[c * R + r]; };
   // HALS divisors S(r, r), read once
   for (int c = threadIdx.x; c < R; c += 256) sdiag[c] = Sv(c, c);
   double h[CPL], m[CPL], g[CPL];
@@ -459,22 +447,10 @@ __global__ __launch_bounds__(256) void k_update_rows(UpdateArgs a) {
 }
 
 template <typename HT>
-__global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblocks) {
-  __shared__ double wred[16][2];
-  __shared__ double lam_s[256];
-  __shared__ double lds[1024];
-  __shared__ double chunk[4096];
+__device__ void finish_generic(const UpdateArgs &a, int nblocks, double (*wred)[2], double *lam_s,
+                               double *lds, double *chunk) {
   const int R = a.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t IR = a.I * R;
-  // Hhat entries e = threadIdx.x + 1024 k, k < 16, loaded before anything
-  // else (entries past 16384 are read chunk by chunk below)
-  double hpre[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int64_t e = threadIdx.x + 1024 * k;
-    hpre[k] = e < IR ? a.hhat[e] : 0.0;
-  }
   // column norms and beta: one wave per column, lanes over the workgroup
   // partials, then a fixed butterfly
   for (int c = wave; c <= R; c += 16) {
@@ -491,87 +467,12 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
   for (int c = threadIdx.x; c < R; c += 1024) a.lambda[c] = lam_s[c];
   HT *H = (HT *)a.H;
   double *Gm = a.G + (int64_t)a.mode * R * R;
-  if (R <= 64) {
-    // normalise rows chunk by chunk; each normalised (stored) chunk also feeds
-    // the Gram straight from LDS.  Pairs (x, y), x <= y, in at most 3 rounds.
-    const int npairs = R * (R + 1) / 2;
-    int ns = 1;
-    while (ns * 2 * npairs <= 1024) ns *= 2;
-    const int per_round = 1024 / ns;
-    const int rounds = (npairs + per_round - 1) / per_round;
-    const int pl = threadIdx.x / ns, sl = threadIdx.x % ns;
-    int px[3], py[3];
-    double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      int p = k * per_round + pl, x = 0;
-      px[k] = py[k] = -1;
-      if (k < rounds && p < npairs) {
-        while (p >= R - x) { p -= R - x; ++x; }
-        px[k] = x;
-        py[k] = x + p;
-      }
-    }
-    const int CH = 4096 / R;
-    for (int64_t i0 = 0; i0 < a.I; i0 += CH) {
-      const int rows = (int)(a.I - i0 < CH ? a.I - i0 : CH);
-      const int ne = rows * R;
-      __syncthreads();
-      {
-        // ne <= 4096: at most four entries per thread; chunk c of 4096
-        // entries is registers 4c..4c+3 of the prefetch when c < 4
-        double hv4[4];
-        const int cidx = (int)(i0 * R / 4096);
-        if (CH * R == 4096 && cidx < 4) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (q == cidx) hv4[k] = hpre[4 * q + k];
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int e = threadIdx.x + 1024 * k;
-            hv4[k] = e < ne ? a.hhat[i0 * R + e] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int e = threadIdx.x + 1024 * k;
-          if (e < ne) {
-            const double l = lam_s[e % R];
-            const HT hv = (HT)(l > 0.0 ? hv4[k] / l : 0.0);
-            H[i0 * R + e] = hv;
-            chunk[e] = (double)hv;
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        if (px[k] >= 0) acc[k] = gram_rows(chunk, R, px[k], py[k], sl, rows, ns, acc[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      __syncthreads();
-      lds[threadIdx.x] = acc[k];
-      __syncthreads();
-      if (sl == 0 && px[k] >= 0) {
-        double v = lds[threadIdx.x];
-        for (int q = 1; q < ns; ++q) v += lds[threadIdx.x + q];
-        Gm[px[k] * R + py[k]] = v;
-        Gm[py[k] * R + px[k]] = v;
-      }
-    }
-  } else {
-    for (int64_t e = threadIdx.x; e < a.I * R; e += 1024) {
-      const double l = lam_s[e % R];
-      H[e] = (HT)(l > 0.0 ? a.hhat[e] / l : 0.0);
-    }
-    __syncthreads();
-    gram_block<HT>(H, a.I, R, Gm, lds, chunk);
+  for (int64_t e = threadIdx.x; e < a.I * R; e += 1024) {
+    const double l = lam_s[e % R];
+    H[e] = (HT)(l > 0.0 ? a.hhat[e] / l : 0.0);
   }
+  __syncthreads();
+  gram_block<HT>(H, a.I, R, Gm, lds, chunk);
   __syncthreads();
   if (a.relerr_out || a.scal) {
     double gsum = 0.0;
@@ -611,6 +512,314 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
       for (int q = 0; q < a.N; ++q)
         if (q != a.next_mode) v *= a.G[(int64_t)q * R * R + e];
       a.S_next[e] = v;
+    }
+  }
+}
+
+
+// Single-workgroup finish, used for R > 64.
+template <typename HT>
+__global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblocks) {
+  __shared__ double wred[16][2];
+  __shared__ double lam_s[256];
+  __shared__ double lds[1024];
+  __shared__ double chunk[4096];
+  finish_generic<HT>(a, nblocks, wred, lam_s, lds, chunk);
+}
+
+// ---------------------------------------------------------------------------
+// Row update for R <= RB <= 64: one row per wave, lane c owns column c and
+// keeps column c of S in registers.  HALS (Alg 2) visits the columns in
+// order; at step r every lane forms its candidate, the value of lane r is
+// broadcast and every lane folds the change into its entry of the gradient,
+// so a step costs a few dependent instructions.  The HALS quotient uses the
+// reciprocal of S(r, r) (within one rounding of the quotient).
+template <typename HT, int RB>
+__global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
+  __shared__ double wred[4][64];
+  __shared__ double bred[4];
+  const int R = a.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const HT *M = (const HT *)a.M;
+  const HT *H = (const HT *)a.H;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  const bool live = i < a.I;
+  const bool own = lane < R;
+  const int c = own ? lane : 0;
+  // every load first: column c of S, S(c, c), lambda, the entries of H and M
+  double sc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) sc[r] = (own && r < R) ? a.S[r * R + c] : 0.0;
+  const double d = own ? a.S[c * R + c] : 0.0;
+  const double lam = own ? a.lambda[c] : 0.0;
+  const double hraw = (live && own) ? (double)H[i * R + c] : 0.0;
+  const HT mraw = (live && own) ? ordered_split_sum_wide(M + i * R + c, a.msplit, a.mstride) : (HT)0;
+  double h = hraw * lam;
+  const double m = (double)mraw;
+  // g = (Hhat S)(i, c), j in order
+  double g = 0.0;
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+    if (j < R) g += bcast(h, j) * sc[j];
+  if (a.algo == NNCP_MU) {
+    h = h * m / (g + a.eps);
+  } else {
+    g = m - g;
+    const bool pos = d > 0.0;
+    const double invd = pos ? 1.0 / d : 0.0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (r < R) {
+        double v = h + g * invd;
+        v = v > 0.0 ? v : 0.0;
+        const double dl = pos ? v - h : 0.0;
+        const double delta = bcast(dl, r);
+        if (lane == r && pos) h = v;
+        g -= delta * sc[r];
+      }
+    }
+  }
+  double sq = 0.0, beta = 0.0;
+  if (live && own) {
+    a.hhat[i * R + c] = h;
+    sq = h * h;
+    beta = m * h;
+  }
+  wred[wave][lane] = sq;
+  beta = wave_sum(beta);
+  if (lane == 0) bred[wave] = beta;
+  __syncthreads();
+  // per-workgroup partials (the 4 rows added in wave order)
+  double *cpart = a.part + (int64_t)blockIdx.x * (R + 1);
+  if (threadIdx.x < R)
+    cpart[threadIdx.x] = wred[0][threadIdx.x] + wred[1][threadIdx.x] + wred[2][threadIdx.x] +
+                         wred[3][threadIdx.x];
+  if (threadIdx.x == 0) cpart[R] = bred[0] + bred[1] + bred[2] + bred[3];
+}
+
+// Upper tiles (tx <= ty) of the T x T grid of 16 x 16 tiles of an R x R
+// matrix, T = ceil(R / 16), in row-major order.
+__device__ __forceinline__ void tile_pair(int t, int T, int &tx, int &ty) {
+  int q = t, r = 0;
+  while (q >= T - r) { q -= T - r; ++r; }
+  tx = r;
+  ty = r + q;
+}
+
+int norm_gpart_elems(int R) {
+  const int T = (R + 15) / 16;
+  return kNormWG * (T * (T + 1) / 2) * 256;
+}
+
+// Finish of the update for R <= RB <= 64, spread over a few workgroups.
+// Every workgroup adds the row kernel's per-workgroup partials itself (the
+// same order everywhere, so all hold the same lambda and beta), normalises
+// its slice of rows and writes the Gram of that slice (FP64 MFMA over the
+// stored, rounded values; upper 16 x 16 tiles).  The workgroup that takes the
+// last ticket (a counter it resets for the next launch) adds the slices'
+// Grams in workgroup order and forms gamma and the next mode's S.
+template <typename HT, int RB>
+__global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, int64_t rpw) {
+  constexpr int SL = (RB * RB + 255) / 256;       // R x R entries per thread
+  constexpr int TB = RB / 16;                     // tile grid bound
+  constexpr int TW = (TB * (TB + 1) / 2 + 3) / 4; // tiles per wave
+  __shared__ double rowbuf[4096];
+  __shared__ double colsum[256];
+  __shared__ double lam_s[64];
+  __shared__ double wred[4];
+  __shared__ double beta_s;
+  __shared__ int last_s;
+  const int R = a.R, RR = R * R;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nct = R + 1, tpc = 256 / nct;
+  const int pc = tid % nct, pj = tid / nct;
+  const bool pl = pj < tpc;
+  const int64_t r0 = (int64_t)blockIdx.x * rpw;
+  const int64_t r1 = a.I < r0 + rpw ? a.I : r0 + rpw;
+  const int CHR = 4096 / R;
+  const int T = (R + 15) / 16, ntile = T * (T + 1) / 2;
+  const bool want_err = a.relerr_out || a.scal;
+  // ---- loads first: the row kernel's partials (consecutive threads read
+  // consecutive entries), the first chunk of Hhat, S of this mode and the
+  // Grams the next mode's S is formed from
+  double pp[32], hv[16], sv[SL], pn[SL];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int b = pj + k * tpc;
+    pp[k] = (pl && b < nblocks) ? a.part[(int64_t)b * nct + pc] : 0.0;
+  }
+  const int rows0 = (int)(r1 - r0 < CHR ? r1 - r0 : CHR);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = tid + 256 * k;
+    hv[k] = e < rows0 * R ? a.hhat[r0 * R + e] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < SL; ++k) {
+    const int e = tid + 256 * k;
+    sv[k] = (want_err && e < RR) ? a.S[e] : 0.0;
+    pn[k] = 1.0;
+  }
+  if (a.S_next) {
+    for (int q = 0; q < a.N; ++q) {
+      if (q == a.mode || q == a.next_mode) continue;
+      double gq[SL];
+#pragma unroll
+      for (int k = 0; k < SL; ++k) {
+        const int e = tid + 256 * k;
+        gq[k] = e < RR ? a.G[(int64_t)q * RR + e] : 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < SL; ++k) pn[k] *= gq[k];
+    }
+  }
+  // ---- lambda (column norms) and beta
+  {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if (pl && pj + k * tpc < nblocks) acc += pp[k];
+    for (int b = pj + 32 * tpc; pl && b < nblocks; b += tpc) acc += a.part[(int64_t)b * nct + pc];
+    colsum[tid] = acc;
+  }
+  __syncthreads();
+  if (tid < nct) {
+    double sum = 0.0;
+    for (int j = 0; j < tpc; ++j) sum += colsum[j * nct + tid];
+    if (tid < R) lam_s[tid] = sqrt(sum);
+    else beta_s = sum;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && tid < R) a.lambda[tid] = lam_s[tid];
+  // ---- normalise the slice chunk by chunk; Gram tiles of the stored values
+  HT *H = (HT *)a.H;
+  f64x4 acc[TW];
+  int tx[TW], ty[TW];
+#pragma unroll
+  for (int s = 0; s < TW; ++s) {
+    acc[s][0] = acc[s][1] = acc[s][2] = acc[s][3] = 0.0;
+    tx[s] = ty[s] = -1;
+    const int t = wave + 4 * s;
+    if (t < ntile) tile_pair(t, T, tx[s], ty[s]);
+  }
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int64_t c0 = r0; c0 < r1; c0 += CHR) {
+    const int rows = (int)(r1 - c0 < CHR ? r1 - c0 : CHR);
+    const int ne = rows * R;
+    if (c0 != r0) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k;
+        hv[k] = e < ne ? a.hhat[c0 * R + e] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k;
+      if (e < ne) {
+        const double l = lam_s[e % R];
+        const HT h = (HT)(l > 0.0 ? hv[k] / l : 0.0);
+        H[c0 * R + e] = h;
+        rowbuf[e] = (double)h;
+      }
+    }
+    __syncthreads();
+    // C(x, y) += sum_k rowbuf(k, 16 tx + x) rowbuf(k, 16 ty + y), four rows a step
+#pragma unroll
+    for (int s = 0; s < TW; ++s) {
+      if (tx[s] < 0) continue;
+      const int cx = 16 * tx[s] + lc, cy = 16 * ty[s] + lc;
+      for (int k0 = 0; k0 < rows; k0 += 4) {
+        const int kr = k0 + lr;
+        const double av = (kr < rows && cx < R) ? rowbuf[kr * R + cx] : 0.0;
+        const double bv = (kr < rows && cy < R) ? rowbuf[kr * R + cy] : 0.0;
+        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[s], 0, 0, 0);
+      }
+    }
+  }
+  // result entry (lr + 4 v, lc) of each tile
+  double *gp = a.gpart + (int64_t)blockIdx.x * ntile * 256;
+#pragma unroll
+  for (int s = 0; s < TW; ++s) {
+    if (tx[s] < 0) continue;
+    const int t = wave + 4 * s;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gp[t * 256 + (lr + 4 * v) * 16 + lc] = acc[s][v];
+  }
+  // ---- ticket: the last workgroup to arrive sees every slice's Gram
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last_s = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  const int nw = gridDim.x;
+  double *Gm = a.G + (int64_t)a.mode * RR;
+  double *Gs = rowbuf;  // the chunks are done (barrier above)
+  // entry e of tile t = e / 256 (x = (e / 16) % 16, y = e % 16), slices added
+  // in workgroup order; upper entries of diagonal tiles give both halves
+  for (int e0 = 0; e0 < ntile * 256; e0 += 512) {
+    double v[2][kNormWG];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int e = e0 + tid + 256 * kk;
+#pragma unroll
+      for (int w = 0; w < kNormWG; ++w)
+        v[kk][w] = (e < ntile * 256 && w < nw) ? a.gpart[(int64_t)w * ntile * 256 + e] : 0.0;
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int e = e0 + tid + 256 * kk;
+      if (e >= ntile * 256) continue;
+      double sum = v[kk][0];
+#pragma unroll
+      for (int w = 1; w < kNormWG; ++w)
+        if (w < nw) sum += v[kk][w];
+      int bx, by;
+      tile_pair(e >> 8, T, bx, by);
+      const int x = (e >> 4) & 15, y = e & 15;
+      const int gx = 16 * bx + x, gy = 16 * by + y;
+      if (gx < R && gy < R && (bx != by || x <= y)) {
+        Gm[gx * R + gy] = sum;
+        Gm[gy * R + gx] = sum;
+        Gs[gx * R + gy] = sum;
+        Gs[gy * R + gx] = sum;
+      }
+    }
+  }
+  if (tid == 0) atomicExch(a.ticket, 0u);
+  __syncthreads();
+  if (want_err) {
+    double gsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+      const int e = tid + 256 * k;
+      if (e < RR) gsum += lam_s[e / R] * sv[k] * Gs[e] * lam_s[e % R];
+    }
+    const double v = wave_sum(gsum);
+    if (lane == 0) wred[wave] = v;
+    __syncthreads();
+    if (tid == 0) {
+      const double gamma = wred[0] + wred[1] + wred[2] + wred[3];
+      const double beta = beta_s;
+      const double alpha = a.alpha ? a.alpha[0] : 0.0;
+      const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+      if (a.scal) {
+        a.scal[0] = beta;
+        a.scal[1] = gamma;
+        a.scal[2] = e2;
+      }
+      if (a.relerr_out) a.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
+    }
+  }
+  // S of the next mode, written after every read of this mode's S (the two
+  // may share a buffer; this mode's S was read at the start)
+  if (a.S_next) {
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+      const int e = tid + 256 * k;
+      if (e < RR) a.S_next[e] = a.next_mode == a.mode ? pn[k] : pn[k] * Gs[e];
     }
   }
 }
@@ -883,11 +1092,33 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
   const int rpb = update_rows_per_block(a.R);
   const int nb = (int)((a.I + rpb - 1) / rpb);
   dim3 grid(nb), block(256);
-  if (a.R <= 64) hipLaunchKernelGGL((k_update_rows<HT, 1>), grid, block, 0, st, a);
-  else if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
-  else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
-  hipLaunchKernelGGL((k_update_finish<HT>), dim3(1), dim3(1024), 0, st, a, nb);
+  if (a.R <= 64) {
+    int64_t rpw;
+    const int nw = norm_workgroups(a.I, &rpw);
+    if (a.R <= 16) {
+      hipLaunchKernelGGL((k_update_rows_small<HT, 16>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_update_norm<HT, 16>), dim3(nw), dim3(256), 0, st, a, nb, rpw);
+    } else if (a.R <= 32) {
+      hipLaunchKernelGGL((k_update_rows_small<HT, 32>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_update_norm<HT, 32>), dim3(nw), dim3(256), 0, st, a, nb, rpw);
+    } else {
+      hipLaunchKernelGGL((k_update_rows_small<HT, 64>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_update_norm<HT, 64>), dim3(nw), dim3(256), 0, st, a, nb, rpw);
+    }
+  } else {
+    if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_update_finish<HT>), dim3(1), dim3(1024), 0, st, a, nb);
+  }
   return hipGetLastError();
+}
+
+int norm_workgroups(int64_t I, int64_t *rows_per_wg) {
+  int64_t nw = (I + 15) / 16;
+  nw = nw < 1 ? 1 : (nw > kNormWG ? kNormWG : nw);
+  const int64_t rpw = (I + nw - 1) / nw;
+  if (rows_per_wg) *rows_per_wg = rpw;
+  return (int)((I + rpw - 1) / rpw);
 }
 
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st) {
