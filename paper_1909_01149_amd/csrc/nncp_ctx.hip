@@ -228,7 +228,7 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   for (int side = 0; side < 2; ++side) {
     const int lo = side == 0 ? 0 : S, hi = side == 0 ? S : N;
     for (int a = lo; a < hi - 1; ++a)
-      part = std::max(part, mttv_strided_part_elems(L.dims[a], L.dims + a + 1, hi - a - 1, R));
+      part = std::max(part, mttv_strided_part_elems(L.hdt, L.dims[a], L.dims + a + 1, hi - a - 1, R));
   }
   L.part_elems = part;
   L.kfast_elems = 0;

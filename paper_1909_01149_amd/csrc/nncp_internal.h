@@ -112,7 +112,7 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
 hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
                                const void *const *Hq, int R, void *M, void *part,
                                int64_t part_elems, hipStream_t st, int *nsplit_out);
-int64_t mttv_strided_part_elems(int64_t Ia, const int64_t *qdims, int nq, int R);
+int64_t mttv_strided_part_elems(int hdt, int64_t Ia, const int64_t *qdims, int nq, int R);
 
 // Gram G = H^T H (FP64) for one factor; single workgroup.
 hipError_t launch_gram(int hdt, const void *H, int64_t I, int R, double *G, hipStream_t st);

@@ -116,6 +116,56 @@ __global__ __launch_bounds__(256) void k_mttv_contig_wide(const HT *__restrict__
   }
 }
 
+// Same reduction for Ia % V == 0 and Ia <= 64 V CPL: a wave owns QB = 16 / CPL
+// outputs (q, r).  Each lane issues its loads of the QB rows of T first, the
+// workgroup then stages H(:, r) in LDS, and the products are added in the
+// order of the kernel above; a workgroup costs one memory round trip.
+template <typename HT, int CPL>
+__global__ __launch_bounds__(256) void k_mttv_contig_reg(const HT *__restrict__ T, int64_t Ia,
+                                                         int64_t Q, int R, const HT *__restrict__ H,
+                                                         HT *__restrict__ out, int leaf) {
+  constexpr int V = 16 / (int)sizeof(HT);
+  constexpr int QB = 16 / CPL;
+  typedef HT vt __attribute__((ext_vector_type(V)));
+  __shared__ vt hs[64 * CPL];
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t qb = ((int64_t)blockIdx.y * 4 + wave) * QB;
+  const int64_t nv = Ia / V;
+  const HT *Tr = T + (int64_t)r * Ia * Q;
+  vt x[QB][CPL];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    const int64_t q = qb + j < Q ? qb + j : Q - 1;
+    const vt *t = reinterpret_cast<const vt *>(Tr + Ia * q);
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int64_t cv = lane + 64 * u;
+      x[j][u] = t[cv < nv ? cv : 0];
+    }
+  }
+  HT *hsf = reinterpret_cast<HT *>(hs);
+  for (int64_t i = threadIdx.x; i < Ia; i += 256) hsf[i] = H[i * R + r];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    HT acc = 0;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (lane + 64 * u < nv) {
+        const vt hv = hs[lane + 64 * u];
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc += x[j][u][e] * hv[e];
+      }
+    acc = wave_sum(acc);
+    const int64_t q = qb + j;
+    if (lane == 0 && q < Q) {
+      if (leaf) out[q * R + r] = acc;
+      else out[(int64_t)r * Q + q] = acc;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // multi-TTV, strided reduction keeping the first mode:
 //   part[z][i][r] = sum_{q in split z} T[r][i + Ia q] K(q, r),
@@ -130,19 +180,23 @@ struct StridedArgs {
   int R, IT, QS, nsplit;
 };
 
-template <typename HT>
+template <typename HT, int V>
 __global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, StridedArgs a,
                                                       HT *__restrict__ part) {
-  __shared__ HT red[256];
+  typedef HT vt __attribute__((ext_vector_type(V)));
+  __shared__ vt red[256];
   __shared__ HT kq[1024];
   const int il = threadIdx.x % a.IT, qs = threadIdx.x / a.IT;
-  const int64_t i = (int64_t)blockIdx.x * a.IT + il;
+  const int64_t i0 = ((int64_t)blockIdx.x * a.IT + il) * V;
+  const bool live = i0 < a.Ia;
   const int r = blockIdx.y;
   const int64_t z = blockIdx.z;
   const int64_t q0 = a.Q * z / a.nsplit, q1 = a.Q * (z + 1) / a.nsplit;
   const HT *const *H = (const HT *const *)a.H;
-  const HT *t = T + (int64_t)r * a.Ia * a.Q + (i < a.Ia ? i : 0);
-  HT acc = 0;
+  const HT *t = T + (int64_t)r * a.Ia * a.Q + (live ? i0 : 0);
+  const int64_t Ia = a.Ia;
+  const int QS = a.QS;
+  vt acc = (vt)0;
   for (int64_t c0 = q0; c0 < q1; c0 += 1024) {
     const int cn = (int)(q1 - c0 < 1024 ? q1 - c0 : 1024);
     __syncthreads();
@@ -157,18 +211,26 @@ __global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, 
       kq[e] = kv;
     }
     __syncthreads();
-    if (i < a.Ia) {
+    if (live) {
+      // eight rows of T in flight, then their products in q order
       int e = qs;
-#pragma unroll 4
-      for (; e < cn; e += a.QS) acc += t[a.Ia * (c0 + e)] * kq[e];
+      for (; e + 7 * QS < cn; e += 8 * QS) {
+        vt x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = *reinterpret_cast<const vt *>(t + Ia * (c0 + e + u * QS));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += x[u] * kq[e + u * QS];
+      }
+      for (; e < cn; e += QS) acc += *reinterpret_cast<const vt *>(t + Ia * (c0 + e)) * kq[e];
     }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  if (qs == 0 && i < a.Ia) {
-    HT s = red[il];
-    for (int k = 1; k < a.QS; ++k) s += red[k * a.IT + il];
-    part[(z * a.Ia + i) * a.R + r] = s;
+  if (qs == 0 && live) {
+    vt sum = red[il];
+    for (int k = 1; k < QS; ++k) sum += red[k * a.IT + il];
+#pragma unroll
+    for (int v = 0; v < V; ++v) part[(z * Ia + i0 + v) * a.R + r] = sum[v];
   }
 }
 
@@ -546,16 +608,34 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   const bool live = i < a.I;
   const bool own = lane < R;
   const int c = own ? lane : 0;
-  // every load first: column c of S, S(c, c), lambda, the entries of H and M
+  const int64_t ir = live ? i : a.I - 1;
+  // every load is issued before any value is used (addresses clamped into
+  // range instead of branching): the split partials of M, column c of S,
+  // S(c, c), lambda and the entry of H
+  const int ns = a.msplit;
+  const HT *mp = M + ir * R + c;
+  HT mv[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) mv[k] = k < ns ? mp[(int64_t)k * a.mstride] : (HT)0;
   double sc[RB];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) sc[r] = (own && r < R) ? a.S[r * R + c] : 0.0;
-  const double d = own ? a.S[c * R + c] : 0.0;
-  const double lam = own ? a.lambda[c] : 0.0;
-  const double hraw = (live && own) ? (double)H[i * R + c] : 0.0;
-  const HT mraw = (live && own) ? ordered_split_sum_wide(M + i * R + c, a.msplit, a.mstride) : (HT)0;
-  double h = hraw * lam;
-  const double m = (double)mraw;
+  for (int r = 0; r < RB; ++r) sc[r] = r < R ? a.S[r * R + c] : 0.0;
+  const double d_raw = a.S[c * R + c];
+  const double lam_raw = a.lambda[c];
+  const HT h_raw = H[ir * R + c];
+  HT macc = mv[0];
+#pragma unroll
+  for (int k = 1; k < 32; ++k)
+    if (k < ns) macc += mv[k];
+  for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
+  const bool ok = live && own;
+  if (!own) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) sc[r] = 0.0;
+  }
+  const double d = own ? d_raw : 0.0;
+  double h = ok ? (double)h_raw * lam_raw : 0.0;
+  const double m = ok ? (double)macc : 0.0;
   // g = (Hhat S)(i, c), j in order
   double g = 0.0;
 #pragma unroll
@@ -643,6 +723,7 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
   // consecutive entries), the first chunk of Hhat, S of this mode and the
   // Grams the next mode's S is formed from
   double pp[32], hv[16], sv[SL], pn[SL];
+  const double alpha = (want_err && a.alpha) ? a.alpha[0] : 0.0;
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int b = pj + k * tpc;
@@ -725,16 +806,22 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
       }
     }
     __syncthreads();
-    // C(x, y) += sum_k rowbuf(k, 16 tx + x) rowbuf(k, 16 ty + y), four rows a step
+    // C(x, y) += sum_k rowbuf(k, 16 tx + x) rowbuf(k, 16 ty + y), four rows a
+    // step; the operands of eight steps are read before their products
 #pragma unroll
     for (int s = 0; s < TW; ++s) {
       if (tx[s] < 0) continue;
       const int cx = 16 * tx[s] + lc, cy = 16 * ty[s] + lc;
-      for (int k0 = 0; k0 < rows; k0 += 4) {
-        const int kr = k0 + lr;
-        const double av = (kr < rows && cx < R) ? rowbuf[kr * R + cx] : 0.0;
-        const double bv = (kr < rows && cy < R) ? rowbuf[kr * R + cy] : 0.0;
-        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[s], 0, 0, 0);
+      for (int k0 = 0; k0 < rows; k0 += 32) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int kr = k0 + 4 * u + lr;
+          av[u] = (kr < rows && cx < R) ? rowbuf[kr * R + cx] : 0.0;
+          bv[u] = (kr < rows && cy < R) ? rowbuf[kr * R + cy] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc[s], 0, 0, 0);
       }
     }
   }
@@ -803,7 +890,6 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
     if (tid == 0) {
       const double gamma = wred[0] + wred[1] + wred[2] + wred[3];
       const double beta = beta_s;
-      const double alpha = a.alpha ? a.alpha[0] : 0.0;
       const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
       if (a.scal) {
         a.scal[0] = beta;
@@ -980,6 +1066,31 @@ __global__ __launch_bounds__(256) void k_pgd_trial(int64_t n, const HT *__restri
 hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R, const void *H,
                               void *out, int leaf, hipStream_t st) {
   const int V = hdt == NNCP_F64 ? 2 : 4;
+  if (Ia % V == 0 && Ia <= 8 * 64 * V) {
+    const int CPL = Ia <= 64 * V ? 1 : Ia <= 128 * V ? 2 : Ia <= 256 * V ? 4 : 8;
+    const int QB = 16 / CPL;
+    dim3 grid((unsigned)R, (unsigned)((Q + 4 * QB - 1) / (4 * QB))), block(256);
+#define NNCP_CONTIG_REG(HTV, C)                                                            \
+  hipLaunchKernelGGL((k_mttv_contig_reg<HTV, C>), grid, block, 0, st, (const HTV *)T, Ia, Q, R, \
+                     (const HTV *)H, (HTV *)out, leaf)
+    if (hdt == NNCP_F64) {
+      switch (CPL) {
+        case 1: NNCP_CONTIG_REG(double, 1); break;
+        case 2: NNCP_CONTIG_REG(double, 2); break;
+        case 4: NNCP_CONTIG_REG(double, 4); break;
+        default: NNCP_CONTIG_REG(double, 8); break;
+      }
+    } else {
+      switch (CPL) {
+        case 1: NNCP_CONTIG_REG(float, 1); break;
+        case 2: NNCP_CONTIG_REG(float, 2); break;
+        case 4: NNCP_CONTIG_REG(float, 4); break;
+        default: NNCP_CONTIG_REG(float, 8); break;
+      }
+    }
+#undef NNCP_CONTIG_REG
+    return hipGetLastError();
+  }
   if (Ia >= 64 && Ia <= 8192 && Ia % V == 0 && (hdt != NNCP_F64 || Ia <= 4096)) {
     // about 2048 workgroups, at least 4 outputs (one per wave) each
     int64_t qper = (Q * R + 2047) / 2048;
@@ -1007,11 +1118,18 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
   return hipGetLastError();
 }
 
-static void strided_shape(int64_t Ia, int64_t Q, int R, int &IT, int &QS, int &ns, int64_t &gx) {
+// vector width of the strided kernel: 16-byte loads when Ia allows them
+static int strided_vec(int hdt, int64_t Ia) {
+  const int V = hdt == NNCP_F64 ? 2 : 4;
+  return Ia % V == 0 ? V : 1;
+}
+
+static void strided_shape(int64_t Ia, int V, int64_t Q, int R, int &IT, int &QS, int &ns,
+                          int64_t &gx) {
   IT = 1;
-  while (IT < 256 && IT < Ia) IT *= 2;
+  while (IT < 256 && IT * V < Ia) IT *= 2;
   QS = 256 / IT;
-  gx = (Ia + IT - 1) / IT;
+  gx = (Ia + (int64_t)IT * V - 1) / ((int64_t)IT * V);
   int64_t want = (512 + gx * R - 1) / (gx * R);
   int64_t maxs = (Q + QS - 1) / QS;
   if (want > maxs) want = maxs;
@@ -1020,12 +1138,12 @@ static void strided_shape(int64_t Ia, int64_t Q, int R, int &IT, int &QS, int &n
   ns = (int)want;
 }
 
-int64_t mttv_strided_part_elems(int64_t Ia, const int64_t *qdims, int nq, int R) {
+int64_t mttv_strided_part_elems(int hdt, int64_t Ia, const int64_t *qdims, int nq, int R) {
   int64_t Q = 1;
   for (int k = 0; k < nq; ++k) Q *= qdims[k];
   int IT, QS, ns;
   int64_t gx;
-  strided_shape(Ia, Q, R, IT, QS, ns, gx);
+  strided_shape(Ia, strided_vec(hdt, Ia), Q, R, IT, QS, ns, gx);
   return (int64_t)ns * Ia * R;
 }
 
@@ -1041,18 +1159,25 @@ hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t
   }
   a.nq = nq; a.Ia = Ia; a.Q = Q; a.R = R;
   int64_t gx;
-  strided_shape(Ia, Q, R, a.IT, a.QS, a.nsplit, gx);
+  const int V = strided_vec(hdt, Ia);
+  strided_shape(Ia, V, Q, R, a.IT, a.QS, a.nsplit, gx);
   if ((int64_t)a.nsplit * Ia * R > part_elems) return hipErrorInvalidValue;
   dim3 grid((unsigned)gx, R, a.nsplit), block(256);
   const int64_t n = Ia * R;
   dim3 g2((unsigned)((n + 255) / 256));
   if (nsplit_out) *nsplit_out = a.nsplit;
   if (hdt == NNCP_F64) {
-    hipLaunchKernelGGL(k_mttv_strided<double>, grid, block, 0, st, (const double *)T, a, (double *)part);
+    if (V == 2)
+      hipLaunchKernelGGL((k_mttv_strided<double, 2>), grid, block, 0, st, (const double *)T, a, (double *)part);
+    else
+      hipLaunchKernelGGL((k_mttv_strided<double, 1>), grid, block, 0, st, (const double *)T, a, (double *)part);
     if (M)
       hipLaunchKernelGGL(k_sum_splits<double>, g2, dim3(256), 0, st, (const double *)part, n, a.nsplit, (double *)M);
   } else {
-    hipLaunchKernelGGL(k_mttv_strided<float>, grid, block, 0, st, (const float *)T, a, (float *)part);
+    if (V == 4)
+      hipLaunchKernelGGL((k_mttv_strided<float, 4>), grid, block, 0, st, (const float *)T, a, (float *)part);
+    else
+      hipLaunchKernelGGL((k_mttv_strided<float, 1>), grid, block, 0, st, (const float *)T, a, (float *)part);
     if (M)
       hipLaunchKernelGGL(k_sum_splits<float>, g2, dim3(256), 0, st, (const float *)part, n, a.nsplit, (float *)M);
   }
@@ -1095,16 +1220,17 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
   if (a.R <= 64) {
     int64_t rpw;
     const int nw = norm_workgroups(a.I, &rpw);
+#define NNCP_UPDATE_SMALL(RBV)                                                \
+  hipLaunchKernelGGL((k_update_rows_small<HT, RBV>), grid, block, 0, st, a); \
+  hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw)
     if (a.R <= 16) {
-      hipLaunchKernelGGL((k_update_rows_small<HT, 16>), grid, block, 0, st, a);
-      hipLaunchKernelGGL((k_update_norm<HT, 16>), dim3(nw), dim3(256), 0, st, a, nb, rpw);
+      NNCP_UPDATE_SMALL(16);
     } else if (a.R <= 32) {
-      hipLaunchKernelGGL((k_update_rows_small<HT, 32>), grid, block, 0, st, a);
-      hipLaunchKernelGGL((k_update_norm<HT, 32>), dim3(nw), dim3(256), 0, st, a, nb, rpw);
+      NNCP_UPDATE_SMALL(32);
     } else {
-      hipLaunchKernelGGL((k_update_rows_small<HT, 64>), grid, block, 0, st, a);
-      hipLaunchKernelGGL((k_update_norm<HT, 64>), dim3(nw), dim3(256), 0, st, a, nb, rpw);
+      NNCP_UPDATE_SMALL(64);
     }
+#undef NNCP_UPDATE_SMALL
   } else {
     if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
