@@ -138,6 +138,126 @@ def cpu_baseline(X32, H0, algo_oracle, nthreads):
 
 
 # ---------------------------------------------------------------------------
+# the other workloads (parity cases of the test suite), timed on request:
+# `python bench.py --configs c1,c3,c4,c5` writes one JSON object per line to
+# stdout; the default run is unaffected
+# ---------------------------------------------------------------------------
+
+def _side_bytes(dims, R, xbytes, S, side):
+    import math
+    I = math.prod(dims)
+    rows = math.prod(dims[:S]) if side == 0 else math.prod(dims[S:])
+    return I * xbytes + rows * R * 4
+
+
+def _timed_sweeps(nn, torch, ctx, algo, n):
+    """n sweeps as one graph replay (rate), then the same count eagerly with
+    per-launch events (per-kernel means); returns rate, relerr, category times."""
+    dev = ctx.X.device
+    ctx.sweep(algo, 1)
+    rel = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx.capture(algo, n, rel)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.sweep(algo, n, rel)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rel_list = rel.cpu().tolist()
+    ctx.timers_enable(True)
+    ctx.sweep(algo, n)
+    torch.cuda.synchronize()
+    cat_ms, cat_n = ctx.timers_read()
+    ctx.timers_enable(False)
+    return ms / n, rel_list, cat_ms, cat_n
+
+
+def _gemm_rates(dims, R, xbytes, S, cat_ms, cat_n):
+    out = {}
+    for side, name in ((0, "gemm_left"), (1, "gemm_right")):
+        if cat_n[side]:
+            avg = cat_ms[side] / cat_n[side]
+            out[name] = {"avg_ms": avg, "GBps": _side_bytes(dims, R, xbytes, S, side) / (avg / 1e3) / 1e9}
+    return out
+
+
+def run_configs(names):
+    import torch
+    import nncp_inputs as gen
+    import paper_1909_01149_amd as nn
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    for name in names:
+        log(f"config {name}")
+        if name == "c1":
+            w = gen.workload1()
+            X = torch.from_numpy(w["X"]).to(dev)
+            H = [torch.from_numpy(h).to(dev) for h in w["H0"]]
+            ctx = nn.Context(X, H)
+            mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, nn.NNCP_MU, 20)
+            res = dict(config="c1", workload=w["name"], sweeps=20, ms_per_sweep=mps,
+                       sweeps_per_s=1e3 / mps, final_relerr=rel[-1],
+                       **_gemm_rates(w["dims"], w["R"], 8, ctx.split(), cm, cn))
+            ctx.close()
+        elif name == "c3":
+            w = gen.workload3()
+            H = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+            ctx = nn.Context(w["X"], H)
+            n = 5
+            mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, nn.NNCP_HALS, n)
+            res = dict(config="c3", workload=w["name"], sweeps=n, ms_per_sweep=mps,
+                       sweeps_per_s=1e3 / mps, relerr=rel,
+                       **_gemm_rates(w["dims"], w["R"], 2, ctx.split(), cm, cn))
+            ctx.close()
+            del w
+        elif name == "c4":
+            w = gen.workload4()
+            H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+            res = dict(config="c4", workload=w["name"], sweeps=30)
+            for algo, an in ((nn.NNCP_MU, "mu"), (nn.NNCP_HALS, "hals")):
+                ctx = nn.Context(w["X"], [h.clone() for h in H0])
+                mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, algo, 30)
+                res[an] = dict(ms_per_sweep=mps, sweeps_per_s=1e3 / mps, final_relerr=rel[-1],
+                               **_gemm_rates(w["dims"], w["R"], 2, ctx.split(), cm, cn))
+                ctx.close()
+            del w
+        elif name == "c5":
+            w = gen.workload5(keep_bf16=True)
+            H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+            res = dict(config="c5", workload=w["name"])
+            for form in ("X32", "Xbf16"):
+                ctx = nn.Context(w[form], [h.clone() for h in H0])
+                grads, loss = ctx.grad()
+                torch.cuda.synchronize()
+                reps = 10
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    ctx.grad(grads, loss)
+                e1.record()
+                torch.cuda.synchronize()
+                gms = e0.elapsed_time(e1) / reps
+                L0 = float(loss.item())
+                t0 = time.perf_counter()
+                lh, eh = ctx.pgd(100)
+                torch.cuda.synchronize()
+                pgd_s = time.perf_counter() - t0
+                res[form] = dict(ms_per_gradient=gms, gradients_per_s=1e3 / gms,
+                                 bytes_per_gradient_GBps=(w[form].numel() * w[form].element_size()
+                                                          * 2 / (gms / 1e3) / 1e9),
+                                 loss0=L0, loss_after_100_pgd=float(lh[-1]),
+                                 pgd_100_steps_s=pgd_s,
+                                 accepted_steps=int(sum(1 for e in eh if e > 0)))
+                ctx.close()
+            del w
+        else:
+            raise SystemExit(f"unknown config {name}")
+        print(json.dumps(res), flush=True)
+        torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
 # counter summaries for profiles/ (run on the CSVs that rocprofv3 wrote)
 # ---------------------------------------------------------------------------
 
@@ -231,6 +351,9 @@ def main():
                  "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe")
         cmd_w = cmd_f.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_fetch", "pmc_write").replace("-o f", "-o w")
         summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w)
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--configs":
+        run_configs(sys.argv[2].split(","))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
