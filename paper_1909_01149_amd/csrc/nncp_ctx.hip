@@ -151,7 +151,10 @@ void plan_side(Layout &L, int side) {
       ns = std::min<int64_t>(ns, 4096);
       p.nsplit = (int)std::max<int64_t>(ns, 1);
     } else {
-      p.lds_bytes = stage;
+      // the epilogue stages 16 result columns of each wave's 16 QV columns
+      // of T (rows padded by 16 bytes) in the same LDS
+      const size_t epi = (size_t)4 * 16 * (16 * QV * hs + 16);
+      p.lds_bytes = std::max(stage, epi);
       p.tiles = (p.m + 64 * QV - 1) / (64 * QV);
       const int64_t steps = p.k / KSTEP;
       // no split (T written straight into the node) when the columns alone

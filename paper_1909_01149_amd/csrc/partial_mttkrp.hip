@@ -437,11 +437,14 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) { czero(acc[q][nt]); czero(blk[q][nt]); }
 
-  // Steps are taken in batches of SB (SB * KL rows per lane: 8 loads), the
-  // next batch loaded before the current one is consumed.  Steps past the end
-  // of the range re-load the last valid step and are not computed.
+  // Steps are taken in batches of SB (SB * KL rows per lane: 8 loads).  NB
+  // batch buffers rotate with the loop unrolled over them, so the loads of
+  // the next NB - 1 batches are in flight while a batch is consumed and no
+  // register copy waits for them.  Steps past the end of the range re-load
+  // the last valid step and are not computed.
   constexpr int SB = KL == 8 ? 1 : 8;
-  LT raw[SB * KL], nxt[SB * KL];
+  constexpr int NB = 3;
+  LT buf[NB][SB * KL];
   auto load_batch = [&](LT *dst, int64_t t0) {
 #pragma unroll
     for (int b = 0; b < SB; ++b) {
@@ -452,98 +455,135 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
         else dst[b * KL + u] = gload_c<LT>(xp + (tt * KSTEP + u) * m);
     }
   };
-  if (s_lo < s_hi) load_batch(raw, s_lo);
+  if (s_lo < s_hi) {
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) load_batch(buf[j], s_lo + j * SB);
+  }
   // position in the fast block, window index and block index, advanced with
   // the steps (one division at the start)
   int pfa = (int)(s_lo % spb) * KSTEP;
   int64_t bI = s_lo / spb;
-  for (int64_t t0 = s_lo; t0 < s_hi; t0 += SB) {
-    load_batch(nxt, t0 + SB < s_hi ? t0 + SB : t0);
+  for (int64_t t0 = s_lo; t0 < s_hi; t0 += NB * SB) {
 #pragma unroll
-    for (int b = 0; b < SB; ++b) {
-      const int64_t t = t0 + b;
-      if (t >= s_hi) break;
-      const LT *rw = raw + b * KL;
-      const int wi = W == Pf ? 0 : pfa / W;
-      if (wi != cur_w) {
-        __syncthreads();
-        stage(wi * W);
-        __syncthreads();
-        cur_w = wi;
-      }
-      const int pf0 = pfa - wi * W;
-      if constexpr (KL == 8) {
-        u32x4 vb[NT], vbl[NT];
+    for (int j = 0; j < NB; ++j) {
+      const int64_t tb = t0 + j * SB;
+      load_batch(buf[(j + NB - 1) % NB], tb + (NB - 1) * SB);
+      if (tb >= s_hi) break;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const XT *bp = sk + kidx<XT>(16 * nt + rho, pf0 + g * KL, ldk, swz);
-          vb[nt] = *reinterpret_cast<const u32x4 *>(bp);
-          if (HL) vbl[nt] = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
+      for (int b = 0; b < SB; ++b) {
+        const int64_t t = tb + b;
+        if (t >= s_hi) break;
+        const LT *rw = buf[j] + b * KL;
+        const int wi = W == Pf ? 0 : pfa / W;
+        if (wi != cur_w) {
+          __syncthreads();
+          stage(wi * W);
+          __syncthreads();
+          cur_w = wi;
         }
-#pragma unroll
-        for (int q = 0; q < QV; ++q) {
-          const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
-          u32x4 a;
-          a.x = __builtin_amdgcn_perm(dw(rw[1], q >> 1), dw(rw[0], q >> 1), sel);
-          a.y = __builtin_amdgcn_perm(dw(rw[3], q >> 1), dw(rw[2], q >> 1), sel);
-          a.z = __builtin_amdgcn_perm(dw(rw[5], q >> 1), dw(rw[4], q >> 1), sel);
-          a.w = __builtin_amdgcn_perm(dw(rw[7], q >> 1), dw(rw[6], q >> 1), sel);
+        const int pf0 = pfa - wi * W;
+        if constexpr (KL == 8) {
+          u32x4 vb[NT], vbl[NT];
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
-            CT &c = SLOW ? blk[q][nt] : acc[q][nt];
-            mma16(c, a, vb[nt], (XT *)nullptr);
-            if (HL) mma16(c, a, vbl[nt], (XT *)nullptr);
+            const XT *bp = sk + kidx<XT>(16 * nt + rho, pf0 + g * KL, ldk, swz);
+            vb[nt] = *reinterpret_cast<const u32x4 *>(bp);
+            if (HL) vbl[nt] = *reinterpret_cast<const u32x4 *>(bp + RP * ldk);
           }
-        }
-      } else {
-        AT bb[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) bb[nt] = (AT)sk[kidx<XT>(16 * nt + rho, pf0 + g, ldk, swz)];
-        const AT *xv = reinterpret_cast<const AT *>(rw);
-#pragma unroll
-        for (int q = 0; q < QV; ++q)
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) mma1(SLOW ? blk[q][nt] : acc[q][nt], xv[q], bb[nt]);
-      }
-      pfa += KSTEP;
-      const bool wrap = pfa == Pf;
-      if (SLOW && (wrap || t + 1 == s_hi)) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const AT sc = kslow[bI * RP + 16 * nt + rho];
 #pragma unroll
           for (int q = 0; q < QV; ++q) {
+            const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
+            u32x4 a;
+            a.x = __builtin_amdgcn_perm(dw(rw[1], q >> 1), dw(rw[0], q >> 1), sel);
+            a.y = __builtin_amdgcn_perm(dw(rw[3], q >> 1), dw(rw[2], q >> 1), sel);
+            a.z = __builtin_amdgcn_perm(dw(rw[5], q >> 1), dw(rw[4], q >> 1), sel);
+            a.w = __builtin_amdgcn_perm(dw(rw[7], q >> 1), dw(rw[6], q >> 1), sel);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[q][nt][v] += blk[q][nt][v] * sc;
-            czero(blk[q][nt]);
+            for (int nt = 0; nt < NT; ++nt) {
+              CT &c = SLOW ? blk[q][nt] : acc[q][nt];
+              mma16(c, a, vb[nt], (XT *)nullptr);
+              if (HL) mma16(c, a, vbl[nt], (XT *)nullptr);
+            }
+          }
+        } else {
+          AT bb[NT];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) bb[nt] = (AT)sk[kidx<XT>(16 * nt + rho, pf0 + g, ldk, swz)];
+          const AT *xv = reinterpret_cast<const AT *>(rw);
+#pragma unroll
+          for (int q = 0; q < QV; ++q)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) mma1(SLOW ? blk[q][nt] : acc[q][nt], xv[q], bb[nt]);
+        }
+        pfa += KSTEP;
+        const bool wrap = pfa == Pf;
+        if (SLOW && (wrap || t + 1 == s_hi)) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const AT sc = kslow[bI * RP + 16 * nt + rho];
+#pragma unroll
+            for (int q = 0; q < QV; ++q) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[q][nt][v] += blk[q][nt][v] * sc;
+              czero(blk[q][nt]);
+            }
           }
         }
-      }
-      if (wrap) {
-        pfa = 0;
-        ++bI;
+        if (wrap) {
+          pfa = 0;
+          ++bI;
+        }
       }
     }
-#pragma unroll
-    for (int u = 0; u < SB * KL; ++u) raw[u] = nxt[u];
   }
 
+  // Epilogue: each group of 16 result columns r goes through LDS (the
+  // operand's LDS, free after the barrier) so that every store writes whole
+  // 16-byte pieces of the rows T(r, i0 ..) instead of scattered elements.
+  constexpr int CW = 16 * QV;                // columns of T per wave
+  constexpr int VE = 16 / (int)sizeof(AT);   // elements per 16-byte store
+  constexpr int LDW = CW + VE;               // LDS row stride (elements)
+  constexpr int LPR = CW / VE;               // lanes per row segment
+  constexpr int RPI = 64 / LPR;              // rows per store instruction
+  typedef AT avec __attribute__((ext_vector_type(VE)));
+  AT *eb = reinterpret_cast<AT *>(smem) + wave * 16 * LDW;
   AT *o = out + (int64_t)blockIdx.y * R * m;
+  const bool vec_ok = (m % VE) == 0;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
-    const int r = 16 * nt + rho;  // result column of this lane
     const AT s = SLOW ? (AT)1 : kslow[16 * nt + rho];
-    if (r < R) {
+    __syncthreads();
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t ib = i0 + QV * crow<AT>(g, v);
-        if (ib < m) {
-          AT vals[QV];
+    for (int v = 0; v < 4; ++v) {
+      AT *dst = eb + rho * LDW + QV * crow<AT>(g, v);
 #pragma unroll
-          for (int q = 0; q < QV; ++q) vals[q] = acc[q][nt][v] * s;
-          AT *dst = o + (int64_t)r * m + ib;
+      for (int q0 = 0; q0 < QV; q0 += (VE < QV ? VE : QV)) {
+        if constexpr (VE <= QV) {
+          avec t;
 #pragma unroll
-          for (int q = 0; q < QV; ++q) dst[q] = vals[q];
+          for (int e = 0; e < VE; ++e) t[e] = acc[q0 + e][nt][v] * s;
+          *reinterpret_cast<avec *>(dst + q0) = t;
+        } else {
+#pragma unroll
+          for (int e = 0; e < QV; ++e) dst[e] = acc[e][nt][v] * s;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += RPI) {
+      const int rr = r0 + lane / LPR, cc = (lane % LPR) * VE;
+      const int r = 16 * nt + rr;
+      const int64_t col = i0 + cc;
+      if (r < R && col < m) {
+        const AT *src = eb + rr * LDW + cc;
+        AT *gd = o + (int64_t)r * m + col;
+        if (vec_ok && col + VE <= m) {
+          *reinterpret_cast<avec *>(gd) = *reinterpret_cast<const avec *>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VE; ++e)
+            if (col + e < m) gd[e] = src[e];
         }
       }
     }
