@@ -11,7 +11,7 @@
  * an MU (Eq. eqn:muupd) or HALS (Eq. eqn:halsupd) update, column
  * normalisation, and the relative error through the identity of the
  * appendix (Algorithm 4).  MTTKRP runs through the dimension tree of
- * Section 3.2 (Algorithm 3): two partial MTTKRPs (one GEMM each) at the root
+ * Section 4.2 (Algorithm 3): two partial MTTKRPs (one GEMM each) at the root
  * and multi-TTVs below.
  *
  * Conventions shared by every entry point
@@ -19,8 +19,8 @@
  * Modes are 0-based (the paper numbers them from 1).
  *
  * Tensor layout: X is dense, mode 0 varies fastest: entry (i_0, ..., i_{N-1})
- * is at linear index i_0 + I_0 (i_1 + I_1 (i_2 + ...))  (the paper's
- * "mode-descending, generalizing column-major" order, Section 3.1.1).  In
+ * is at linear index i_0 + I_0 (i_1 + I_1 (i_2 + ...)), the local storage
+ * order of Section 4.1.2 (column-major carried to N modes).  In
  * PyTorch this is a contiguous tensor of shape (I_{N-1}, ..., I_0).
  *
  * Factor layout: H^(n) is I_n x R, row-major (entry (i, r) at i*R + r).  The
@@ -83,8 +83,9 @@ typedef struct nncp_options {
   int split;        /* root split: modes 0..split-1 form the left subtree.  0 =
                        automatic [0]: the smallest S with
                        prod(I_0..I_{S-1}) >= prod(I_S..I_{N-1}), clamped to
-                       [1, N-1] (Section 3.2.2; ">=" is the reading of "greater
-                       than" that gives a balanced split for equal halves).  */
+                       [1, N-1] (Section 4.2.2; ">=" is the reading of the
+                       strict comparison there that gives a balanced split
+                       for equal halves).  */
   int krp_split;    /* BF16/FP16 tensors: 1 = feed the Khatri-Rao operand to the
                        matrix cores as a hi+lo pair of the tensor's type (error
                        about 2^-16 instead of 2^-8), 0 = single rounding [1]. */

@@ -6,7 +6,7 @@ with the GPU library (``paper_1909_01149_amd``) and neither imports the other.
 
 The arithmetic lives in ``nncp_oracle.c`` (plain C, FP64), which follows the
 paper's definitions (PLANC, arXiv 1909.01149): MTTKRP by its entrywise
-definition (Section 3.2.1, Appendix A), Algorithm 1 with the MU rule
+definition (Section 4.2.1, Appendix A), Algorithm 1 with the MU rule
 (Eq. eqn:muupd) and the HALS rule (Eq. eqn:halsupd), column normalisation and
 the relative-error identity (Appendix A, Algorithm 4).  This module only
 marshals NumPy arrays into that library.

@@ -12,10 +12,10 @@
  *   - the objective, Eq. (eqn:nncp), Section 1;
  *   - the alternating-update outer/inner iteration, Algorithm 1 (alg:nncp);
  *   - MTTKRP M^(n) = X_(n) (H^(N) kr ... kr H^(n+1) kr H^(n-1) kr ... kr H^(1)),
- *     Appendix "Factor Matrix Normalization" and Section 3.2.1 (3-way example);
+ *     Appendix "Factor Matrix Normalization" and Section 4.2.1 (3-way example);
  *   - Gram G^(n) = H^(n)^T H^(n) and S^(n) = Hadamard product of the other
  *     Grams, Algorithm 1;
- *   - MU rule, Eq. (eqn:muupd); HALS rule, Eq. (eqn:halsupd), Section 3.3;
+ *   - MU rule, Eq. (eqn:muupd); HALS rule, Eq. (eqn:halsupd), Section 4.3;
  *   - column normalisation with weights lambda, Appendix "Factor Matrix
  *     Normalization" and Algorithm 4 (alg:Par-NNCP-long);
  *   - relative error through the identity
@@ -26,8 +26,8 @@
  * the design notes of the repository):
  *   - lambda is folded into the factor being updated before the update,
  *     because the appendix states that the solve actually computes H^(n) Lambda;
- *   - MU adds eps (default 1e-16) to the denominator; the paper only says a
- *     "small value" is added;
+ *   - MU adds eps (default 1e-16) to the denominator; the paper only asks
+ *     for some small positive guard;
  *   - HALS divides by S(r,r) as in Eq. (eqn:halsupd) and skips a column whose
  *     S(r,r) is 0; columns are updated in order 1..R using the latest values;
  *   - HALS normalisation happens once after the whole update (Algorithm 4),
@@ -37,8 +37,8 @@
  *   - a zero column stays zero with lambda_r = 0;
  *   - the squared relative error is clamped at 0 before the square root.
  *
- * Layouts: the tensor is stored with mode 0 varying fastest (the paper's
- * "mode-descending, generalizing column-major" order, Section 3.1.1), so the
+ * Layouts: the tensor is stored with mode 0 varying fastest (the local
+ * storage order of Section 4.1.2, column-major carried to N modes), so the
  * linear index of (i_0, ..., i_{N-1}) is i_0 + I_0 (i_1 + I_1 (i_2 + ...)).
  * A factor H^(n) is I_n x R, row-major (entry (i, r) at i*R + r).  Modes are
  * 0-based here; the paper numbers them from 1.
@@ -99,7 +99,7 @@ int orc_max_threads(void) {
  * M^(n)[i_n, r] = sum over every entry of X whose mode-n index is i_n of
  *                 X[i_0..i_{N-1}] * prod_{k != n} H^(k)[i_k, r].
  * This is the mode-n matricized tensor times the Khatri-Rao product of all
- * other factors, written entrywise (Section 3.2.1; Appendix, normalisation
+ * other factors, written entrywise (Section 4.2.1; Appendix, normalisation
  * paragraph).  One pass over X in memory order; when nthreads > 1 the pass is
  * cut into nthreads contiguous ranges, each thread accumulates into its own
  * copy of M, and the copies are added in thread order (so a given nthreads

@@ -1,5 +1,5 @@
 // Partial MTTKRP: the two GEMMs at the root of the dimension tree
-// (Section 3.2.2, Algorithm 3, partial-MTTKRP lines), plus the partial
+// (Section 4.2.2, Algorithm 3, partial-MTTKRP lines), plus the partial
 // Khatri-Rao operand (Algorithm 3, partial-KRP lines) and the deterministic
 // split-reduction finalize.
 //

@@ -1,4 +1,4 @@
-// Dimension-tree multi-TTVs (Section 3.2, Algorithm 3 multi-TTV lines), Gram
+// Dimension-tree multi-TTVs (Section 4.2, Algorithm 3 multi-TTV lines), Gram
 // and Hadamard products (Algorithm 1), the per-mode factor update with
 // column normalisation and the relative-error identity (Eqs. eqn:muupd,
 // eqn:halsupd; Appendix A, Algorithm 4), the loss, the gradient of the loss

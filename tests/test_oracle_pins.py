@@ -156,7 +156,7 @@ def test_mttkrp_mode_permutation_covariance():
 
 
 def test_mttkrp_three_way_dimension_tree_identities():
-    """Section 3.2.1: with T = X x_3 W (I x J x R), M^(1) = sum_j V T and
+    """Section 4.2.1: with T = X x_3 W (I x J x R), M^(1) = sum_j V T and
     M^(2) = sum_i U T (formed here with einsum, independently)."""
     I, J, K, R = 5, 4, 6, 3
     rng = np.random.default_rng(3)
