@@ -29,6 +29,7 @@ _LIB = os.path.join(_HERE, "_liboracle.so")
 
 MU = 0
 HALS = 1
+BPP = 2
 
 
 def build(force: bool = False) -> str:
@@ -66,6 +67,10 @@ def lib():
         L.orc_update_mu.argtypes = [i64, ci, pd, pd, pd, d]
         L.orc_update_hals.argtypes = [i64, ci, pd, pd, pd]
         L.orc_normalize.argtypes = [i64, ci, pd, pd, pd]
+        L.orc_update_bpp.argtypes = [i64, ci, pd, pd, pd]
+        L.orc_update_bpp.restype = i64
+        L.orc_bpp_row.argtypes = [ci, pd, pd, pd, pd]
+        L.orc_bpp_row.restype = ci
         L.orc_sweeps.argtypes = [ci, pi64, ci, pd, ppd, pd, ci, d, ci, pd, pd, ci]
         L.orc_residual.argtypes = [ci, pi64, ci, pd, ppd, pd, pd]
         L.orc_residual.restype = d
@@ -167,6 +172,26 @@ def update_hals(Hhat, M, S) -> np.ndarray:
     S = _f64(S)
     lib().orc_update_hals(H.shape[0], H.shape[1], _pd(H), _pd(M), _pd(S))
     return H
+
+
+def update_bpp(M, S):
+    """Exact NNLS solve of every row (BPP).  Returns (Hhat, failed_rows)."""
+    M = _f64(M)
+    S = _f64(S)
+    H = np.zeros_like(M)
+    failed = lib().orc_update_bpp(M.shape[0], M.shape[1], _pd(H), _pd(M), _pd(S))
+    return H, int(failed)
+
+
+def bpp_row(S, m):
+    """One row: returns (x, number of solves or -1)."""
+    S = _f64(S)
+    m = _f64(m)
+    R = m.shape[0]
+    x = np.zeros(R)
+    work = np.zeros(R * R + 4 * R)
+    n = lib().orc_bpp_row(R, _pd(S), _pd(m), _pd(x), _pd(work))
+    return x, int(n)
 
 
 def normalize(Hhat):

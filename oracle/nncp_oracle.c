@@ -16,6 +16,8 @@
  *   - Gram G^(n) = H^(n)^T H^(n) and S^(n) = Hadamard product of the other
  *     Grams, Algorithm 1;
  *   - MU rule, Eq. (eqn:muupd); HALS rule, Eq. (eqn:halsupd), Section 4.3;
+ *   - BPP (exact NNLS per row, Eq. (eqn:snls) and its KKT conditions),
+ *     Section 4.3.3, with the pivoting rule of the method the paper cites;
  *   - column normalisation with weights lambda, Appendix "Factor Matrix
  *     Normalization" and Algorithm 4 (alg:Par-NNCP-long);
  *   - relative error through the identity
@@ -272,6 +274,108 @@ void orc_update_hals(int64_t I, int R, double *Hhat, const double *M, const doub
 }
 
 /*
+ * BPP, Section 4.3.3 with Eq. (eqn:snls): each row x of Hhat becomes the
+ * exact solution of the single right-hand-side NNLS problem
+ *   min_{x >= 0} 1/2 x^T S x - m^T x      (A^T A = S, A^T b = m = row of M),
+ * whose KKT conditions are x >= 0, y = S x - m >= 0, x_i y_i = 0.  The
+ * active set is found by block principal pivoting (Kim and Park, 2011): with
+ * a passive set F, x_F solves S_FF x_F = m_F by a Cholesky factorisation of
+ * S_FF, x is 0 off F and y = S x - m off F (0 on F).  Every index breaking
+ * the conditions (x_i < 0 on F, y_i < 0 off F) switches sets while their
+ * count keeps falling; after the count stops falling three more full
+ * switches are allowed, then only the largest such index switches until
+ * the count falls again.  The search ends when no index breaks the
+ * conditions, after 5 R + 10 solves, or when S_FF is not positive definite
+ * (then the last x, clipped at 0, is kept).  Returns the number of solves,
+ * or -1 if the search ended without meeting the conditions.
+ * work: R*R + 4*R doubles.
+ */
+int orc_bpp_row(int R, const double *S, const double *m, double *x, double *work) {
+  double *L = work;            /* R x R, row-major, lower triangle */
+  double *y = L + R * R;
+  double *z = y + R;
+  double *passive = z + R;     /* 1.0 on F, 0.0 off F */
+  double *idx = passive + R;   /* F's indices in increasing order */
+  for (int i = 0; i < R; ++i) {
+    x[i] = 0.0;
+    y[i] = -m[i];
+    passive[i] = 0.0;
+  }
+  int ninf = R + 1, backup = 3, solves = 0;
+  const int maxsolves = 5 * R + 10;
+  for (;;) {
+    int nv = 0, last = -1;
+    for (int i = 0; i < R; ++i) {
+      const int bad = passive[i] != 0.0 ? (x[i] < 0.0) : (y[i] < 0.0);
+      if (bad) { ++nv; last = i; }
+    }
+    if (nv == 0) return solves;
+    if (solves >= maxsolves) break;
+    int full;
+    if (nv < ninf) { ninf = nv; backup = 3; full = 1; }
+    else if (backup >= 1) { --backup; full = 1; }
+    else full = 0;
+    for (int i = 0; i < R; ++i) {
+      const int bad = passive[i] != 0.0 ? (x[i] < 0.0) : (y[i] < 0.0);
+      if (bad && (full || i == last)) passive[i] = passive[i] != 0.0 ? 0.0 : 1.0;
+    }
+    /* S_FF = L L^T, then L z = m_F and L^T x_F = z */
+    int f = 0;
+    for (int i = 0; i < R; ++i)
+      if (passive[i] != 0.0) idx[f++] = (double)i;
+    int pd = 1;
+    for (int a = 0; a < f && pd; ++a) {
+      const int ia = (int)idx[a];
+      for (int b = 0; b <= a; ++b) {
+        const int ib = (int)idx[b];
+        double v = S[ia * R + ib];
+        for (int c = 0; c < b; ++c) v -= L[a * R + c] * L[b * R + c];
+        if (b == a) {
+          if (!(v > 0.0)) { pd = 0; break; }
+          L[a * R + a] = sqrt(v);
+        } else {
+          L[a * R + b] = v / L[b * R + b];
+        }
+      }
+    }
+    ++solves;
+    if (!pd) break;
+    for (int a = 0; a < f; ++a) {
+      double v = m[(int)idx[a]];
+      for (int c = 0; c < a; ++c) v -= L[a * R + c] * z[c];
+      z[a] = v / L[a * R + a];
+    }
+    for (int a = f - 1; a >= 0; --a) {
+      double v = z[a];
+      for (int c = a + 1; c < f; ++c) v -= L[c * R + a] * z[c];
+      z[a] = v / L[a * R + a];
+    }
+    for (int i = 0; i < R; ++i) x[i] = 0.0;
+    for (int a = 0; a < f; ++a) x[(int)idx[a]] = z[a];
+    for (int i = 0; i < R; ++i) {
+      if (passive[i] != 0.0) { y[i] = 0.0; continue; }
+      double v = -m[i];
+      for (int a = 0; a < f; ++a) v += S[i * R + (int)idx[a]] * z[a];
+      y[i] = v;
+    }
+  }
+  for (int i = 0; i < R; ++i) x[i] = x[i] > 0.0 ? x[i] : 0.0;
+  return -1;
+}
+
+/* BPP for every row of Hhat (the start values are not used: the solve is
+ * exact).  Returns the number of rows whose search ended without meeting the
+ * KKT conditions. */
+int64_t orc_update_bpp(int64_t I, int R, double *Hhat, const double *M, const double *S) {
+  double *work = (double *)malloc(sizeof(double) * (size_t)(R * R + 4 * R));
+  int64_t failed = 0;
+  for (int64_t i = 0; i < I; ++i)
+    if (orc_bpp_row(R, S, M + i * R, Hhat + i * R, work) < 0) ++failed;
+  free(work);
+  return failed;
+}
+
+/*
  * Column normalisation (Algorithm 4, column-norm and column-scale lines):
  * lambda_r = ||Hhat[:,r]||_2 and H[:,r] = Hhat[:,r] / lambda_r, or a zero
  * column with lambda_r = 0.
@@ -290,7 +394,7 @@ void orc_normalize(int64_t I, int R, const double *Hhat, double *H, double *lamb
 /* alternating-update sweeps                                            */
 /* ------------------------------------------------------------------ */
 
-enum { ORC_MU = 0, ORC_HALS = 1 };
+enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2 };
 
 /*
  * nsweeps outer iterations of Algorithm 1 with the local steps of
@@ -304,7 +408,7 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
                double *lambda, int algo, double eps_mu, int nsweeps,
                double *relerr, double *relerr2_raw, int nthreads) {
   if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0) return -1;
-  if (algo != ORC_MU && algo != ORC_HALS) return -1;
+  if (algo != ORC_MU && algo != ORC_HALS && algo != ORC_BPP) return -1;
   const int64_t I = prod_dims(N, dims);
   double *G[ORC_MAXN];
   int64_t maxI = 0;
@@ -328,8 +432,10 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
         for (int r = 0; r < R; ++r) Hhat[i * R + r] = H[n][i * R + r] * lambda[r];
       if (algo == ORC_MU)
         orc_update_mu(In, R, Hhat, M, S, eps_mu);
-      else
+      else if (algo == ORC_HALS)
         orc_update_hals(In, R, Hhat, M, S);
+      else
+        orc_update_bpp(In, R, Hhat, M, S);
       orc_normalize(In, R, Hhat, H[n], lambda);
       orc_gram(In, R, H[n], G[n]);
       if (n == N - 1) {

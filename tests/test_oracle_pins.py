@@ -270,6 +270,67 @@ def test_hals_last_column_kkt_and_monotone():
     assert subproblem_objective(out, M, S) <= subproblem_objective(Hh, M, S) + 1e-12
 
 
+# ---------------------------------------------------------------------------
+# BPP (Section 4.3.3): exact NNLS per row
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("R", [1, 3, 8, 17, 32, 64])
+def test_bpp_matches_scipy_nnls(R):
+    """min ||A x - b|| over x >= 0 from scipy's active-set solver (Lawson and
+    Hanson), an independent implementation, against BPP on S = A^T A, m = A^T b."""
+    rng = np.random.default_rng(100 + R)
+    for t in range(20):
+        n = int(rng.integers(R, 3 * R + 5))
+        A = rng.standard_normal((n, R))
+        b = rng.standard_normal(n)
+        x, solves = oracle.bpp_row(A.T @ A, A.T @ b)
+        xs, _ = nnls(A, b, maxiter=50 * R)
+        assert solves >= 0
+        np.testing.assert_allclose(x, xs, rtol=1e-9, atol=1e-12 * max(1.0, np.abs(xs).max()))
+
+
+def test_bpp_kkt_and_special_cases():
+    rng = np.random.default_rng(7)
+    R = 12
+    A = rng.random((30, R))
+    S = A.T @ A
+    # KKT on a general right-hand side
+    m = 5.0 * rng.standard_normal(R)
+    assert (m > 0).any() and (m < 0).any()
+    x, solves = oracle.bpp_row(S, m)
+    y = S @ x - m
+    assert solves >= 1 and np.all(x >= 0)
+    assert np.all(y >= -1e-10 * np.abs(m).max())
+    assert np.abs(x * y).max() <= 1e-10 * np.abs(m).max() ** 2
+    # interior solution: the unconstrained solve is already nonnegative
+    xt = rng.random(R) + 0.1
+    x, _ = oracle.bpp_row(S, S @ xt)
+    np.testing.assert_allclose(x, np.linalg.solve(S, S @ xt), rtol=1e-10)
+    np.testing.assert_allclose(x, xt, rtol=1e-8)
+    # m <= 0 (S has nonnegative entries): x = 0 satisfies KKT at once
+    x, solves = oracle.bpp_row(S, -rng.random(R))
+    assert solves == 0 and np.all(x == 0)
+    # R = 1 closed form max(0, m / s)
+    x, _ = oracle.bpp_row(np.array([[4.0]]), np.array([3.0]))
+    assert x[0] == 0.75
+
+
+def test_bpp_update_is_the_limit_of_hals():
+    """Repeated HALS sweeps over the columns converge to the exact per-row
+    NNLS solution, which BPP computes directly (the start values do not
+    matter to BPP)."""
+    dims = [7, 4, 5]
+    X, H, A, M, S = _subproblem(dims, 4, 1, 12)
+    M = M - 0.3 * M.mean()
+    Hb, failed = oracle.update_bpp(M, S)
+    assert failed == 0 and np.all(Hb >= 0)
+    Hh = H[1].copy()
+    for _ in range(3000):
+        Hh = oracle.update_hals(Hh, M, S)
+    np.testing.assert_allclose(Hb, Hh, rtol=1e-8, atol=1e-10)
+    assert subproblem_objective(Hb, M, S) <= subproblem_objective(Hh, M, S) + 1e-12
+
+
 def test_mu_invariants():
     dims = [6, 5, 4]
     X, H, A, M, S = _subproblem(dims, 3, 2, 10)
@@ -289,7 +350,7 @@ def test_mu_invariants():
 # sweeps: identity, monotonicity, exact low rank, KKT
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS])
+@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP])
 @pytest.mark.parametrize("dims", [[6, 5, 4], [4, 3, 5, 2]])
 def test_sweep_relerr_identity_matches_direct_residual(algo, dims):
     X, H0 = gen.small_lowrank(dims, 3, 3, 21, noise=0.05)
@@ -308,10 +369,11 @@ def test_sweep_relerr_identity_matches_direct_residual(algo, dims):
             np.testing.assert_allclose(n[n > 0], 1.0, rtol=1e-13)
 
 
-@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS])
+@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP])
 def test_objective_nonincreasing_after_every_mode(algo):
     """With lambda folded into the updated factor, each mode update can only
-    lower ||X - [[lambda; H]]|| (MU: Lee-Seung; HALS: exact coordinate steps)."""
+    lower ||X - [[lambda; H]]|| (MU: Lee-Seung; HALS: exact coordinate steps;
+    BPP: the exact block minimiser)."""
     dims = [5, 4, 6]
     X, H = gen.small_lowrank(dims, 3, 3, 31, noise=0.1)
     lam = np.ones(3)
@@ -323,7 +385,13 @@ def test_objective_nonincreasing_after_every_mode(algo):
             M = oracle.mttkrp(X, Hs, n)
             S = oracle.hadamard_except(Gs, n)
             Hhat = Hs[n] * lam[None, :]
-            Hhat = oracle.update_mu(Hhat, M, S) if algo == oracle.MU else oracle.update_hals(Hhat, M, S)
+            if algo == oracle.MU:
+                Hhat = oracle.update_mu(Hhat, M, S)
+            elif algo == oracle.HALS:
+                Hhat = oracle.update_hals(Hhat, M, S)
+            else:
+                Hhat, failed = oracle.update_bpp(M, S)
+                assert failed == 0
             Hs[n], lam = oracle.normalize(Hhat)
             fn = np.linalg.norm(X - reconstruct(Hs, lam))
             assert fn <= f * (1 + 1e-12)
