@@ -76,7 +76,7 @@ enum nncp_status {
 
 enum nncp_dtype { NNCP_F64 = 0, NNCP_F32 = 1, NNCP_BF16 = 2, NNCP_F16 = 3 };
 
-enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1 };
+enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1, NNCP_BPP = 2 };
 
 /* Options (pass NULL for the defaults, shown in brackets). */
 typedef struct nncp_options {
@@ -161,6 +161,21 @@ int nncp_hadamard(nncp_ctx *ctx, int mode, double *S);
  */
 int nncp_update_mu(nncp_ctx *ctx, int mode, const void *M, const double *S, double eps);
 int nncp_update_hals(nncp_ctx *ctx, int mode, const void *M, const double *S);
+
+/*
+ * BPP update of mode n (Section 4.3.3, Eq. eqn:snls): every row of Hhat
+ * becomes the exact solution of the nonnegative least-squares subproblem
+ *   min_{x >= 0} 0.5 x^T S x - m^T x   (m = that row of M),
+ * found by block principal pivoting on the KKT conditions x >= 0,
+ * y = S x - m >= 0, x_i y_i = 0, with S_FF solved by Cholesky in FP64 (the
+ * pivoting rule is that of the method the paper cites: full switches while
+ * the number of violating indices falls, three more, then the largest index
+ * alone; at most 5 R + 10 solves per row, and a row whose S_FF is not
+ * positive definite keeps its last solution clipped at 0).  The start values
+ * of H^(n) are not used.  Then normalisation and G^(n) as above.  R <= 64
+ * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_BPP as its algo.
+ */
+int nncp_update_bpp(nncp_ctx *ctx, int mode, const void *M, const double *S);
 
 /*
  * Loss of the current model through the identity of the appendix:

@@ -25,7 +25,7 @@ NNCP_E_STATE = -5
 NNCP_E_UNSUPPORTED = -6
 
 NNCP_F64, NNCP_F32, NNCP_BF16, NNCP_F16 = 0, 1, 2, 3
-NNCP_MU, NNCP_HALS = 0, 1
+NNCP_MU, NNCP_HALS, NNCP_BPP = 0, 1, 2
 NNCP_MAX_MODES = 16
 
 EXPORTS = [
@@ -33,6 +33,7 @@ EXPORTS = [
     "nncp_hadamard", "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep",
     "nncp_grad", "nncp_pgd", "nncp_destroy", "nncp_last_error", "nncp_split",
     "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read", "nncp_sweep_capture",
+    "nncp_update_bpp",
 ]
 NNCP_TIMER_CATEGORIES = 5
 
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
     L.nncp_hadamard.argtypes = [vp, ci, dp]
     L.nncp_update_mu.argtypes = [vp, ci, vp, dp, cd]
     L.nncp_update_hals.argtypes = [vp, ci, vp, dp]
+    L.nncp_update_bpp.argtypes = [vp, ci, vp, dp]
     L.nncp_cp_loss.argtypes = [vp, dp, dp]
     L.nncp_sweep.argtypes = [vp, ci, ci, dp]
     L.nncp_sweep_capture.argtypes = [vp, ci, ci, dp]
@@ -91,7 +93,7 @@ def lib() -> ctypes.CDLL:
                  "nncp_init", "nncp_set_factors", "nncp_mttkrp", "nncp_gram", "nncp_hadamard",
                  "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep", "nncp_grad",
                  "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path",
-                 "nncp_sweep_capture"):
+                 "nncp_sweep_capture", "nncp_update_bpp"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -170,6 +172,10 @@ def nncp_update_mu(ctx, mode, M, S, eps=-1.0):
 
 def nncp_update_hals(ctx, mode, M, S):
     return _check(lib().nncp_update_hals(ctx, int(mode), _ptr(M), _ptr(S)))
+
+
+def nncp_update_bpp(ctx, mode, M, S):
+    return _check(lib().nncp_update_bpp(ctx, int(mode), _ptr(M), _ptr(S)))
 
 
 def nncp_cp_loss(ctx, loss=None, relerr=None):
@@ -286,6 +292,8 @@ class Context:
     def update(self, algo: int, mode: int, M, S, eps: float = -1.0):
         if algo == NNCP_MU:
             nncp_update_mu(self.ctx, mode, M, S, eps)
+        elif algo == NNCP_BPP:
+            nncp_update_bpp(self.ctx, mode, M, S)
         else:
             nncp_update_hals(self.ctx, mode, M, S)
 

@@ -658,6 +658,13 @@ int nncp_update_hals(nncp_ctx *c, int mode, const void *M, const double *S) {
   return update_api(c, NNCP_HALS, mode, M, S, 0.0);
 }
 
+int nncp_update_bpp(nncp_ctx *c, int mode, const void *M, const double *S) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "BPP needs R <= 64 (R = %d)", c->L.R);
+  return update_api(c, NNCP_BPP, mode, M, S, 0.0);
+}
+
 int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -731,7 +738,8 @@ static int build_graph(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) 
 int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo != NNCP_MU && algo != NNCP_HALS) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo != NNCP_MU && algo != NNCP_HALS && algo != NNCP_BPP) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo == NNCP_BPP && c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "BPP needs R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
   if (nsweeps == 0) return NNCP_OK;
   // Eager launches while timing (each launch is bracketed by events) or when
@@ -750,7 +758,8 @@ int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
 int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo != NNCP_MU && algo != NNCP_HALS) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo != NNCP_MU && algo != NNCP_HALS && algo != NNCP_BPP) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo == NNCP_BPP && c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "BPP needs R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 1) return fail(NNCP_E_INVAL, "nsweeps %d < 1", nsweeps);
   if (!c->L.opt.graphs) return fail(NNCP_E_INVAL, "graphs are switched off for this context");
   return build_graph(c, algo, nsweeps, relerr_hist);

@@ -677,6 +677,170 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   if (threadIdx.x == 0) cpart[R] = bred[0] + bred[1] + bred[2] + bred[3];
 }
 
+// Cross-lane exchange through LDS inside one wave: a wave's LDS accesses are
+// performed in order, so a compiler barrier with wavefront-scope fences is
+// all that orders a write by one lane before a read by another.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// BPP rows for R <= RB <= 64 (Section 4.3.3, Eq. eqn:snls): every row x of
+// Hhat becomes the exact solution of min_{x >= 0} 1/2 x^T S x - m^T x, whose
+// KKT conditions are x >= 0, y = S x - m >= 0, x_i y_i = 0.  One wave per row;
+// lane c owns index c.  The passive set F is a ballot mask; the indices that
+// break the conditions (x < 0 on F, y < 0 off F) switch sets while their
+// count keeps falling, then three more full switches are allowed, then only
+// the largest index switches (block principal pivoting).  Each switch solves
+// S_FF x_F = m_F by a left-looking Cholesky factorisation in the wave's LDS
+// (lane p owns row p of the factor) and two triangular solves, and forms
+// y = S x - m off F.  The search ends when no index breaks the conditions,
+// after 5 R + 10 solves, or when S_FF is not positive definite (the last x,
+// clipped at 0, is kept).  All arithmetic is FP64.
+template <typename HT, int RB>
+__global__ __launch_bounds__(RB <= 32 ? 256 : 64) void k_update_bpp(UpdateArgs a) {
+  constexpr int WPB = RB <= 32 ? 4 : 1;  // rows (waves) per workgroup
+  constexpr bool S_LDS = RB <= 32;
+  constexpr int LD = RB + 1;             // LDS row stride of the factor
+  __shared__ double sS[S_LDS ? RB * RB : 1];
+  __shared__ double sL[WPB][RB * LD];
+  __shared__ double sv[WPB][2][RB];
+  __shared__ double wred[WPB][64];
+  __shared__ double bred[WPB];
+  const int R = a.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const HT *M = (const HT *)a.M;
+  const int64_t i = (int64_t)blockIdx.x * WPB + wave;
+  const bool live = i < a.I;
+  const bool own = lane < R;
+  const int c = own ? lane : 0;
+  const int64_t ir = live ? i : a.I - 1;
+  // M row (split partials added in order), then S staged for the workgroup
+  const int ns = a.msplit;
+  const HT *mp = M + ir * R + c;
+  HT mv[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) mv[k] = k < ns ? mp[(int64_t)k * a.mstride] : (HT)0;
+  if constexpr (S_LDS) {
+    for (int e = threadIdx.x; e < R * R; e += 64 * WPB) sS[e] = a.S[e];
+  }
+  HT macc = mv[0];
+#pragma unroll
+  for (int k = 1; k < 32; ++k)
+    if (k < ns) macc += mv[k];
+  for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
+  const double m = (live && own) ? (double)macc : 0.0;
+  __syncthreads();
+  auto Sat = [&](int r, int q) -> double { return S_LDS ? sS[r * R + q] : a.S[r * R + q]; };
+  double *L = sL[wave];
+  double *zv = sv[wave][0];
+  double *xv = sv[wave][1];
+
+  bool pas = false;
+  double x = 0.0, y = -m;
+  int ninf = R + 1, backup = 3, solves = 0;
+  const int maxsolves = 5 * R + 10;
+  for (;;) {
+    const bool bad = own && (pas ? (x < 0.0) : (y < 0.0));
+    const uint64_t V = __ballot(bad);
+    const int nv = __popcll(V);
+    if (nv == 0 || solves >= maxsolves) break;
+    bool full;
+    if (nv < ninf) { ninf = nv; backup = 3; full = true; }
+    else if (backup >= 1) { --backup; full = true; }
+    else full = false;
+    const int last = 63 - __clzll(V);
+    if (bad && (full || lane == last)) pas = !pas;
+    const uint64_t Fm = __ballot(pas);
+    const int f = __popcll(Fm);
+    const int pos = __popcll(Fm & ((1ull << lane) - 1));
+    // rows of S_FF, lane p (passive) writing row p (columns 0..p)
+    wave_sync();
+    if (pas) {
+      uint64_t t = Fm;
+      for (int q = 0; q <= pos; ++q) {
+        const int c2 = __ffsll((unsigned long long)t) - 1;
+        t &= t - 1;
+        L[pos * LD + q] = Sat(c, c2);
+      }
+    }
+    // left-looking Cholesky: column k from the finished columns 0..k-1
+    bool fail = false;
+    for (int k = 0; k < f; ++k) {
+      wave_sync();
+      double v = 0.0;
+      if (pas && pos >= k) {
+        v = L[pos * LD + k];
+        for (int j = 0; j < k; ++j) v -= L[pos * LD + j] * L[k * LD + j];
+        if (pos == k) L[k * LD + k] = v > 0.0 ? sqrt(v) : 0.0;
+      }
+      const bool nonpd = pas && pos == k && !(v > 0.0);
+      if (__ballot(nonpd)) { fail = true; break; }
+      wave_sync();
+      if (pas && pos > k) L[pos * LD + k] = v / L[k * LD + k];
+    }
+    ++solves;
+    if (fail) break;
+    // L z = m_F (column by column), then L^T x_F = z
+    double b = pas ? m : 0.0;
+    for (int k = 0; k < f; ++k) {
+      wave_sync();
+      if (pas && pos == k) zv[k] = b / L[k * LD + k];
+      wave_sync();
+      if (pas && pos > k) b -= L[pos * LD + k] * zv[k];
+    }
+    double zz = 0.0;
+    wave_sync();
+    if (pas) zz = zv[pos];
+    for (int k = f - 1; k >= 0; --k) {
+      wave_sync();
+      if (pas && pos == k) xv[k] = zz / L[k * LD + k];
+      wave_sync();
+      if (pas && pos < k) zz -= L[k * LD + pos] * xv[k];
+    }
+    wave_sync();
+    x = pas ? xv[pos] : 0.0;
+    // y = S x - m off F
+    double yv = 0.0;
+    if (own && !pas) {
+      yv = -m;
+      uint64_t t = Fm;
+      for (int q = 0; q < f; ++q) {
+        const int c2 = __ffsll((unsigned long long)t) - 1;
+        t &= t - 1;
+        yv += Sat(c, c2) * xv[q];
+      }
+    }
+    y = yv;
+  }
+  const double h = (own && x > 0.0) ? x : 0.0;
+  double sq = 0.0, beta = 0.0;
+  if (live && own) {
+    a.hhat[i * R + c] = h;
+    sq = h * h;
+    beta = m * h;
+  }
+  wred[wave][lane] = sq;
+  beta = wave_sum(beta);
+  if (lane == 0) bred[wave] = beta;
+  __syncthreads();
+  // per-workgroup partials (the WPB rows added in wave order)
+  double *cpart = a.part + (int64_t)blockIdx.x * (R + 1);
+  if (threadIdx.x < R) {
+    double v = wred[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < WPB; ++w) v += wred[w][threadIdx.x];
+    cpart[threadIdx.x] = v;
+  }
+  if (threadIdx.x == 0) {
+    double v = bred[0];
+#pragma unroll
+    for (int w = 1; w < WPB; ++w) v += bred[w];
+    cpart[R] = v;
+  }
+}
+
 // Upper tiles (tx <= ty) of the T x T grid of 16 x 16 tiles of an R x R
 // matrix, T = ceil(R / 16), in row-major order.
 __device__ __forceinline__ void tile_pair(int t, int T, int &tx, int &ty) {
@@ -1220,9 +1384,16 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
   if (a.R <= 64) {
     int64_t rpw;
     const int nw = norm_workgroups(a.I, &rpw);
-#define NNCP_UPDATE_SMALL(RBV)                                                \
-  hipLaunchKernelGGL((k_update_rows_small<HT, RBV>), grid, block, 0, st, a); \
-  hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw)
+#define NNCP_UPDATE_SMALL(RBV)                                                           \
+  if (a.algo == NNCP_BPP) {                                                             \
+    constexpr int WPB = RBV <= 32 ? 4 : 1;                                              \
+    const int nbb = (int)((a.I + WPB - 1) / WPB);                                       \
+    hipLaunchKernelGGL((k_update_bpp<HT, RBV>), dim3(nbb), dim3(64 * WPB), 0, st, a);   \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nbb, rpw); \
+  } else {                                                                               \
+    hipLaunchKernelGGL((k_update_rows_small<HT, RBV>), grid, block, 0, st, a);          \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+  }
     if (a.R <= 16) {
       NNCP_UPDATE_SMALL(16);
     } else if (a.R <= 32) {
@@ -1232,6 +1403,7 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
     }
 #undef NNCP_UPDATE_SMALL
   } else {
+    if (a.algo == NNCP_BPP) return hipErrorInvalidValue;
     if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
     hipLaunchKernelGGL((k_update_finish<HT>), dim3(1), dim3(1024), 0, st, a, nb);
@@ -1252,8 +1424,8 @@ hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st) {
 }
 
 int64_t update_part_elems(int64_t I, int R) {
-  const int rpb = update_rows_per_block(R);
-  return ((I + rpb - 1) / rpb) * (int64_t)(R + 1);
+  // one row per workgroup at the most (the BPP kernel at R > 32)
+  return I * (int64_t)(R + 1);
 }
 
 hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const void *H,
