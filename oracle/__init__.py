@@ -174,21 +174,22 @@ def update_hals(Hhat, M, S) -> np.ndarray:
     return H
 
 
-def update_bpp(M, S):
-    """Exact NNLS solve of every row (BPP).  Returns (Hhat, failed_rows)."""
+def update_bpp(M, S, Hhat0=None):
+    """Exact NNLS solve of every row (BPP), each search starting from the
+    support of Hhat0's row (all zero if None).  Returns (Hhat, failed_rows)."""
     M = _f64(M)
     S = _f64(S)
-    H = np.zeros_like(M)
+    H = np.zeros_like(M) if Hhat0 is None else _f64(Hhat0).copy()
     failed = lib().orc_update_bpp(M.shape[0], M.shape[1], _pd(H), _pd(M), _pd(S))
     return H, int(failed)
 
 
-def bpp_row(S, m):
-    """One row: returns (x, number of solves or -1)."""
+def bpp_row(S, m, x0=None):
+    """One row: returns (x, number of solves or -1); x0 gives the start support."""
     S = _f64(S)
     m = _f64(m)
     R = m.shape[0]
-    x = np.zeros(R)
+    x = np.zeros(R) if x0 is None else _f64(x0).copy()
     work = np.zeros(R * R + 4 * R)
     n = lib().orc_bpp_row(R, _pd(S), _pd(m), _pd(x), _pd(work))
     return x, int(n)

@@ -280,28 +280,84 @@ void orc_update_hals(int64_t I, int R, double *Hhat, const double *M, const doub
  * whose KKT conditions are x >= 0, y = S x - m >= 0, x_i y_i = 0.  The
  * active set is found by block principal pivoting (Kim and Park, 2011): with
  * a passive set F, x_F solves S_FF x_F = m_F by a Cholesky factorisation of
- * S_FF, x is 0 off F and y = S x - m off F (0 on F).  Every index breaking
- * the conditions (x_i < 0 on F, y_i < 0 off F) switches sets while their
- * count keeps falling; after the count stops falling three more full
- * switches are allowed, then only the largest such index switches until
- * the count falls again.  The search ends when no index breaks the
- * conditions, after 5 R + 10 solves, or when S_FF is not positive definite
- * (then the last x, clipped at 0, is kept).  Returns the number of solves,
+ * S_FF, x is 0 off F and y = S x - m off F (0 on F).  The search starts from
+ * the support of the row's current value (F = {i : x_i > 0}, solved once; an
+ * empty F starts from x = 0, y = -m), as alternating NNLS solvers do between
+ * outer iterations.  Every index breaking the conditions (x_i < 0 on F,
+ * y_i < 0 off F) switches sets while their count keeps falling; after the
+ * count stops falling three more full switches are allowed, then only the
+ * largest such index switches until the count falls again.  The search ends
+ * when no index breaks the conditions, after 5 R + 10 solves, or when S_FF
+ * is not positive definite (then the last x, clipped at 0, is kept; a start
+ * set that fails this way is replaced by the empty set).  x is the start
+ * value on entry and the solution on exit.  Returns the number of solves,
  * or -1 if the search ended without meeting the conditions.
  * work: R*R + 4*R doubles.
  */
+static int bpp_solve(int R, const double *S, const double *m, const double *passive,
+                     double *x, double *y, double *L, double *z, double *idx) {
+  int f = 0;
+  for (int i = 0; i < R; ++i)
+    if (passive[i] != 0.0) idx[f++] = (double)i;
+  /* S_FF = L L^T, then L z = m_F and L^T x_F = z */
+  for (int a = 0; a < f; ++a) {
+    const int ia = (int)idx[a];
+    for (int b = 0; b <= a; ++b) {
+      const int ib = (int)idx[b];
+      double v = S[ia * R + ib];
+      for (int c = 0; c < b; ++c) v -= L[a * R + c] * L[b * R + c];
+      if (b == a) {
+        if (!(v > 0.0)) return 0;
+        L[a * R + a] = sqrt(v);
+      } else {
+        L[a * R + b] = v / L[b * R + b];
+      }
+    }
+  }
+  for (int a = 0; a < f; ++a) {
+    double v = m[(int)idx[a]];
+    for (int c = 0; c < a; ++c) v -= L[a * R + c] * z[c];
+    z[a] = v / L[a * R + a];
+  }
+  for (int a = f - 1; a >= 0; --a) {
+    double v = z[a];
+    for (int c = a + 1; c < f; ++c) v -= L[c * R + a] * z[c];
+    z[a] = v / L[a * R + a];
+  }
+  for (int i = 0; i < R; ++i) x[i] = 0.0;
+  for (int a = 0; a < f; ++a) x[(int)idx[a]] = z[a];
+  for (int i = 0; i < R; ++i) {
+    if (passive[i] != 0.0) { y[i] = 0.0; continue; }
+    double v = -m[i];
+    for (int a = 0; a < f; ++a) v += S[i * R + (int)idx[a]] * z[a];
+    y[i] = v;
+  }
+  return 1;
+}
+
 int orc_bpp_row(int R, const double *S, const double *m, double *x, double *work) {
   double *L = work;            /* R x R, row-major, lower triangle */
   double *y = L + R * R;
   double *z = y + R;
   double *passive = z + R;     /* 1.0 on F, 0.0 off F */
   double *idx = passive + R;   /* F's indices in increasing order */
+  int f0 = 0, solves = 0;
   for (int i = 0; i < R; ++i) {
-    x[i] = 0.0;
-    y[i] = -m[i];
-    passive[i] = 0.0;
+    passive[i] = x[i] > 0.0 ? 1.0 : 0.0;
+    f0 += x[i] > 0.0;
   }
-  int ninf = R + 1, backup = 3, solves = 0;
+  if (f0 > 0) {
+    ++solves;
+    if (!bpp_solve(R, S, m, passive, x, y, L, z, idx)) f0 = 0;
+  }
+  if (f0 == 0) {
+    for (int i = 0; i < R; ++i) {
+      x[i] = 0.0;
+      y[i] = -m[i];
+      passive[i] = 0.0;
+    }
+  }
+  int ninf = R + 1, backup = 3;
   const int maxsolves = 5 * R + 10;
   for (;;) {
     int nv = 0, last = -1;
@@ -319,53 +375,16 @@ int orc_bpp_row(int R, const double *S, const double *m, double *x, double *work
       const int bad = passive[i] != 0.0 ? (x[i] < 0.0) : (y[i] < 0.0);
       if (bad && (full || i == last)) passive[i] = passive[i] != 0.0 ? 0.0 : 1.0;
     }
-    /* S_FF = L L^T, then L z = m_F and L^T x_F = z */
-    int f = 0;
-    for (int i = 0; i < R; ++i)
-      if (passive[i] != 0.0) idx[f++] = (double)i;
-    int pd = 1;
-    for (int a = 0; a < f && pd; ++a) {
-      const int ia = (int)idx[a];
-      for (int b = 0; b <= a; ++b) {
-        const int ib = (int)idx[b];
-        double v = S[ia * R + ib];
-        for (int c = 0; c < b; ++c) v -= L[a * R + c] * L[b * R + c];
-        if (b == a) {
-          if (!(v > 0.0)) { pd = 0; break; }
-          L[a * R + a] = sqrt(v);
-        } else {
-          L[a * R + b] = v / L[b * R + b];
-        }
-      }
-    }
     ++solves;
-    if (!pd) break;
-    for (int a = 0; a < f; ++a) {
-      double v = m[(int)idx[a]];
-      for (int c = 0; c < a; ++c) v -= L[a * R + c] * z[c];
-      z[a] = v / L[a * R + a];
-    }
-    for (int a = f - 1; a >= 0; --a) {
-      double v = z[a];
-      for (int c = a + 1; c < f; ++c) v -= L[c * R + a] * z[c];
-      z[a] = v / L[a * R + a];
-    }
-    for (int i = 0; i < R; ++i) x[i] = 0.0;
-    for (int a = 0; a < f; ++a) x[(int)idx[a]] = z[a];
-    for (int i = 0; i < R; ++i) {
-      if (passive[i] != 0.0) { y[i] = 0.0; continue; }
-      double v = -m[i];
-      for (int a = 0; a < f; ++a) v += S[i * R + (int)idx[a]] * z[a];
-      y[i] = v;
-    }
+    if (!bpp_solve(R, S, m, passive, x, y, L, z, idx)) break;
   }
   for (int i = 0; i < R; ++i) x[i] = x[i] > 0.0 ? x[i] : 0.0;
   return -1;
 }
 
-/* BPP for every row of Hhat (the start values are not used: the solve is
- * exact).  Returns the number of rows whose search ended without meeting the
- * KKT conditions. */
+/* BPP for every row of Hhat, each search starting from the row's current
+ * support.  Returns the number of rows whose search ended without meeting
+ * the KKT conditions. */
 int64_t orc_update_bpp(int64_t I, int R, double *Hhat, const double *M, const double *S) {
   double *work = (double *)malloc(sizeof(double) * (size_t)(R * R + 4 * R));
   int64_t failed = 0;

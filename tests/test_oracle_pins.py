@@ -315,6 +315,22 @@ def test_bpp_kkt_and_special_cases():
     assert x[0] == 0.75
 
 
+def test_bpp_warm_start():
+    """The solution does not depend on the start support; started from the
+    solution's own support the search needs one solve."""
+    rng = np.random.default_rng(8)
+    for R in (5, 16, 40):
+        A = rng.random((2 * R, R)) + 0.05 * rng.standard_normal((2 * R, R))
+        m = 3.0 * rng.standard_normal(R)
+        S = A.T @ A
+        xc, nc = oracle.bpp_row(S, m)
+        xr, nr = oracle.bpp_row(S, m, x0=rng.random(R) * (rng.random(R) < 0.5))
+        xw, nw = oracle.bpp_row(S, m, x0=xc)
+        assert nc >= 1 and nr >= 1 and nw == 1
+        np.testing.assert_allclose(xr, xc, rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(xw, xc, rtol=1e-10, atol=1e-13)
+
+
 def test_bpp_update_is_the_limit_of_hals():
     """Repeated HALS sweeps over the columns converge to the exact per-row
     NNLS solution, which BPP computes directly (the start values do not
