@@ -692,7 +692,8 @@ __device__ __forceinline__ void wave_sync() {
 // lane c owns index c.  The passive set F is a ballot mask; the indices that
 // break the conditions (x < 0 on F, y < 0 off F) switch sets while their
 // count keeps falling, then three more full switches are allowed, then only
-// the largest index switches (block principal pivoting).  Each switch solves
+// the largest index switches (block principal pivoting).  The search starts
+// from the support of the row's current value H diag(lambda).  Each switch solves
 // S_FF x_F = m_F by a left-looking Cholesky factorisation in the wave's LDS
 // (lane p owns row p of the factor) and two triangular solves, and forms
 // y = S x - m off F.  The search ends when no index breaks the conditions,
@@ -705,7 +706,6 @@ __global__ __launch_bounds__(RB <= 32 ? 256 : 64) void k_update_bpp(UpdateArgs a
   constexpr int LD = RB + 1;             // LDS row stride of the factor
   __shared__ double sS[S_LDS ? RB * RB : 1];
   __shared__ double sL[WPB][RB * LD];
-  __shared__ double sv[WPB][2][RB];
   __shared__ double wred[WPB][64];
   __shared__ double bred[WPB];
   const int R = a.R;
@@ -731,16 +731,122 @@ __global__ __launch_bounds__(RB <= 32 ? 256 : 64) void k_update_bpp(UpdateArgs a
     if (k < ns) macc += mv[k];
   for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
   const double m = (live && own) ? (double)macc : 0.0;
+  const double h0 = (live && own) ? (double)((const HT *)a.H)[ir * R + c] * a.lambda[c] : 0.0;
   __syncthreads();
   auto Sat = [&](int r, int q) -> double { return S_LDS ? sS[r * R + q] : a.S[r * R + q]; };
   double *L = sL[wave];
-  double *zv = sv[wave][0];
-  double *xv = sv[wave][1];
 
-  bool pas = false;
+  // One solve on the passive set Fm: S_FF = L L^T (left-looking; lane p
+  // owns row p of L in the wave's LDS and its diagonal in a register, column
+  // k from columns 0..k-1 with eight products' operands read before they are
+  // added), L z = m_F and L^T x_F = z with the pivots and the running values
+  // broadcast by v_readlane, then y = S x - m off F.  The only cross-lane
+  // LDS reads are of rows of L finished at an earlier step, so one wave
+  // barrier per column suffices.  Returns false (leaving x and y) when S_FF
+  // is not positive definite.
+  auto solve = [&](bool pas, uint64_t Fm, double &x, double &y) -> bool {
+    const int f = __popcll(Fm);
+    const int pos = __popcll(Fm & ((1ull << lane) - 1));
+    wave_sync();
+    if (pas) {
+      uint64_t t = Fm;
+      for (int q = 0; q <= pos; ++q) {
+        const int c2 = __ffsll((unsigned long long)t) - 1;
+        t &= t - 1;
+        L[pos * LD + q] = Sat(c, c2);
+      }
+    }
+    double dk = 0.0;  // L(pos, pos) on the lane that owns row pos
+    {
+      uint64_t t = Fm;
+      for (int k = 0; k < f; ++k) {
+        const int lk = __ffsll((unsigned long long)t) - 1;  // lane of row k
+        t &= t - 1;
+        wave_sync();
+        double v = 0.0;
+        if (pas && pos >= k) {
+          v = L[pos * LD + k];
+          const double *lp = L + pos * LD, *lkr = L + k * LD;
+          int j = 0;
+          for (; j + 8 <= k; j += 8) {
+            double u[8], w[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              u[e] = lp[j + e];
+              w[e] = lkr[j + e];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v -= u[e] * w[e];
+          }
+          for (; j < k; ++j) v -= lp[j] * lkr[j];
+        }
+        const double piv = bcast(v, lk);
+        if (!(piv > 0.0)) return false;
+        const double d = sqrt(piv);
+        if (pas && pos == k) dk = d;
+        if (pas && pos > k) L[pos * LD + k] = v / d;
+      }
+    }
+    wave_sync();
+    // L z = m_F: column by column, z_k broadcast from the lane of row k
+    double b = pas ? m : 0.0, zz = 0.0;
+    {
+      uint64_t t = Fm;
+      for (int k = 0; k < f; ++k) {
+        const int lk = __ffsll((unsigned long long)t) - 1;
+        t &= t - 1;
+        const double zk = bcast(b, lk) / bcast(dk, lk);
+        if (pas && pos == k) zz = zk;
+        if (pas && pos > k) b -= L[pos * LD + k] * zk;
+      }
+    }
+    // L^T x_F = z: rows from the last, x_k broadcast from the lane of row k
+    double xr = 0.0;
+    {
+      // lanes of rows f-1 .. 0: the set bits of Fm from the highest
+      uint64_t t = Fm;
+      for (int k = f - 1; k >= 0; --k) {
+        const int lk = 63 - __clzll(t);
+        t &= ~(1ull << lk);
+        const double xk = bcast(zz, lk) / bcast(dk, lk);
+        if (pas && pos == k) xr = xk;
+        if (pas && pos < k) zz -= L[k * LD + pos] * xk;
+      }
+    }
+    x = pas ? xr : 0.0;
+    double yv = 0.0;
+    {
+      if (own && !pas) yv = -m;
+      uint64_t t = Fm;
+      for (int q = 0; q < f; ++q) {
+        const int lq = __ffsll((unsigned long long)t) - 1;
+        t &= t - 1;
+        const double xq = bcast(xr, lq);
+        if (own && !pas) yv += Sat(c, lq) * xq;
+      }
+    }
+    y = yv;
+    return true;
+  };
+
+  // start from the row's current support (H diag(lambda) > 0), solved once
+  bool pas = own && live && h0 > 0.0;
   double x = 0.0, y = -m;
   int ninf = R + 1, backup = 3, solves = 0;
   const int maxsolves = 5 * R + 10;
+  {
+    const uint64_t F0 = __ballot(pas);
+    bool started = false;
+    if (F0) {
+      ++solves;
+      started = solve(pas, F0, x, y);
+    }
+    if (!started) {
+      pas = false;
+      x = 0.0;
+      y = -m;
+    }
+  }
   for (;;) {
     const bool bad = own && (pas ? (x < 0.0) : (y < 0.0));
     const uint64_t V = __ballot(bad);
@@ -752,67 +858,8 @@ __global__ __launch_bounds__(RB <= 32 ? 256 : 64) void k_update_bpp(UpdateArgs a
     else full = false;
     const int last = 63 - __clzll(V);
     if (bad && (full || lane == last)) pas = !pas;
-    const uint64_t Fm = __ballot(pas);
-    const int f = __popcll(Fm);
-    const int pos = __popcll(Fm & ((1ull << lane) - 1));
-    // rows of S_FF, lane p (passive) writing row p (columns 0..p)
-    wave_sync();
-    if (pas) {
-      uint64_t t = Fm;
-      for (int q = 0; q <= pos; ++q) {
-        const int c2 = __ffsll((unsigned long long)t) - 1;
-        t &= t - 1;
-        L[pos * LD + q] = Sat(c, c2);
-      }
-    }
-    // left-looking Cholesky: column k from the finished columns 0..k-1
-    bool fail = false;
-    for (int k = 0; k < f; ++k) {
-      wave_sync();
-      double v = 0.0;
-      if (pas && pos >= k) {
-        v = L[pos * LD + k];
-        for (int j = 0; j < k; ++j) v -= L[pos * LD + j] * L[k * LD + j];
-        if (pos == k) L[k * LD + k] = v > 0.0 ? sqrt(v) : 0.0;
-      }
-      const bool nonpd = pas && pos == k && !(v > 0.0);
-      if (__ballot(nonpd)) { fail = true; break; }
-      wave_sync();
-      if (pas && pos > k) L[pos * LD + k] = v / L[k * LD + k];
-    }
     ++solves;
-    if (fail) break;
-    // L z = m_F (column by column), then L^T x_F = z
-    double b = pas ? m : 0.0;
-    for (int k = 0; k < f; ++k) {
-      wave_sync();
-      if (pas && pos == k) zv[k] = b / L[k * LD + k];
-      wave_sync();
-      if (pas && pos > k) b -= L[pos * LD + k] * zv[k];
-    }
-    double zz = 0.0;
-    wave_sync();
-    if (pas) zz = zv[pos];
-    for (int k = f - 1; k >= 0; --k) {
-      wave_sync();
-      if (pas && pos == k) xv[k] = zz / L[k * LD + k];
-      wave_sync();
-      if (pas && pos < k) zz -= L[k * LD + pos] * xv[k];
-    }
-    wave_sync();
-    x = pas ? xv[pos] : 0.0;
-    // y = S x - m off F
-    double yv = 0.0;
-    if (own && !pas) {
-      yv = -m;
-      uint64_t t = Fm;
-      for (int q = 0; q < f; ++q) {
-        const int c2 = __ffsll((unsigned long long)t) - 1;
-        t &= t - 1;
-        yv += Sat(c, c2) * xv[q];
-      }
-    }
-    y = yv;
+    if (!solve(pas, __ballot(pas), x, y)) break;
   }
   const double h = (own && x > 0.0) ? x : 0.0;
   double sq = 0.0, beta = 0.0;
