@@ -123,18 +123,27 @@ def gemm_bytes(dims, R, xbytes, side):
     return I * xbytes + out_rows * R * 4
 
 
-def cpu_baseline(X32, H0, algo_oracle, nthreads):
+def cpu_baseline(X32, H0, algo_oracle, nthreads, min_seconds=10.0, max_sweeps=30):
+    """The oracle on the host: HALS sweeps of the same 512^3 tensor in FP64,
+    run one after another from the same start until min_seconds have passed
+    (at most max_sweeps), reported as sweeps/s."""
     import numpy as np
     import oracle
     Xh = X32.double().cpu().numpy().reshape(-1)
     Hh = [h.double().cpu().numpy() for h in H0]
     R = Hh[0].shape[1]
+    lam = np.ones(R)
+    n = 0
     t0 = time.perf_counter()
-    oracle.sweeps(Xh, Hh, np.ones(R), algo_oracle, 1, nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="sweeps/s", cores=nthreads, kind="oracle",
-                sample=f"one HALS sweep (3 MTTKRPs by definition + updates) of the same 512^3 "
-                       f"tensor in FP64, {dt:.2f} s on {nthreads} host threads")
+    while True:
+        Hh, lam, _, _ = oracle.sweeps(Xh, Hh, lam, algo_oracle, 1, nthreads=nthreads)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or n >= max_sweeps:
+            break
+    return dict(value=n / dt, unit="sweeps/s", cores=nthreads, kind="oracle",
+                sample=f"{n} HALS sweeps (3 MTTKRPs by definition + updates each) of the same "
+                       f"512^3 tensor in FP64, {dt:.1f} s on {nthreads} host threads")
 
 
 # ---------------------------------------------------------------------------
@@ -200,6 +209,34 @@ def run_configs(names):
                        sweeps_per_s=1e3 / mps, final_relerr=rel[-1],
                        **_gemm_rates(w["dims"], w["R"], 8, ctx.split(), cm, cn))
             ctx.close()
+        elif name == "c2bpp":
+            # the 512^3 BF16 workload, 50 sweeps with HALS and with BPP from
+            # the same start; BPP's time to reach HALS's final error
+            w = gen.workload2(keep_fp32=False)
+            H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+            res = dict(config="c2bpp", workload=w["name"], sweeps=50)
+            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp")):
+                ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
+                mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, algo, 50)
+                res[an] = dict(ms_per_sweep=mps, sweeps_per_s=1e3 / mps, final_relerr=rel[-1],
+                               relerr_every_10=rel[9::10], update_ms_per_sweep=cm[4] / 50)
+                ctx.close()
+            # error trajectories from the start factors (the timed replays
+            # above began after one warm-up sweep)
+            traj = {}
+            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp")):
+                ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
+                traj[an] = ctx.sweep(algo, 50).cpu().tolist()
+                ctx.close()
+            target = traj["hals"][-1]
+            relb = traj["bpp"]
+            res["hals_relerr_after_50"] = target
+            res["bpp_relerr_after_50"] = relb[-1]
+            k = next((i + 1 for i, r in enumerate(relb) if r <= target), None)
+            res["bpp_sweeps_to_hals_final_relerr"] = k
+            res["bpp_ms_to_hals_final_relerr"] = None if k is None else k * res["bpp"]["ms_per_sweep"]
+            res["hals_ms_for_50_sweeps"] = 50 * res["hals"]["ms_per_sweep"]
+            del w
         elif name == "c3":
             w = gen.workload3()
             H = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
@@ -316,6 +353,35 @@ def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write):
         print(f"{kname}: {len(ids)} dispatches, {hbm / 2**20:.1f} MiB per launch")
 
 
+def summarize_mfma(csv_path, cmd):
+    """MFMA utilisation per partial-MTTKRP kernel from a rocprofv3 --pmc run of
+    SQ_VALU_MFMA_BUSY_CYCLES (summed over every SIMD) and GRBM_GUI_ACTIVE
+    (summed over the 8 XCDs): busy / (GUI cycles per XCD x 1024 SIMDs)."""
+    import collections
+    import csv
+    by = collections.defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        d = by[int(r["Dispatch_Id"])]
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["name"] = r["Kernel_Name"]
+    lines = [f"# MFMA utilisation of the partial MTTKRP kernels, 512x512x512 R=32 HALS workload",
+             f"# command: {cmd}",
+             f"# summarised with: python bench.py --summarize-mfma <counter_collection.csv>",
+             f"# kernel_source_sha = {source_sha()}",
+             f"# util = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 * 1024 SIMDs)",
+             " dispatches  mfma_busy_cycles  gui_active_per_xcd   util  kernel"]
+    for key, test in KERNEL_PATTERNS.items():
+        rows = [v for v in by.values() if test(v["name"])]
+        if not rows:
+            continue
+        mb = sum(v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for v in rows) / len(rows)
+        ga = sum(v.get("GRBM_GUI_ACTIVE", 0.0) for v in rows) / len(rows) / 8.0
+        lines.append(f" {len(rows):10d}  {mb:16.0f}  {ga:18.0f}  {mb / (ga * 1024):5.3f}  {key}")
+    with open(os.path.join(ROOT, "profiles", "mfma_util_512cube.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt"):
     """Write profiles/<out_name>: the library's kernels from a rocprofv3
     --kernel-trace --stats run (calls, average and total duration)."""
@@ -351,6 +417,11 @@ def main():
                  "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe")
         cmd_w = cmd_f.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_fetch", "pmc_write").replace("-o f", "-o w")
         summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w)
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-mfma":
+        summarize_mfma(sys.argv[2], "rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE "
+                       "--output-format csv -d gpurun_out/pmc_mfma -o m -- python3 bench.py "
+                       "--steps 3 --warmup 1 --no-cpu-baseline")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--configs":
         run_configs(sys.argv[2].split(","))
