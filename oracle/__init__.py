@@ -30,6 +30,7 @@ _LIB = os.path.join(_HERE, "_liboracle.so")
 MU = 0
 HALS = 1
 BPP = 2
+ADMM = 3
 
 
 def build(force: bool = False) -> str:
@@ -71,6 +72,8 @@ def lib():
         L.orc_update_bpp.restype = i64
         L.orc_bpp_row.argtypes = [ci, pd, pd, pd, pd]
         L.orc_bpp_row.restype = ci
+        L.orc_update_admm.argtypes = [i64, ci, pd, pd, pd, pd, ci, d]
+        L.orc_update_admm.restype = ci
         L.orc_sweeps.argtypes = [ci, pi64, ci, pd, ppd, pd, ci, d, ci, pd, pd, ci]
         L.orc_residual.argtypes = [ci, pi64, ci, pd, ppd, pd, pd]
         L.orc_residual.restype = d
@@ -193,6 +196,18 @@ def bpp_row(S, m, x0=None):
     work = np.zeros(R * R + 4 * R)
     n = lib().orc_bpp_row(R, _pd(S), _pd(m), _pd(x), _pd(work))
     return x, int(n)
+
+
+def update_admm(Hhat, U, M, S, maxit: int = 5, tol: float = 0.01):
+    """ADMM passes from the start value Hhat with dual U.  Returns
+    (Hhat, U, passes)."""
+    H = _f64(Hhat).copy()
+    Uc = _f64(U).copy()
+    M = _f64(M)
+    S = _f64(S)
+    n = lib().orc_update_admm(H.shape[0], H.shape[1], _pd(H), _pd(Uc), _pd(M), _pd(S), int(maxit),
+                              float(tol))
+    return H, Uc, int(n)
 
 
 def normalize(Hhat):

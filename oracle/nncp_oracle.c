@@ -18,6 +18,8 @@
  *   - MU rule, Eq. (eqn:muupd); HALS rule, Eq. (eqn:halsupd), Section 4.3;
  *   - BPP (exact NNLS per row, Eq. (eqn:snls) and its KKT conditions),
  *     Section 4.3.3, with the pivoting rule of the method the paper cites;
+ *   - ADMM, Eqs. (eqn:admmnls), (eqn:admmupd), Section 4.3.4 (at most 5
+ *     passes, rho = trace(S)/R, the stopping test of the cited method);
  *   - column normalisation with weights lambda, Appendix "Factor Matrix
  *     Normalization" and Algorithm 4 (alg:Par-NNCP-long);
  *   - relative error through the identity
@@ -37,6 +39,9 @@
  *   - all N factors are given as the start iterate (Algorithm 1 initialises
  *     only modes 2..N, but MU and HALS need a start value for mode 1 as well);
  *   - a zero column stays zero with lambda_r = 0;
+ *   - the ADMM dual U of each mode starts at zero and is kept from one
+ *     update of that mode to the next (it lives with the solver, like the
+ *     auxiliary variables the paper's solver classes hold);
  *   - the squared relative error is clamped at 0 before the square root.
  *
  * Layouts: the tensor is stored with mode 0 varying fastest (the local
@@ -395,6 +400,86 @@ int64_t orc_update_bpp(int64_t I, int R, double *Hhat, const double *M, const do
 }
 
 /*
+ * ADMM, Section 4.3.4 with Eqs. (eqn:admmnls) and (eqn:admmupd), written for
+ * the factor (H = X^T, A^T A = S, A^T B = M^T), with the scaled dual U:
+ *   rho   = trace(S) / R                     (||A||_F^2 / R)
+ *   Ht    = (M + rho (H + U)) (S + rho I)^-1  (Cholesky of S + rho I, once)
+ *   H     = max(0, Ht - U)
+ *   U     = U + H - Ht
+ * repeated at most maxit times; after each pass the stopping test of the
+ * cited method is taken on the whole factor:
+ *   r = ||H - Ht||_F^2 / ||H||_F^2 < tol  and  s = ||H - H_prev||_F^2 / ||U||_F^2 < tol
+ * (a zero denominator counts as passing only when its numerator is 0).
+ * Hhat (the start value) and U are updated in place.  Returns the number of
+ * passes, or -1 if S + rho I is not positive definite (Hhat unchanged).
+ */
+int orc_update_admm(int64_t I, int R, double *Hhat, double *U, const double *M,
+                    const double *S, int maxit, double tol) {
+  double tr = 0.0;
+  for (int r = 0; r < R; ++r) tr += S[r * R + r];
+  const double rho = tr / R;
+  double *L = (double *)malloc(sizeof(double) * (size_t)R * R);
+  double *z = (double *)malloc(sizeof(double) * (size_t)R);
+  double *Ht = (double *)malloc(sizeof(double) * (size_t)(I * R));
+  double *Hp = (double *)malloc(sizeof(double) * (size_t)(I * R));
+  int rc = 0;
+  /* S + rho I = L L^T */
+  for (int a = 0; a < R && rc == 0; ++a) {
+    for (int b = 0; b <= a; ++b) {
+      double v = S[a * R + b] + (a == b ? rho : 0.0);
+      for (int c = 0; c < b; ++c) v -= L[a * R + c] * L[b * R + c];
+      if (b == a) {
+        if (!(v > 0.0)) { rc = -1; break; }
+        L[a * R + a] = sqrt(v);
+      } else {
+        L[a * R + b] = v / L[b * R + b];
+      }
+    }
+  }
+  int pass = 0;
+  while (rc == 0 && pass < maxit) {
+    ++pass;
+    double nd = 0.0, nh = 0.0, nc = 0.0, nu = 0.0;
+    for (int64_t i = 0; i < I; ++i) {
+      double *h = Hhat + i * R, *u = U + i * R, *t = Ht + i * R;
+      /* (S + rho I) t^T = (m + rho (h + u))^T: L z = ., L^T t = z */
+      for (int a = 0; a < R; ++a) {
+        double v = M[i * R + a] + rho * (h[a] + u[a]);
+        for (int c = 0; c < a; ++c) v -= L[a * R + c] * z[c];
+        z[a] = v / L[a * R + a];
+      }
+      for (int a = R - 1; a >= 0; --a) {
+        double v = z[a];
+        for (int c = a + 1; c < R; ++c) v -= L[c * R + a] * z[c];
+        z[a] = v / L[a * R + a];
+      }
+      for (int a = 0; a < R; ++a) {
+        t[a] = z[a];
+        Hp[i * R + a] = h[a];
+        const double hn = t[a] - u[a] > 0.0 ? t[a] - u[a] : 0.0;
+        h[a] = hn;
+        u[a] += hn - t[a];
+      }
+    }
+    for (int64_t e = 0; e < I * R; ++e) {
+      const double d = Hhat[e] - Ht[e], c = Hhat[e] - Hp[e];
+      nd += d * d;
+      nh += Hhat[e] * Hhat[e];
+      nc += c * c;
+      nu += U[e] * U[e];
+    }
+    const int rok = nh > 0.0 ? nd / nh < tol : nd == 0.0;
+    const int sok = nu > 0.0 ? nc / nu < tol : nc == 0.0;
+    if (rok && sok) break;
+  }
+  free(L);
+  free(z);
+  free(Ht);
+  free(Hp);
+  return rc == 0 ? pass : -1;
+}
+
+/*
  * Column normalisation (Algorithm 4, column-norm and column-scale lines):
  * lambda_r = ||Hhat[:,r]||_2 and H[:,r] = Hhat[:,r] / lambda_r, or a zero
  * column with lambda_r = 0.
@@ -413,7 +498,9 @@ void orc_normalize(int64_t I, int R, const double *Hhat, double *H, double *lamb
 /* alternating-update sweeps                                            */
 /* ------------------------------------------------------------------ */
 
-enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2 };
+enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3 };
+#define ORC_ADMM_MAXIT 5
+#define ORC_ADMM_TOL 0.01
 
 /*
  * nsweeps outer iterations of Algorithm 1 with the local steps of
@@ -427,7 +514,7 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
                double *lambda, int algo, double eps_mu, int nsweeps,
                double *relerr, double *relerr2_raw, int nthreads) {
   if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0) return -1;
-  if (algo != ORC_MU && algo != ORC_HALS && algo != ORC_BPP) return -1;
+  if (algo != ORC_MU && algo != ORC_HALS && algo != ORC_BPP && algo != ORC_ADMM) return -1;
   const int64_t I = prod_dims(N, dims);
   double *G[ORC_MAXN];
   int64_t maxI = 0;
@@ -438,6 +525,10 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
   }
   double *M = (double *)malloc(sizeof(double) * (size_t)(maxI * R));
   double *Hhat = (double *)malloc(sizeof(double) * (size_t)(maxI * R));
+  /* ADMM duals, one per mode, zero at the start and kept across sweeps */
+  double *Ud[ORC_MAXN];
+  for (int k = 0; k < N; ++k)
+    Ud[k] = algo == ORC_ADMM ? (double *)calloc((size_t)(dims[k] * R), sizeof(double)) : NULL;
   double *S = (double *)malloc(sizeof(double) * (size_t)R * R);
   const double alpha = orc_sumsq(I, X);
 
@@ -453,8 +544,10 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
         orc_update_mu(In, R, Hhat, M, S, eps_mu);
       else if (algo == ORC_HALS)
         orc_update_hals(In, R, Hhat, M, S);
-      else
+      else if (algo == ORC_BPP)
         orc_update_bpp(In, R, Hhat, M, S);
+      else
+        orc_update_admm(In, R, Hhat, Ud[n], M, S, ORC_ADMM_MAXIT, ORC_ADMM_TOL);
       orc_normalize(In, R, Hhat, H[n], lambda);
       orc_gram(In, R, H[n], G[n]);
       if (n == N - 1) {
@@ -469,7 +562,10 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
     if (relerr2_raw) relerr2_raw[s] = e2;
     relerr[s] = sqrt(e2 > 0.0 ? e2 : 0.0);
   }
-  for (int k = 0; k < N; ++k) free(G[k]);
+  for (int k = 0; k < N; ++k) {
+    free(G[k]);
+    free(Ud[k]);
+  }
   free(M);
   free(Hhat);
   free(S);

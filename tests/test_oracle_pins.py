@@ -347,6 +347,54 @@ def test_bpp_update_is_the_limit_of_hals():
     assert subproblem_objective(Hb, M, S) <= subproblem_objective(Hh, M, S) + 1e-12
 
 
+# ---------------------------------------------------------------------------
+# ADMM (Section 4.3.4)
+# ---------------------------------------------------------------------------
+
+def test_admm_single_pass_is_regularised_least_squares():
+    """One pass from (H, U): Ht minimises ||A t - b||^2 + rho ||t - (h + u)||^2,
+    solved here as a stacked least-squares problem with lstsq (no normal
+    equations), rho = ||A||_F^2 / R; then H = max(0, Ht - U), U += H - Ht."""
+    dims = [6, 5, 4]
+    R, n = 3, 1
+    X, H, A, M, S = _subproblem(dims, R, n, 13)
+    B = unfold(X, dims, n)                  # I_n x J, so M = B A
+    rng = np.random.default_rng(14)
+    H0 = rng.random((dims[n], R))
+    U0 = 0.1 * rng.standard_normal((dims[n], R))
+    rho = np.linalg.norm(A) ** 2 / R
+    Ht = np.zeros_like(H0)
+    for i in range(dims[n]):
+        lhs = np.vstack([A, np.sqrt(rho) * np.eye(R)])
+        rhs = np.concatenate([B[i], np.sqrt(rho) * (H0[i] + U0[i])])
+        Ht[i] = np.linalg.lstsq(lhs, rhs, rcond=None)[0]
+    Hn = np.maximum(0.0, Ht - U0)
+    Un = U0 + Hn - Ht
+    Ho, Uo, passes = oracle.update_admm(H0, U0, M, S, maxit=1)
+    assert passes == 1
+    np.testing.assert_allclose(Ho, Hn, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(Uo, Un, rtol=1e-10, atol=1e-12)
+
+
+def test_admm_fixed_point_and_limit_are_the_nnls_solution():
+    rng = np.random.default_rng(15)
+    R = 6
+    A = rng.random((20, R))
+    Bm = rng.standard_normal((9, 20)) + 0.5
+    S = A.T @ A
+    M = Bm @ A
+    Xs = np.stack([nnls(A, b)[0] for b in Bm])          # scipy NNLS per row
+    rho = np.trace(S) / R
+    Us = (Xs @ S - M) / rho                               # scaled dual at the optimum
+    Ho, Uo, passes = oracle.update_admm(Xs, Us, M, S, maxit=5)
+    assert passes == 1                                    # stops at once: r = s = 0
+    np.testing.assert_allclose(Ho, Xs, rtol=1e-9, atol=1e-12)
+    # from a cold start many passes reach the same solution
+    Ho, Uo, passes = oracle.update_admm(np.zeros_like(Xs), np.zeros_like(Xs), M, S, maxit=3000,
+                                        tol=1e-30)
+    np.testing.assert_allclose(Ho, Xs, rtol=1e-6, atol=1e-9)
+
+
 def test_mu_invariants():
     dims = [6, 5, 4]
     X, H, A, M, S = _subproblem(dims, 3, 2, 10)
@@ -366,7 +414,7 @@ def test_mu_invariants():
 # sweeps: identity, monotonicity, exact low rank, KKT
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP])
+@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP, oracle.ADMM])
 @pytest.mark.parametrize("dims", [[6, 5, 4], [4, 3, 5, 2]])
 def test_sweep_relerr_identity_matches_direct_residual(algo, dims):
     X, H0 = gen.small_lowrank(dims, 3, 3, 21, noise=0.05)
