@@ -76,7 +76,7 @@ enum nncp_status {
 
 enum nncp_dtype { NNCP_F64 = 0, NNCP_F32 = 1, NNCP_BF16 = 2, NNCP_F16 = 3 };
 
-enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1, NNCP_BPP = 2 };
+enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1, NNCP_BPP = 2, NNCP_ADMM = 3 };
 
 /* Options (pass NULL for the defaults, shown in brackets). */
 typedef struct nncp_options {
@@ -176,6 +176,22 @@ int nncp_update_hals(nncp_ctx *ctx, int mode, const void *M, const double *S);
  * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_BPP as its algo.
  */
 int nncp_update_bpp(nncp_ctx *ctx, int mode, const void *M, const double *S);
+
+/*
+ * ADMM update of mode n (Section 4.3.4, Eqs. eqn:admmnls and eqn:admmupd),
+ * written for the factor with the scaled dual U^(n) (I_n x R FP64, held in
+ * the workspace, zero after nncp_init and nncp_set_factors, and kept from
+ * one ADMM update of mode n to the next):
+ *   rho = trace(S) / R;  Ht = (M + rho (Hhat + U)) (S + rho I)^-1;
+ *   Hhat = max(0, Ht - U);  U = U + Hhat - Ht,
+ * starting from Hhat = H^(n) diag(lambda), at most 5 passes, stopped after a
+ * pass once ||Hhat - Ht||^2 / ||Hhat||^2 < 0.01 and
+ * ||Hhat - Hhat_prev||^2 / ||U||^2 < 0.01 over the whole factor (the test of
+ * the method the paper cites).  (S + rho I)^-1 is formed once per update from
+ * its Cholesky factor.  Then normalisation and G^(n) as above.  R <= 64
+ * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_ADMM as its algo.
+ */
+int nncp_update_admm(nncp_ctx *ctx, int mode, const void *M, const double *S);
 
 /*
  * Loss of the current model through the identity of the appendix:

@@ -50,7 +50,8 @@ struct Layout {
   int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
   // byte offsets into the workspace
   size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart, off_ticket,
-      off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, total;
+      off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_admmU,
+      off_admmMc, off_admmP, off_admmNorm, off_admmStatus, total;
 };
 
 nncp_options default_options() {
@@ -263,6 +264,13 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_ks = take(hs * L.kslow_elems);
   L.off_pgdH = take(hs * L.sumI * R);
   L.off_pgdG = take(hs * L.sumI * R);
+  // ADMM (R <= 64): duals of every mode, the kept M sum, P and rho, norms
+  const bool admm = R <= 64;
+  L.off_admmU = take(admm ? sizeof(double) * L.sumI * R : 0);
+  L.off_admmMc = take(admm ? sizeof(double) * L.maxI * R : 0);
+  L.off_admmP = take(admm ? sizeof(double) * (R * R + 2) : 0);
+  L.off_admmNorm = take(admm ? sizeof(double) * kAdmmMaxit * ((L.maxI + 3) / 4) * 4 : 0);
+  L.off_admmStatus = take(admm ? sizeof(int) * kAdmmMaxit : 0);
   L.total = o;
   return NNCP_OK;
 }
@@ -301,6 +309,8 @@ struct nncp_ctx {
   char *ws;
   double *G, *Gt, *S, *scal, *ones, *hhat, *upart, *gpart, *red;
   unsigned *ticket;
+  double *admmU, *admmMc, *admmP, *admmNorm;
+  int *admmStatus;
   void *M, *nodeA, *nodeB, *part, *kf, *ks;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
 };
@@ -481,6 +491,15 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.part = c->upart;
   a.gpart = c->gpart;
   a.ticket = c->ticket;
+  {
+    int64_t off = 0;
+    for (int k = 0; k < n; ++k) off += L.dims[k] * L.R;
+    a.admmU = c->admmU + off;
+  }
+  a.admmMc = c->admmMc;
+  a.admmP = c->admmP;
+  a.admmNorm = c->admmNorm;
+  a.admmStatus = c->admmStatus;
   a.eps = eps;
   a.alpha = c->scal + 8;
   a.relerr_out = relerr_out;
@@ -543,6 +562,11 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->upart = (double *)(c->ws + L.off_upart);
   c->gpart = (double *)(c->ws + L.off_gpart);
   c->ticket = (unsigned *)(c->ws + L.off_ticket);
+  c->admmU = (double *)(c->ws + L.off_admmU);
+  c->admmMc = (double *)(c->ws + L.off_admmMc);
+  c->admmP = (double *)(c->ws + L.off_admmP);
+  c->admmNorm = (double *)(c->ws + L.off_admmNorm);
+  c->admmStatus = (int *)(c->ws + L.off_admmStatus);
   c->red = (double *)(c->ws + L.off_red);
   c->M = c->ws + L.off_M;
   c->nodeA = c->ws + L.off_A;
@@ -567,6 +591,9 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
     hipError_t e = hipMemcpyAsync(c->ones, onesh, sizeof(double) * R, hipMemcpyHostToDevice, c->st);
     // the finish kernel's ticket counter starts at zero and is left at zero
     if (e == hipSuccess) e = hipMemsetAsync(c->ticket, 0, sizeof(unsigned), c->st);
+    // ADMM duals start at zero
+    if (e == hipSuccess && R <= 64)
+      e = hipMemsetAsync(c->admmU, 0, sizeof(double) * L.sumI * R, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
       delete c;
@@ -597,6 +624,9 @@ int nncp_set_factors(nncp_ctx *c, void *const *H, double *lambda) {
   for (int n = 0; n < c->L.N; ++n) c->H[n] = H[n];
   if (lambda) c->lambda = lambda;
   ++c->binding;
+  // a new start point: the ADMM duals start again from zero
+  if (c->L.R <= 64)
+    HIPCHK(hipMemsetAsync(c->admmU, 0, sizeof(double) * c->L.sumI * c->L.R, c->st));
   return refresh_grams(c, factors_of(c, c->H), c->G);
 }
 
@@ -663,6 +693,13 @@ int nncp_update_bpp(nncp_ctx *c, int mode, const void *M, const double *S) {
   if (rc) return rc;
   if (c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "BPP needs R <= 64 (R = %d)", c->L.R);
   return update_api(c, NNCP_BPP, mode, M, S, 0.0);
+}
+
+int nncp_update_admm(nncp_ctx *c, int mode, const void *M, const double *S) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "ADMM needs R <= 64 (R = %d)", c->L.R);
+  return update_api(c, NNCP_ADMM, mode, M, S, 0.0);
 }
 
 int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
@@ -738,8 +775,9 @@ static int build_graph(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) 
 int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo != NNCP_MU && algo != NNCP_HALS && algo != NNCP_BPP) return fail(NNCP_E_INVAL, "algo %d", algo);
-  if (algo == NNCP_BPP && c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "BPP needs R <= 64 (R = %d)", c->L.R);
+  if (algo < NNCP_MU || algo > NNCP_ADMM) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if ((algo == NNCP_BPP || algo == NNCP_ADMM) && c->L.R > 64)
+    return fail(NNCP_E_UNSUPPORTED, "BPP and ADMM need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
   if (nsweeps == 0) return NNCP_OK;
   // Eager launches while timing (each launch is bracketed by events) or when
@@ -758,8 +796,9 @@ int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
 int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo != NNCP_MU && algo != NNCP_HALS && algo != NNCP_BPP) return fail(NNCP_E_INVAL, "algo %d", algo);
-  if (algo == NNCP_BPP && c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "BPP needs R <= 64 (R = %d)", c->L.R);
+  if (algo < NNCP_MU || algo > NNCP_ADMM) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if ((algo == NNCP_BPP || algo == NNCP_ADMM) && c->L.R > 64)
+    return fail(NNCP_E_UNSUPPORTED, "BPP and ADMM need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 1) return fail(NNCP_E_INVAL, "nsweeps %d < 1", nsweeps);
   if (!c->L.opt.graphs) return fail(NNCP_E_INVAL, "graphs are switched off for this context");
   return build_graph(c, algo, nsweeps, relerr_hist);

@@ -147,7 +147,14 @@ struct UpdateArgs {
   const double *alpha;
   double *relerr_out;
   double *scal;         // [0]=beta [1]=gamma [2]=raw relerr^2
+  // ADMM (R <= 64): the mode's dual U (I x R, in/out), the summed M of the
+  // first pass (I x R), the inverse of S + rho I with rho and a failure flag
+  // after it (R x R + 2), per-pass per-workgroup norms and per-pass status
+  double *admmU, *admmMc, *admmP, *admmNorm;
+  int *admmStatus;
 };
+constexpr int kAdmmMaxit = 5;         // passes per ADMM update (Section 4.3.4)
+constexpr double kAdmmTol = 0.01;     // stopping tolerance of the cited method
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st);
 // workgroups of the finish kernel (R <= 64) and the rows each one normalises
 constexpr int kNormWG = 16;

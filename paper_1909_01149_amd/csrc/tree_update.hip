@@ -888,6 +888,195 @@ __global__ __launch_bounds__(RB <= 32 ? 256 : 64) void k_update_bpp(UpdateArgs a
   }
 }
 
+// ---------------------------------------------------------------------------
+// ADMM (Section 4.3.4, Eqs. eqn:admmnls and eqn:admmupd), for the factor
+// (H = X^T, A^T A = S, A^T B = M^T) with the scaled dual U of the mode:
+//   rho = trace(S) / R,  Ht = (M + rho (H + U)) (S + rho I)^-1,
+//   H = max(0, Ht - U),  U = U + H - Ht,
+// at most kAdmmMaxit passes, stopped after a pass once
+//   ||H - Ht||^2 / ||H||^2 < tol  and  ||H - H_prev||^2 / ||U||^2 < tol
+// over the whole factor.  The Cholesky factor of S + rho I is cached (here as
+// the inverse P = L^-T L^-1, formed once per update: S + rho I has condition
+// number at most R + 1, so a pass is one row-times-P product).
+
+// P and rho, one wave: lane p owns row p of L (left-looking, as in the BPP
+// solve), lane j then forms column j of W = L^-1 and column j of P = W^T W.
+template <int RB>
+__global__ __launch_bounds__(64) void k_admm_prep(UpdateArgs a) {
+  constexpr int LD = RB <= 32 ? RB + 1 : RB;  // two R x LD arrays within 64 KB
+  __shared__ double sL[RB * LD];
+  __shared__ double sW[RB * LD];
+  const int R = a.R;
+  const int lane = threadIdx.x;
+  const bool own = lane < R;
+  const double sd = own ? a.S[lane * R + lane] : 0.0;
+  const double rho = wave_sum(sd) / R;
+  if (own)
+    for (int q = 0; q <= lane; ++q) sL[lane * LD + q] = a.S[lane * R + q] + (q == lane ? rho : 0.0);
+  bool fail = false;
+  for (int k = 0; k < R; ++k) {
+    wave_sync();
+    double v = 0.0;
+    if (own && lane >= k) {
+      v = sL[lane * LD + k];
+      for (int j = 0; j < k; ++j) v -= sL[lane * LD + j] * sL[k * LD + j];
+    }
+    const double piv = bcast(v, k);
+    if (!(piv > 0.0)) { fail = true; break; }
+    const double d = sqrt(piv);
+    if (own && lane > k) sL[lane * LD + k] = v / d;
+    wave_sync();
+    if (lane == k) sL[k * LD + k] = d;
+  }
+  wave_sync();
+  if (!fail) {
+    // column j of W = L^-1: rows j.. by forward substitution on e_j
+    if (own) {
+      for (int r = 0; r < R; ++r) {
+        if (r < lane) { sW[r * LD + lane] = 0.0; continue; }
+        double v = r == lane ? 1.0 : 0.0;
+        for (int c = lane; c < r; ++c) v -= sL[r * LD + c] * sW[c * LD + lane];
+        sW[r * LD + lane] = v / sL[r * LD + r];
+      }
+    }
+    wave_sync();
+    // P(i, j) = sum_{k >= max(i, j)} W(k, i) W(k, j), column j by lane j
+    if (own) {
+      for (int i = 0; i < R; ++i) {
+        double v = 0.0;
+        for (int k = (i > lane ? i : lane); k < R; ++k) v += sW[k * LD + i] * sW[k * LD + lane];
+        a.admmP[i * R + lane] = v;
+      }
+    }
+  }
+  if (lane == 0) {
+    a.admmP[R * R] = rho;
+    a.admmP[R * R + 1] = fail ? 1.0 : 0.0;
+  }
+}
+
+// One ADMM pass over every row: one row per wave, lane c owns column c and
+// keeps column c of P in registers.  Pass 0 starts from H diag(lambda) and
+// the split partials of M (added in order; their sum is kept for the later
+// passes); a later pass first takes the stopping test on the previous pass's
+// per-workgroup norms (every workgroup adds them in the same order, so all
+// agree) and does nothing once the updates have stopped.  Each pass leaves
+// the row kernel's partials (column sums of squares and beta) of its result.
+template <typename HT, int RB>
+__global__ __launch_bounds__(256) void k_admm_pass(UpdateArgs a, int pass, int nblocks) {
+  __shared__ double wred[4][64];
+  __shared__ double nred[4][4];
+  __shared__ double bred[4];
+  __shared__ double tred[256][4];
+  __shared__ int run_s;
+  const int R = a.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  const bool live = i < a.I;
+  const bool own = lane < R;
+  const int c = own ? lane : 0;
+  const int64_t ir = live ? i : a.I - 1;
+  const double rho = a.admmP[R * R];
+  const bool singular = a.admmP[R * R + 1] != 0.0;
+  // ---- the stopping test on the previous pass
+  if (threadIdx.x == 0) run_s = 1;
+  if (pass > 0) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *np = a.admmNorm + (int64_t)(pass - 1) * nblocks * 4;
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += np[(int64_t)b * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tred[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < 256; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t[k] += tred[q][k];
+      const double nd = t[0], nh = t[1], nc = t[2], nu = t[3];
+      const bool rok = nh > 0.0 ? nd / nh < kAdmmTol : nd == 0.0;
+      const bool sok = nu > 0.0 ? nc / nu < kAdmmTol : nc == 0.0;
+      run_s = (a.admmStatus[pass - 1] != 0 && !(rok && sok)) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  const bool run = run_s != 0 && !singular;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.admmStatus[pass] = run ? 1 : 0;
+  // a singular S + rho I leaves the start value (pass 0 writes it back)
+  if (!run && !(pass == 0 && singular)) return;
+  // ---- loads: column c of P, the row of M (or its kept sum), H, U
+  double pc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) pc[r] = (own && r < R && run) ? a.admmP[r * R + c] : 0.0;
+  double m, h;
+  if (pass == 0) {
+    const HT *M = (const HT *)a.M;
+    const HT *mp = M + ir * R + c;
+    const int ns = a.msplit;
+    HT mv[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) mv[k] = k < ns ? mp[(int64_t)k * a.mstride] : (HT)0;
+    HT macc = mv[0];
+#pragma unroll
+    for (int k = 1; k < 32; ++k)
+      if (k < ns) macc += mv[k];
+    for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
+    m = (live && own) ? (double)macc : 0.0;
+    h = (live && own) ? (double)((const HT *)a.H)[ir * R + c] * a.lambda[c] : 0.0;
+    if (live && own) a.admmMc[i * R + c] = m;
+  } else {
+    m = (live && own) ? a.admmMc[i * R + c] : 0.0;
+    h = (live && own) ? a.hhat[i * R + c] : 0.0;
+  }
+  const double u = (live && own) ? a.admmU[i * R + c] : 0.0;
+  double hn = h, un = u, t = h;
+  if (run) {
+    // Ht(c) = sum_j (m + rho (h + u))_j P(j, c), j in order
+    const double bj = m + rho * (h + u);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < R) acc += bcast(bj, j) * pc[j];
+    t = acc;
+    hn = t - u > 0.0 ? t - u : 0.0;
+    un = u + hn - t;
+  }
+  double sq = 0.0, beta = 0.0, nd = 0.0, nh = 0.0, nc = 0.0, nu = 0.0;
+  if (live && own) {
+    a.hhat[i * R + c] = hn;
+    a.admmU[i * R + c] = un;
+    sq = hn * hn;
+    beta = m * hn;
+    nd = (hn - t) * (hn - t);
+    nh = hn * hn;
+    nc = (hn - h) * (hn - h);
+    nu = un * un;
+  }
+  wred[wave][lane] = sq;
+  beta = wave_sum(beta);
+  nd = wave_sum(nd);
+  nh = wave_sum(nh);
+  nc = wave_sum(nc);
+  nu = wave_sum(nu);
+  if (lane == 0) {
+    bred[wave] = beta;
+    nred[wave][0] = nd;
+    nred[wave][1] = nh;
+    nred[wave][2] = nc;
+    nred[wave][3] = nu;
+  }
+  __syncthreads();
+  double *cpart = a.part + (int64_t)blockIdx.x * (R + 1);
+  if (threadIdx.x < R)
+    cpart[threadIdx.x] = wred[0][threadIdx.x] + wred[1][threadIdx.x] + wred[2][threadIdx.x] +
+                         wred[3][threadIdx.x];
+  if (threadIdx.x == 0) cpart[R] = bred[0] + bred[1] + bred[2] + bred[3];
+  if (threadIdx.x < 4)
+    a.admmNorm[((int64_t)pass * nblocks + blockIdx.x) * 4 + threadIdx.x] =
+        nred[0][threadIdx.x] + nred[1][threadIdx.x] + nred[2][threadIdx.x] + nred[3][threadIdx.x];
+}
+
 // Upper tiles (tx <= ty) of the T x T grid of 16 x 16 tiles of an R x R
 // matrix, T = ceil(R / 16), in row-major order.
 __device__ __forceinline__ void tile_pair(int t, int T, int &tx, int &ty) {
@@ -1432,7 +1621,12 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
     int64_t rpw;
     const int nw = norm_workgroups(a.I, &rpw);
 #define NNCP_UPDATE_SMALL(RBV)                                                           \
-  if (a.algo == NNCP_BPP) {                                                             \
+  if (a.algo == NNCP_ADMM) {                                                            \
+    hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(64), 0, st, a);                \
+    for (int p = 0; p < kAdmmMaxit; ++p)                                                \
+      hipLaunchKernelGGL((k_admm_pass<HT, RBV>), grid, block, 0, st, a, p, nb);         \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+  } else if (a.algo == NNCP_BPP) {                                                      \
     constexpr int WPB = RBV <= 32 ? 4 : 1;                                              \
     const int nbb = (int)((a.I + WPB - 1) / WPB);                                       \
     hipLaunchKernelGGL((k_update_bpp<HT, RBV>), dim3(nbb), dim3(64 * WPB), 0, st, a);   \
@@ -1450,7 +1644,7 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
     }
 #undef NNCP_UPDATE_SMALL
   } else {
-    if (a.algo == NNCP_BPP) return hipErrorInvalidValue;
+    if (a.algo == NNCP_BPP || a.algo == NNCP_ADMM) return hipErrorInvalidValue;
     if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
     hipLaunchKernelGGL((k_update_finish<HT>), dim3(1), dim3(1024), 0, st, a, nb);
