@@ -215,7 +215,7 @@ def run_configs(names):
             w = gen.workload2(keep_fp32=False)
             H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
             res = dict(config="c2bpp", workload=w["name"], sweeps=50)
-            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp")):
+            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp"), (nn.NNCP_ADMM, "admm")):
                 ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
                 mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, algo, 50)
                 res[an] = dict(ms_per_sweep=mps, sweeps_per_s=1e3 / mps, final_relerr=rel[-1],
@@ -224,18 +224,19 @@ def run_configs(names):
             # error trajectories from the start factors (the timed replays
             # above began after one warm-up sweep)
             traj = {}
-            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp")):
+            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp"), (nn.NNCP_ADMM, "admm")):
                 ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
                 traj[an] = ctx.sweep(algo, 50).cpu().tolist()
                 ctx.close()
             target = traj["hals"][-1]
-            relb = traj["bpp"]
             res["hals_relerr_after_50"] = target
-            res["bpp_relerr_after_50"] = relb[-1]
-            k = next((i + 1 for i, r in enumerate(relb) if r <= target), None)
-            res["bpp_sweeps_to_hals_final_relerr"] = k
-            res["bpp_ms_to_hals_final_relerr"] = None if k is None else k * res["bpp"]["ms_per_sweep"]
             res["hals_ms_for_50_sweeps"] = 50 * res["hals"]["ms_per_sweep"]
+            for an in ("bpp", "admm"):
+                rl = traj[an]
+                res[f"{an}_relerr_after_50"] = rl[-1]
+                k = next((i + 1 for i, r in enumerate(rl) if r <= target), None)
+                res[f"{an}_sweeps_to_hals_final_relerr"] = k
+                res[f"{an}_ms_to_hals_final_relerr"] = None if k is None else k * res[an]["ms_per_sweep"]
             del w
         elif name == "c3":
             w = gen.workload3()

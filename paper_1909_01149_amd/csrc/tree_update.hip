@@ -899,59 +899,58 @@ __global__ __launch_bounds__(RB <= 32 ? 256 : 64) void k_update_bpp(UpdateArgs a
 // the inverse P = L^-T L^-1, formed once per update: S + rho I has condition
 // number at most R + 1, so a pass is one row-times-P product).
 
-// P and rho, one wave: lane p owns row p of L (left-looking, as in the BPP
-// solve), lane j then forms column j of W = L^-1 and column j of P = W^T W.
+// P = (S + rho I)^-1 and rho in one workgroup: in-place Gauss-Jordan
+// elimination without pivoting (the pivots of a symmetric positive definite
+// matrix are its positive Schur complements; the condition number here is at
+// most R + 1), each thread owning entries of the R x R array in LDS, two
+// barriers per pivot.  A pivot that is not positive marks the update as
+// singular (the start value is then kept).
 template <int RB>
-__global__ __launch_bounds__(64) void k_admm_prep(UpdateArgs a) {
-  constexpr int LD = RB <= 32 ? RB + 1 : RB;  // two R x LD arrays within 64 KB
-  __shared__ double sL[RB * LD];
-  __shared__ double sW[RB * LD];
-  const int R = a.R;
-  const int lane = threadIdx.x;
-  const bool own = lane < R;
-  const double sd = own ? a.S[lane * R + lane] : 0.0;
-  const double rho = wave_sum(sd) / R;
-  if (own)
-    for (int q = 0; q <= lane; ++q) sL[lane * LD + q] = a.S[lane * R + q] + (q == lane ? rho : 0.0);
-  bool fail = false;
+__global__ __launch_bounds__(1024) void k_admm_prep(UpdateArgs a) {
+  constexpr int EPT = (RB * RB + 1023) / 1024;  // entries per thread
+  __shared__ double A[RB * RB];
+  __shared__ double red[16];
+  __shared__ int bad_s;
+  const int R = a.R, RR = R * R;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // rho = trace(S) / R
+  const double sd = tid < R ? a.S[tid * R + tid] : 0.0;
+  const double ws = wave_sum(sd);
+  if (lane == 0) red[wave] = ws;
+  if (tid == 0) bad_s = 0;
+  __syncthreads();
+  double tr = 0.0;
+  for (int w = 0; w < 16; ++w) tr += red[w];
+  const double rho = tr / R;
+  for (int e = tid; e < RR; e += 1024) A[e] = a.S[e] + ((e / R) == (e % R) ? rho : 0.0);
+  __syncthreads();
   for (int k = 0; k < R; ++k) {
-    wave_sync();
-    double v = 0.0;
-    if (own && lane >= k) {
-      v = sL[lane * LD + k];
-      for (int j = 0; j < k; ++j) v -= sL[lane * LD + j] * sL[k * LD + j];
-    }
-    const double piv = bcast(v, k);
-    if (!(piv > 0.0)) { fail = true; break; }
-    const double d = sqrt(piv);
-    if (own && lane > k) sL[lane * LD + k] = v / d;
-    wave_sync();
-    if (lane == k) sL[k * LD + k] = d;
-  }
-  wave_sync();
-  if (!fail) {
-    // column j of W = L^-1: rows j.. by forward substitution on e_j
-    if (own) {
-      for (int r = 0; r < R; ++r) {
-        if (r < lane) { sW[r * LD + lane] = 0.0; continue; }
-        double v = r == lane ? 1.0 : 0.0;
-        for (int c = lane; c < r; ++c) v -= sL[r * LD + c] * sW[c * LD + lane];
-        sW[r * LD + lane] = v / sL[r * LD + r];
+    const double piv = A[k * R + k];
+    double nv[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + 1024 * q;
+      nv[q] = 0.0;
+      if (e < RR) {
+        const int i = e / R, j = e % R;
+        const double p = 1.0 / piv;
+        const double akj = j == k ? p : A[k * R + j] * p;   // new row k
+        nv[q] = i == k ? akj : (j == k ? 0.0 : A[e]) - A[i * R + k] * akj;
       }
     }
-    wave_sync();
-    // P(i, j) = sum_{k >= max(i, j)} W(k, i) W(k, j), column j by lane j
-    if (own) {
-      for (int i = 0; i < R; ++i) {
-        double v = 0.0;
-        for (int k = (i > lane ? i : lane); k < R; ++k) v += sW[k * LD + i] * sW[k * LD + lane];
-        a.admmP[i * R + lane] = v;
-      }
+    if (tid == 0 && !(piv > 0.0)) bad_s = 1;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + 1024 * q;
+      if (e < RR) A[e] = nv[q];
     }
+    __syncthreads();
   }
-  if (lane == 0) {
-    a.admmP[R * R] = rho;
-    a.admmP[R * R + 1] = fail ? 1.0 : 0.0;
+  for (int e = tid; e < RR; e += 1024) a.admmP[e] = A[e];
+  if (tid == 0) {
+    a.admmP[RR] = rho;
+    a.admmP[RR + 1] = bad_s ? 1.0 : 0.0;
   }
 }
 
@@ -1622,7 +1621,7 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
     const int nw = norm_workgroups(a.I, &rpw);
 #define NNCP_UPDATE_SMALL(RBV)                                                           \
   if (a.algo == NNCP_ADMM) {                                                            \
-    hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(64), 0, st, a);                \
+    hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(1024), 0, st, a);              \
     for (int p = 0; p < kAdmmMaxit; ++p)                                                \
       hipLaunchKernelGGL((k_admm_pass<HT, RBV>), grid, block, 0, st, a, p, nb);         \
     hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
