@@ -153,18 +153,21 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
   const bool live = r < a.R;
   __shared__ double red[256];
   double mx = 0.0;
-  if (live)
-    for (int64_t p = threadIdx.x; p < a.Pf; p += 256) {
-      const double v = krp_entry<HT>(a, a.fast_lo, a.fast_hi, p, r);
-      mx = fmax(mx, fabs(v));
-    }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+  // the column maximum only matters for the FP16 scaling
+  if (a.scale16) {
+    if (live)
+      for (int64_t p = threadIdx.x; p < a.Pf; p += 256) {
+        const double v = krp_entry<HT>(a, a.fast_lo, a.fast_hi, p, r);
+        mx = fmax(mx, fabs(v));
+      }
+    red[threadIdx.x] = mx;
     __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+      __syncthreads();
+    }
+    mx = red[0];
   }
-  mx = red[0];
   int e = 0;
   if (a.scale16 && mx > 0.0) {
     int E;
@@ -172,13 +175,15 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
     e = 14 - E;     // max entry lands in [2^13, 2^14)
   }
   const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
-  for (int64_t p = threadIdx.x; p < a.Pf; p += 256) {
+  // without the FP16 scaling the column is split over gridDim.y workgroups
+  const int64_t t0 = threadIdx.x + 256 * (int64_t)blockIdx.y, ts = 256 * (int64_t)gridDim.y;
+  for (int64_t p = t0; p < a.Pf; p += ts) {
     const double v = live ? krp_entry<HT>(a, a.fast_lo, a.fast_hi, p, r) * up : 0.0;
     const XT hi = from_d<XT>(v);
     kfast[(int64_t)r * a.Pf + p] = hi;
     if (a.hl) kfast[((int64_t)a.Rpad + r) * a.Pf + p] = from_d<XT>(v - to_d<XT>(hi));
   }
-  for (int64_t q = threadIdx.x; q < a.Ps; q += 256) {
+  for (int64_t q = t0; q < a.Ps; q += ts) {
     const double w = live ? krp_entry<HT>(a, a.slow_lo, a.slow_hi, q, r) * down : 0.0;
     kslow[q * a.Rpad + r] = (HT)w;
   }
@@ -721,7 +726,12 @@ static KrpArgs make_krp_args(const GemmPlan &p, int R, const int64_t *dims, cons
 hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t *dims, int N,
                                const FactorSet &F, void *kfast, void *kslow, hipStream_t st) {
   KrpArgs a = make_krp_args(p, R, dims, F, N);
-  dim3 grid(p.Rpad), block(256);
+  // one workgroup per column and per 256 entries of the longer part (one per
+  // column for FP16, whose scaling needs the column maximum)
+  const int64_t longest = p.Pf > p.Ps ? p.Pf : p.Ps;
+  int64_t chunks = (longest + 255) / 256;
+  if (chunks > 64) chunks = 64;
+  dim3 grid(p.Rpad, xdt == NNCP_F16 ? 1 : (unsigned)chunks), block(256);
   switch (xdt) {
     case NNCP_BF16:
       hipLaunchKernelGGL((k_krp_operands<bf16_t, float>), grid, block, 0, st, a, (bf16_t *)kfast, (float *)kslow);
