@@ -49,7 +49,7 @@ struct Layout {
   GemmPlan gp[2];
   int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
   // byte offsets into the workspace
-  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart, off_ticket,
+  size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart,
       off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_admmU,
       off_admmMc, off_admmP, off_admmNorm, off_admmStatus, total;
 };
@@ -254,7 +254,6 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_hhat = take(sizeof(double) * L.maxI * R);
   L.off_upart = take(sizeof(double) * update_part_elems(L.maxI, R));
   L.off_gpart = take(R <= 64 ? sizeof(double) * norm_gpart_elems(R) : 0);
-  L.off_ticket = take(sizeof(unsigned));
   L.off_red = take(sizeof(double) * 1024);
   L.off_M = take(hs * L.maxI * R);
   L.off_A = take(hs * L.nodeA);
@@ -308,7 +307,7 @@ struct nncp_ctx {
   hipStream_t st;
   char *ws;
   double *G, *Gt, *S, *scal, *ones, *hhat, *upart, *gpart, *red;
-  unsigned *ticket;
+  GramJob pending{};          // Gram step of the last update, not yet run (R == 0: none)
   double *admmU, *admmMc, *admmP, *admmNorm;
   int *admmStatus;
   void *M, *nodeA, *nodeB, *part, *kf, *ks;
@@ -390,6 +389,16 @@ struct MRef {
   int64_t mstride;
 };
 
+// Runs a pending Gram step as a kernel of its own.
+hipError_t flush_gram(nncp_ctx *c) {
+  if (c->pending.R == 0) return hipSuccess;
+  hipError_t e = tstart(c, 4);
+  if (e == hipSuccess) e = launch_gram_finish(c->pending, c->st);
+  if (e == hipSuccess) e = tstop(c, 4);
+  c->pending.R = 0;
+  return e;
+}
+
 void *node_buf(nncp_ctx *c, int side, int a) {
   const int lo = side == 0 ? 0 : c->L.S;
   return ((a - lo) % 2 == 0) ? c->nodeA : c->nodeB;
@@ -402,7 +411,12 @@ int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout, MRef *defer
   const GemmPlan &p = L.gp[side];
   const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
   const bool leaf = hi - lo == 1;
-  if (p.mfma) TIMED(2, launch_krp_operands(L.xdt, p, L.R, L.dims, L.N, F, c->kf, c->ks, c->st));
+  // the Gram step of the previous update rides along with the Khatri-Rao
+  // operand kernel; the vector-ALU GEMM path runs it on its own first
+  if (p.mfma)
+    TIMED(2, launch_krp_operands(L.xdt, p, L.R, L.dims, L.N, F, c->kf, c->ks, c->st, &c->pending));
+  else
+    HIPCHK(flush_gram(c));
   void *node = leaf ? Mout : node_buf(c, side, lo);
   const bool direct = p.nsplit == 1 && ((side == 0 && !leaf) || (side == 1 && leaf));
   TIMED(side, launch_partial_mttkrp(L.xdt, p, L.R, c->X, L.dims, L.N, L.S, F, c->kf, c->ks,
@@ -445,7 +459,7 @@ int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_ro
     const bool leaf = a == hi - 1;
     void *out = leaf ? Mout : node_buf(c, side, a);
     TIMED(3, launch_mttv_contig(L.hdt, node_buf(c, side, a - 1), Ia, Q, R, F.H[a - 1], out,
-                                leaf ? 1 : 0, c->st));
+                                leaf ? 1 : 0, c->st, &c->pending));
   }
   if (n < hi - 1) {
     const void *Hq[NNCP_MAX_MODES];
@@ -453,7 +467,7 @@ int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_ro
     int ns = 1;
     TIMED(3, launch_mttv_strided(L.hdt, node_buf(c, side, n), L.dims[n], L.dims + n + 1,
                                  hi - n - 1, Hq, R, defer ? nullptr : Mout, c->part,
-                                 L.part_elems, c->st, &ns));
+                                 L.part_elems, c->st, &ns, &c->pending));
     if (defer) *defer = MRef{c->part, ns, L.dims[n] * R};
   }
   return NNCP_OK;
@@ -465,9 +479,13 @@ int refresh_grams(nncp_ctx *c, const FactorSet &F, double *G) {
   return NNCP_OK;
 }
 
+// When defer is true the update's Gram step is left pending in c->pending
+// for the next multi-TTV or Khatri-Rao launch to carry (flush_gram runs it
+// otherwise); else it runs right after the update.
 int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double eps,
-                double *relerr_out, double *scal, double *S_next = nullptr) {
+                double *relerr_out, double *scal, double *S_next = nullptr, bool defer = false) {
   const Layout &L = c->L;
+  HIPCHK(flush_gram(c));
   UpdateArgs a;
   a.algo = algo;
   a.I = L.dims[n];
@@ -490,7 +508,7 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.hhat = c->hhat;
   a.part = c->upart;
   a.gpart = c->gpart;
-  a.ticket = c->ticket;
+  a.beta_out = c->scal + 48;
   {
     int64_t off = 0;
     for (int k = 0; k < n; ++k) off += L.dims[k] * L.R;
@@ -504,7 +522,10 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.alpha = c->scal + 8;
   a.relerr_out = relerr_out;
   a.scal = scal;
-  TIMED(4, launch_update(L.hdt, a, c->st));
+  GramJob job;
+  TIMED(4, launch_update(L.hdt, a, c->st, &job));
+  c->pending = job;
+  if (!defer) HIPCHK(flush_gram(c));
   return NNCP_OK;
 }
 
@@ -561,7 +582,6 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->hhat = (double *)(c->ws + L.off_hhat);
   c->upart = (double *)(c->ws + L.off_upart);
   c->gpart = (double *)(c->ws + L.off_gpart);
-  c->ticket = (unsigned *)(c->ws + L.off_ticket);
   c->admmU = (double *)(c->ws + L.off_admmU);
   c->admmMc = (double *)(c->ws + L.off_admmMc);
   c->admmP = (double *)(c->ws + L.off_admmP);
@@ -589,8 +609,6 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
     double onesh[256];
     for (int r = 0; r < R; ++r) onesh[r] = 1.0;
     hipError_t e = hipMemcpyAsync(c->ones, onesh, sizeof(double) * R, hipMemcpyHostToDevice, c->st);
-    // the finish kernel's ticket counter starts at zero and is left at zero
-    if (e == hipSuccess) e = hipMemsetAsync(c->ticket, 0, sizeof(unsigned), c->st);
     // ADMM duals start at zero
     if (e == hipSuccess && R <= 64)
       e = hipMemsetAsync(c->admmU, 0, sizeof(double) * L.sumI * R, c->st);
@@ -723,14 +741,21 @@ static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_his
     for (int n = 0; n < L.N; ++n) {
       MRef M;
       int rc = mttkrp_tree(c, F, n, c->M, false, &M);
-      if (rc) return rc;
+      if (rc) {
+        c->pending.R = 0;
+        return rc;
+      }
       const bool last = n == L.N - 1;
       rc = update_mode(c, algo, n, M, c->S, L.opt.eps_mu,
                        last && relerr_hist ? relerr_hist + s : nullptr, last ? c->scal : nullptr,
-                       c->S);
-      if (rc) return rc;
+                       c->S, true);
+      if (rc) {
+        c->pending.R = 0;
+        return rc;
+      }
     }
   }
+  HIPCHK(flush_gram(c));
   return NNCP_OK;
 }
 

@@ -82,10 +82,14 @@ struct FactorSet {
 // launchers (defined in the .hip files; all asynchronous on `st`)
 // ---------------------------------------------------------------------------
 
+struct GramJob;  // the Gram step of an update (below)
+
 // Khatri-Rao operand of a partial MTTKRP: Kfast [Rpad][Pf] (tensor type, hi
 // then lo) and Kslow [Ps][Rpad] (factor type).  One launch.
+// A non-empty *carry is run by an extra workgroup of the launch and emptied.
 hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t *dims, int N,
-                               const FactorSet &F, void *kfast, void *kslow, hipStream_t st);
+                               const FactorSet &F, void *kfast, void *kslow, hipStream_t st,
+                               GramJob *carry = nullptr);
 
 // Partial MTTKRP.  `out` receives [nsplit][...] partials (see the kernels) or,
 // when nsplit == 1 and direct != 0, the node itself ([r][row] layout).
@@ -101,17 +105,21 @@ hipError_t launch_finalize(int hdt, const GemmPlan &p, int R, const void *part, 
 
 // Multi-TTV, contiguous reduction over the node's first mode:
 //   out(q, r) = sum_{i<Ia} T[r][i + Ia q] * H(i, r)
-// out is a node [r][q] or, when leaf != 0, M [q][r].
+// out is a node [r][q] or, when leaf != 0, M [q][r].  A non-empty *carry is
+// run (in an extra workgroup, or as a kernel of its own first) and emptied.
 hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R,
-                              const void *H, void *out, int leaf, hipStream_t st);
+                              const void *H, void *out, int leaf, hipStream_t st,
+                              GramJob *carry = nullptr);
 
 // Multi-TTV, strided reduction keeping the node's first mode:
 //   M(i, r) = sum_q T[r][i + Ia q] * prod_{k in modes} H^(k)(digit_k(q), r)
 // When M is NULL the split partials are left in `part` ([nsplit][Ia][R]) for
-// the consumer to add; *nsplit_out receives their count.
+// the consumer to add; *nsplit_out receives their count.  A non-empty *carry
+// is run by an extra workgroup and emptied.
 hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
                                const void *const *Hq, int R, void *M, void *part,
-                               int64_t part_elems, hipStream_t st, int *nsplit_out);
+                               int64_t part_elems, hipStream_t st, int *nsplit_out,
+                               GramJob *carry = nullptr);
 int64_t mttv_strided_part_elems(int hdt, int64_t Ia, const int64_t *qdims, int nq, int R);
 
 // Gram G = H^T H (FP64) for one factor; single workgroup.
@@ -140,8 +148,8 @@ struct UpdateArgs {
   double *lambda;       // R, in/out
   double *hhat;         // I x R FP64 scratch
   double *part;         // per-workgroup partials, update_part_elems(I, R) doubles
-  double *gpart;        // R <= 64: per-slice Gram tiles, norm_gpart_elems(R) doubles
-  unsigned *ticket;     // R <= 64: zero before the first launch; left at zero
+  double *gpart;        // R <= 64: norm_gpart_elems(R) doubles of scratch (GramJob)
+  double *beta_out;     // R <= 64: receives beta for the Gram step (GramJob)
   double eps;
   // error after a sweep (mode N-1 only): alpha, out pointers (may be NULL)
   const double *alpha;
@@ -155,13 +163,129 @@ struct UpdateArgs {
 };
 constexpr int kAdmmMaxit = 5;         // passes per ADMM update (Section 4.3.4)
 constexpr double kAdmmTol = 0.01;     // stopping tolerance of the cited method
-hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st);
 // workgroups of the finish kernel (R <= 64) and the rows each one normalises
 constexpr int kNormWG = 16;
 int norm_workgroups(int64_t I, int64_t *rows_per_wg);
-// doubles of per-slice Gram tiles the finish kernel needs (R <= 64)
+// scratch of the finish kernel (R <= 64): kNormWG slices of Gram tiles, then
+// the R x R Hadamard product of the Grams other than mode and next_mode
+__host__ __device__ inline int64_t norm_pn_offset(int R) {
+  const int T = (R + 15) / 16;
+  return (int64_t)kNormWG * (T * (T + 1) / 2) * 256;
+}
 int norm_gpart_elems(int R);
 int64_t update_part_elems(int64_t I, int R);
+
+// ---------------------------------------------------------------------------
+// The Gram step of an update with R <= 64.  The update's last kernel leaves
+// the Gram of the new factor as nw slices of upper 16 x 16 tiles (one slice
+// per workgroup, tiles of the R x R grid in row-major order) together with
+// lambda, beta and the product pn of the Grams other than mode and
+// next_mode.  This step adds the slices in slice order into G^(mode) (both
+// halves), forms gamma = lambda^T (S .* G^(mode)) lambda and the relative
+// error when asked, and the next mode's S = pn .* G^(mode).  It runs as one
+// 256-thread workgroup, either a kernel of its own or an extra workgroup of
+// the next kernel on the stream ("carrier"), which must not touch G, S or the
+// error outputs.  R == 0 marks an empty job.
+// ---------------------------------------------------------------------------
+struct GramJob {
+  const double *gpart;   // nw x ntile x 256 slices
+  const double *pn;      // R x R, read when S_next is set
+  double *G;             // N x R x R Grams; G[mode] written
+  const double *S;       // S of this mode (read for gamma)
+  double *S_next;        // may be NULL; may alias S
+  const double *lambda;  // R
+  const double *beta;    // 1, written by the update (always a valid address)
+  const double *alpha;   // ||X||^2 (always a valid address)
+  double *relerr_out;    // may be NULL
+  double *scal;          // may be NULL: [0]=beta [1]=gamma [2]=raw relerr^2
+  int R, N, mode, next_mode, nw;
+};
+
+// One 256-thread workgroup.  Thread t takes the upper-tile entries u = t +
+// 256 k (consecutive threads read consecutive slice entries) and writes both
+// (x, y) and (y, x): G, S and pn are exactly symmetric (each pair is written
+// from one value), so gamma adds the diagonal once and each off-diagonal pair
+// twice.  Each thread reads S(x, y) before it writes S_next(x, y) and
+// S_next(y, x), and no other thread touches either.  All loads of a round are
+// unconditional (clamped indices) so that they are in flight together.
+__device__ inline void gram_finish(const GramJob &j) {
+  __shared__ double gred[4];
+  const int R = j.R, RR = R * R, T = (R + 15) >> 4, slice = (T * (T + 1) / 2) * 256;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool want_err = j.relerr_out || j.scal;
+  const int nw = j.nw;
+  double *Gm = j.G + (int64_t)j.mode * RR;
+  const double *pnp = j.S_next ? j.pn : j.lambda;  // any valid address when unused
+  const double *sp = want_err ? j.S : j.lambda;
+  const double alpha = j.alpha[0], beta = j.beta[0];  // read early (both always valid)
+  double gsum = 0.0;
+  // two entries per thread and round trip
+  for (int u0 = tid; u0 < slice; u0 += 512) {
+    double v[2][kNormWG], sv[2], la[2], lb[2], pn[2];
+    int xs[2], ys[2];
+    bool ok[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int u = u0 + 256 * kk < slice ? u0 + 256 * kk : slice - 1;
+      // tile (tx, tx + q) of the upper tiles in row-major order (T <= 4)
+      int tx = 0, q = u >> 8;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        if (tx == r && q >= T - r) { q -= T - r; tx = r + 1; }
+      const int xl = (u >> 4) & 15, yl = u & 15;
+      const int x = 16 * tx + xl, y = 16 * (tx + q) + yl;
+      ok[kk] = u0 + 256 * kk < slice && x < R && y < R && (q > 0 || xl <= yl);
+      xs[kk] = x < R ? x : R - 1;
+      ys[kk] = y < R ? y : R - 1;
+      const int e = xs[kk] * R + ys[kk];
+      la[kk] = j.lambda[xs[kk]];
+      lb[kk] = j.lambda[ys[kk]];
+      sv[kk] = sp[want_err ? e : 0];
+      pn[kk] = pnp[j.S_next ? e : 0];
+#pragma unroll
+      for (int w = 0; w < kNormWG; ++w) v[kk][w] = j.gpart[(int64_t)(w < nw ? w : nw - 1) * slice + u];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      if (!ok[kk]) continue;
+      double sum = v[kk][0];
+#pragma unroll
+      for (int w = 1; w < kNormWG; ++w)
+        if (w < nw) sum += v[kk][w];
+      const int x = xs[kk], y = ys[kk];
+      Gm[x * R + y] = sum;
+      Gm[y * R + x] = sum;
+      if (want_err) gsum += (x == y ? 1.0 : 2.0) * (la[kk] * sv[kk] * sum * lb[kk]);
+      if (j.S_next) {
+        const double sn = j.next_mode == j.mode ? pn[kk] : pn[kk] * sum;
+        j.S_next[x * R + y] = sn;
+        j.S_next[y * R + x] = sn;
+      }
+    }
+  }
+  if (!want_err) return;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) gsum += __shfl_xor(gsum, o);
+  if (lane == 0) gred[wave] = gsum;
+  __syncthreads();
+  if (tid == 0) {
+    const double gamma = gred[0] + gred[1] + gred[2] + gred[3];
+    const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+    if (j.scal) {
+      j.scal[0] = beta;
+      j.scal[1] = gamma;
+      j.scal[2] = e2;
+    }
+    if (j.relerr_out) j.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
+  }
+}
+
+// Launches the update.  For R <= 64 the Gram step is left out and *job
+// describes it (job->R == 0 otherwise); the caller runs it before anything
+// reads G, S_next or the error outputs.
+hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st, GramJob *job);
+// the Gram step as a kernel of its own (no-op for an empty job)
+hipError_t launch_gram_finish(const GramJob &j, hipStream_t st);
 
 // loss of [[lambda; H]] from M^(N-1): loss = 0.5 (alpha - 2 beta + gamma)
 hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const void *H,

@@ -148,7 +148,13 @@ __device__ double krp_entry(const KrpArgs &a, int lo, int hi, int64_t rho, int r
 
 template <typename XT, typename HT>
 __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict__ kfast,
-                                                      HT *__restrict__ kslow) {
+                                                      HT *__restrict__ kslow, GramJob job) {
+  // an extra column of workgroups (blockIdx.x == Rpad) when carrying the
+  // Gram step of the previous update
+  if (job.R && blockIdx.x == a.Rpad) {
+    if (blockIdx.y == 0) gram_finish(job);
+    return;
+  }
   const int r = blockIdx.x;
   const bool live = r < a.R;
   __shared__ double red[256];
@@ -724,27 +730,30 @@ static KrpArgs make_krp_args(const GemmPlan &p, int R, const int64_t *dims, cons
 }
 
 hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t *dims, int N,
-                               const FactorSet &F, void *kfast, void *kslow, hipStream_t st) {
+                               const FactorSet &F, void *kfast, void *kslow, hipStream_t st,
+                               GramJob *carry) {
   KrpArgs a = make_krp_args(p, R, dims, F, N);
+  const GramJob job = carry ? *carry : GramJob{};
+  if (carry) carry->R = 0;
   // one workgroup per column and per 256 entries of the longer part (one per
   // column for FP16, whose scaling needs the column maximum)
   const int64_t longest = p.Pf > p.Ps ? p.Pf : p.Ps;
   int64_t chunks = (longest + 255) / 256;
   if (chunks > 64) chunks = 64;
-  dim3 grid(p.Rpad, xdt == NNCP_F16 ? 1 : (unsigned)chunks), block(256);
+  dim3 grid(p.Rpad + (job.R ? 1 : 0), xdt == NNCP_F16 ? 1 : (unsigned)chunks), block(256);
   switch (xdt) {
     case NNCP_BF16:
-      hipLaunchKernelGGL((k_krp_operands<bf16_t, float>), grid, block, 0, st, a, (bf16_t *)kfast, (float *)kslow);
+      hipLaunchKernelGGL((k_krp_operands<bf16_t, float>), grid, block, 0, st, a, (bf16_t *)kfast, (float *)kslow, job);
       break;
     case NNCP_F16:
       a.scale16 = 1;
-      hipLaunchKernelGGL((k_krp_operands<f16_t, float>), grid, block, 0, st, a, (f16_t *)kfast, (float *)kslow);
+      hipLaunchKernelGGL((k_krp_operands<f16_t, float>), grid, block, 0, st, a, (f16_t *)kfast, (float *)kslow, job);
       break;
     case NNCP_F32:
-      hipLaunchKernelGGL((k_krp_operands<float, float>), grid, block, 0, st, a, (float *)kfast, (float *)kslow);
+      hipLaunchKernelGGL((k_krp_operands<float, float>), grid, block, 0, st, a, (float *)kfast, (float *)kslow, job);
       break;
     case NNCP_F64:
-      hipLaunchKernelGGL((k_krp_operands<double, double>), grid, block, 0, st, a, (double *)kfast, (double *)kslow);
+      hipLaunchKernelGGL((k_krp_operands<double, double>), grid, block, 0, st, a, (double *)kfast, (double *)kslow, job);
       break;
     default:
       return hipErrorInvalidValue;

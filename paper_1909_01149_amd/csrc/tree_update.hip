@@ -123,11 +123,17 @@ __global__ __launch_bounds__(256) void k_mttv_contig_wide(const HT *__restrict__
 template <typename HT, int CPL>
 __global__ __launch_bounds__(256) void k_mttv_contig_reg(const HT *__restrict__ T, int64_t Ia,
                                                          int64_t Q, int R, const HT *__restrict__ H,
-                                                         HT *__restrict__ out, int leaf) {
+                                                         HT *__restrict__ out, int leaf,
+                                                         GramJob job) {
   constexpr int V = 16 / (int)sizeof(HT);
   constexpr int QB = 16 / CPL;
   typedef HT vt __attribute__((ext_vector_type(V)));
   __shared__ vt hs[64 * CPL];
+  // an extra column of workgroups when carrying the Gram step
+  if (job.R && blockIdx.x == gridDim.x - 1) {
+    if (blockIdx.y == 0) gram_finish(job);
+    return;
+  }
   const int r = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t qb = ((int64_t)blockIdx.y * 4 + wave) * QB;
@@ -182,10 +188,15 @@ struct StridedArgs {
 
 template <typename HT, int V>
 __global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, StridedArgs a,
-                                                      HT *__restrict__ part) {
+                                                      HT *__restrict__ part, GramJob job) {
   typedef HT vt __attribute__((ext_vector_type(V)));
   __shared__ vt red[256];
   __shared__ HT kq[1024];
+  // an extra row of workgroups (blockIdx.y == R) when carrying the Gram step
+  if (job.R && blockIdx.y == a.R) {
+    if (blockIdx.x == 0 && blockIdx.z == 0) gram_finish(job);
+    return;
+  }
   const int il = threadIdx.x % a.IT, qs = threadIdx.x / a.IT;
   const int64_t i0 = ((int64_t)blockIdx.x * a.IT + il) * V;
   const bool live = i0 < a.Ia;
@@ -1085,30 +1096,25 @@ __device__ __forceinline__ void tile_pair(int t, int T, int &tx, int &ty) {
   ty = r + q;
 }
 
-int norm_gpart_elems(int R) {
-  const int T = (R + 15) / 16;
-  return kNormWG * (T * (T + 1) / 2) * 256;
-}
+int norm_gpart_elems(int R) { return (int)norm_pn_offset(R) + R * R; }
 
 // Finish of the update for R <= RB <= 64, spread over a few workgroups.
 // Every workgroup adds the row kernel's per-workgroup partials itself (the
 // same order everywhere, so all hold the same lambda and beta), normalises
 // its slice of rows and writes the Gram of that slice (FP64 MFMA over the
-// stored, rounded values; upper 16 x 16 tiles).  The workgroup that takes the
-// last ticket (a counter it resets for the next launch) adds the slices'
-// Grams in workgroup order and forms gamma and the next mode's S.
+// stored, rounded values; upper 16 x 16 tiles).  When the next mode's S is
+// asked for, the workgroups also write the product of the Grams other than
+// mode and next_mode (256 entries each, in turn).  Adding the slices, gamma
+// and the next mode's S are left to the Gram step (gram_finish), which a
+// later kernel runs once these are complete.
 template <typename HT, int RB>
 __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, int64_t rpw) {
-  constexpr int SL = (RB * RB + 255) / 256;       // R x R entries per thread
   constexpr int TB = RB / 16;                     // tile grid bound
   constexpr int TW = (TB * (TB + 1) / 2 + 3) / 4; // tiles per wave
   __shared__ double rowbuf[4096];
   __shared__ double colsum[256];
   __shared__ double lam_s[64];
-  __shared__ double wred[4];
-  __shared__ double beta_s;
-  __shared__ int last_s;
-  const int R = a.R, RR = R * R;
+  const int R = a.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nct = R + 1, tpc = 256 / nct;
   const int pc = tid % nct, pj = tid / nct;
@@ -1117,41 +1123,40 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
   const int64_t r1 = a.I < r0 + rpw ? a.I : r0 + rpw;
   const int CHR = 4096 / R;
   const int T = (R + 15) / 16, ntile = T * (T + 1) / 2;
-  const bool want_err = a.relerr_out || a.scal;
   // ---- loads first: the row kernel's partials (consecutive threads read
-  // consecutive entries), the first chunk of Hhat, S of this mode and the
-  // Grams the next mode's S is formed from
-  double pp[32], hv[16], sv[SL], pn[SL];
-  const double alpha = (want_err && a.alpha) ? a.alpha[0] : 0.0;
+  // consecutive entries) and the first chunk of Hhat
+  // (addresses clamped, so that every load is issued unconditionally)
+  double pp[32], hv[16];
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int b = pj + k * tpc;
-    pp[k] = (pl && b < nblocks) ? a.part[(int64_t)b * nct + pc] : 0.0;
+    pp[k] = a.part[(int64_t)(b < nblocks ? b : nblocks - 1) * nct + pc];
   }
   const int rows0 = (int)(r1 - r0 < CHR ? r1 - r0 : CHR);
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int e = tid + 256 * k;
-    hv[k] = e < rows0 * R ? a.hhat[r0 * R + e] : 0.0;
+    hv[k] = a.hhat[r0 * R + (e < rows0 * R ? e : rows0 * R - 1)];
   }
+  // ---- the product of the Grams other than mode and next_mode (independent
+  // of this update), 256 entries per workgroup in turn; its loads go out
+  // behind the ones above
+  auto gram_product = [&](int e) {
+    const int ec = e < R * R ? e : R * R - 1;
+    double g[NNCP_MAX_MODES];
 #pragma unroll
-  for (int k = 0; k < SL; ++k) {
-    const int e = tid + 256 * k;
-    sv[k] = (want_err && e < RR) ? a.S[e] : 0.0;
-    pn[k] = 1.0;
-  }
-  if (a.S_next) {
-    for (int q = 0; q < a.N; ++q) {
-      if (q == a.mode || q == a.next_mode) continue;
-      double gq[SL];
+    for (int q = 0; q < NNCP_MAX_MODES; ++q)
+      g[q] = (q < a.N && q != a.mode && q != a.next_mode) ? a.G[(int64_t)q * R * R + ec] : 1.0;
+    double p = 1.0;
 #pragma unroll
-      for (int k = 0; k < SL; ++k) {
-        const int e = tid + 256 * k;
-        gq[k] = e < RR ? a.G[(int64_t)q * RR + e] : 1.0;
-      }
-#pragma unroll
-      for (int k = 0; k < SL; ++k) pn[k] *= gq[k];
-    }
+    for (int q = 0; q < NNCP_MAX_MODES; ++q) p *= g[q];
+    if (e < R * R) a.gpart[norm_pn_offset(R) + e] = p;
+  };
+  if (a.S_next && blockIdx.x * 256 < R * R) {
+    // the first chunk straight-line, the rest (few workgroups) in a loop
+    gram_product(blockIdx.x * 256 + tid);
+    for (int e0 = (blockIdx.x + gridDim.x) * 256; e0 < R * R; e0 += gridDim.x * 256)
+      gram_product(e0 + tid);
   }
   // ---- lambda (column norms) and beta
   {
@@ -1166,11 +1171,14 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
   if (tid < nct) {
     double sum = 0.0;
     for (int j = 0; j < tpc; ++j) sum += colsum[j * nct + tid];
-    if (tid < R) lam_s[tid] = sqrt(sum);
-    else beta_s = sum;
+    if (tid < R) {
+      lam_s[tid] = sqrt(sum);
+      if (blockIdx.x == 0) a.lambda[tid] = lam_s[tid];
+    } else if (blockIdx.x == 0) {
+      a.beta_out[0] = sum;
+    }
   }
   __syncthreads();
-  if (blockIdx.x == 0 && tid < R) a.lambda[tid] = lam_s[tid];
   // ---- normalise the slice chunk by chunk; Gram tiles of the stored values
   HT *H = (HT *)a.H;
   f64x4 acc[TW];
@@ -1190,7 +1198,7 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int e = tid + 256 * k;
-        hv[k] = e < ne ? a.hhat[c0 * R + e] : 0.0;
+        hv[k] = a.hhat[c0 * R + (e < ne ? e : ne - 1)];
       }
     }
     __syncthreads();
@@ -1233,81 +1241,10 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) gp[t * 256 + (lr + 4 * v) * 16 + lc] = acc[s][v];
   }
-  // ---- ticket: the last workgroup to arrive sees every slice's Gram
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) last_s = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  const int nw = gridDim.x;
-  double *Gm = a.G + (int64_t)a.mode * RR;
-  double *Gs = rowbuf;  // the chunks are done (barrier above)
-  // entry e of tile t = e / 256 (x = (e / 16) % 16, y = e % 16), slices added
-  // in workgroup order; upper entries of diagonal tiles give both halves
-  for (int e0 = 0; e0 < ntile * 256; e0 += 512) {
-    double v[2][kNormWG];
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int e = e0 + tid + 256 * kk;
-#pragma unroll
-      for (int w = 0; w < kNormWG; ++w)
-        v[kk][w] = (e < ntile * 256 && w < nw) ? a.gpart[(int64_t)w * ntile * 256 + e] : 0.0;
-    }
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int e = e0 + tid + 256 * kk;
-      if (e >= ntile * 256) continue;
-      double sum = v[kk][0];
-#pragma unroll
-      for (int w = 1; w < kNormWG; ++w)
-        if (w < nw) sum += v[kk][w];
-      int bx, by;
-      tile_pair(e >> 8, T, bx, by);
-      const int x = (e >> 4) & 15, y = e & 15;
-      const int gx = 16 * bx + x, gy = 16 * by + y;
-      if (gx < R && gy < R && (bx != by || x <= y)) {
-        Gm[gx * R + gy] = sum;
-        Gm[gy * R + gx] = sum;
-        Gs[gx * R + gy] = sum;
-        Gs[gy * R + gx] = sum;
-      }
-    }
-  }
-  if (tid == 0) atomicExch(a.ticket, 0u);
-  __syncthreads();
-  if (want_err) {
-    double gsum = 0.0;
-#pragma unroll
-    for (int k = 0; k < SL; ++k) {
-      const int e = tid + 256 * k;
-      if (e < RR) gsum += lam_s[e / R] * sv[k] * Gs[e] * lam_s[e % R];
-    }
-    const double v = wave_sum(gsum);
-    if (lane == 0) wred[wave] = v;
-    __syncthreads();
-    if (tid == 0) {
-      const double gamma = wred[0] + wred[1] + wred[2] + wred[3];
-      const double beta = beta_s;
-      const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
-      if (a.scal) {
-        a.scal[0] = beta;
-        a.scal[1] = gamma;
-        a.scal[2] = e2;
-      }
-      if (a.relerr_out) a.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
-    }
-  }
-  // S of the next mode, written after every read of this mode's S (the two
-  // may share a buffer; this mode's S was read at the start)
-  if (a.S_next) {
-#pragma unroll
-    for (int k = 0; k < SL; ++k) {
-      const int e = tid + 256 * k;
-      if (e < RR) a.S_next[e] = a.next_mode == a.mode ? pn[k] : pn[k] * Gs[e];
-    }
-  }
 }
+
+// the Gram step as a kernel of its own
+__global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_finish(j); }
 
 // ---------------------------------------------------------------------------
 // loss of [[lambda; H]] given M^(N-1) at the current factors
@@ -1463,15 +1400,17 @@ __global__ __launch_bounds__(256) void k_pgd_trial(int64_t n, const HT *__restri
 // ---------------------------------------------------------------------------
 
 hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R, const void *H,
-                              void *out, int leaf, hipStream_t st) {
+                              void *out, int leaf, hipStream_t st, GramJob *carry) {
   const int V = hdt == NNCP_F64 ? 2 : 4;
+  GramJob job = carry ? *carry : GramJob{};
+  if (carry) carry->R = 0;
   if (Ia % V == 0 && Ia <= 8 * 64 * V) {
     const int CPL = Ia <= 64 * V ? 1 : Ia <= 128 * V ? 2 : Ia <= 256 * V ? 4 : 8;
     const int QB = 16 / CPL;
-    dim3 grid((unsigned)R, (unsigned)((Q + 4 * QB - 1) / (4 * QB))), block(256);
+    dim3 grid((unsigned)R + (job.R ? 1 : 0), (unsigned)((Q + 4 * QB - 1) / (4 * QB))), block(256);
 #define NNCP_CONTIG_REG(HTV, C)                                                            \
   hipLaunchKernelGGL((k_mttv_contig_reg<HTV, C>), grid, block, 0, st, (const HTV *)T, Ia, Q, R, \
-                     (const HTV *)H, (HTV *)out, leaf)
+                     (const HTV *)H, (HTV *)out, leaf, job)
     if (hdt == NNCP_F64) {
       switch (CPL) {
         case 1: NNCP_CONTIG_REG(double, 1); break;
@@ -1489,6 +1428,11 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
     }
 #undef NNCP_CONTIG_REG
     return hipGetLastError();
+  }
+  // the other variants do not carry the Gram step: run it first
+  if (job.R) {
+    const hipError_t e = launch_gram_finish(job, st);
+    if (e != hipSuccess) return e;
   }
   if (Ia >= 64 && Ia <= 8192 && Ia % V == 0 && (hdt != NNCP_F64 || Ia <= 4096)) {
     // about 2048 workgroups, at least 4 outputs (one per wave) each
@@ -1548,8 +1492,10 @@ int64_t mttv_strided_part_elems(int hdt, int64_t Ia, const int64_t *qdims, int n
 
 hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
                                const void *const *Hq, int R, void *M, void *part,
-                               int64_t part_elems, hipStream_t st, int *nsplit_out) {
+                               int64_t part_elems, hipStream_t st, int *nsplit_out,
+                               GramJob *carry) {
   StridedArgs a;
+  GramJob job = carry ? *carry : GramJob{};
   int64_t Q = 1;
   for (int k = 0; k < NNCP_MAX_MODES; ++k) {
     a.H[k] = k < nq ? Hq[k] : nullptr;
@@ -1561,22 +1507,23 @@ hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t
   const int V = strided_vec(hdt, Ia);
   strided_shape(Ia, V, Q, R, a.IT, a.QS, a.nsplit, gx);
   if ((int64_t)a.nsplit * Ia * R > part_elems) return hipErrorInvalidValue;
-  dim3 grid((unsigned)gx, R, a.nsplit), block(256);
+  if (carry) carry->R = 0;
+  dim3 grid((unsigned)gx, R + (job.R ? 1 : 0), a.nsplit), block(256);
   const int64_t n = Ia * R;
   dim3 g2((unsigned)((n + 255) / 256));
   if (nsplit_out) *nsplit_out = a.nsplit;
   if (hdt == NNCP_F64) {
     if (V == 2)
-      hipLaunchKernelGGL((k_mttv_strided<double, 2>), grid, block, 0, st, (const double *)T, a, (double *)part);
+      hipLaunchKernelGGL((k_mttv_strided<double, 2>), grid, block, 0, st, (const double *)T, a, (double *)part, job);
     else
-      hipLaunchKernelGGL((k_mttv_strided<double, 1>), grid, block, 0, st, (const double *)T, a, (double *)part);
+      hipLaunchKernelGGL((k_mttv_strided<double, 1>), grid, block, 0, st, (const double *)T, a, (double *)part, job);
     if (M)
       hipLaunchKernelGGL(k_sum_splits<double>, g2, dim3(256), 0, st, (const double *)part, n, a.nsplit, (double *)M);
   } else {
     if (V == 4)
-      hipLaunchKernelGGL((k_mttv_strided<float, 4>), grid, block, 0, st, (const float *)T, a, (float *)part);
+      hipLaunchKernelGGL((k_mttv_strided<float, 4>), grid, block, 0, st, (const float *)T, a, (float *)part, job);
     else
-      hipLaunchKernelGGL((k_mttv_strided<float, 1>), grid, block, 0, st, (const float *)T, a, (float *)part);
+      hipLaunchKernelGGL((k_mttv_strided<float, 1>), grid, block, 0, st, (const float *)T, a, (float *)part, job);
     if (M)
       hipLaunchKernelGGL(k_sum_splits<float>, g2, dim3(256), 0, st, (const float *)part, n, a.nsplit, (float *)M);
   }
@@ -1612,13 +1559,30 @@ hipError_t launch_sumsq(int xdt, const void *X, int64_t n, double *part, double 
 }
 
 template <typename HT>
-static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st) {
+static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *job) {
   const int rpb = update_rows_per_block(a.R);
   const int nb = (int)((a.I + rpb - 1) / rpb);
   dim3 grid(nb), block(256);
+  *job = GramJob{};
+  job->R = 0;
   if (a.R <= 64) {
     int64_t rpw;
     const int nw = norm_workgroups(a.I, &rpw);
+    job->gpart = a.gpart;
+    job->pn = a.gpart + norm_pn_offset(a.R);
+    job->G = a.G;
+    job->S = a.S;
+    job->S_next = a.S_next;
+    job->lambda = a.lambda;
+    job->beta = a.beta_out;
+    job->alpha = a.alpha;
+    job->relerr_out = a.relerr_out;
+    job->scal = a.scal;
+    job->R = a.R;
+    job->N = a.N;
+    job->mode = a.mode;
+    job->next_mode = a.next_mode;
+    job->nw = nw;
 #define NNCP_UPDATE_SMALL(RBV)                                                           \
   if (a.algo == NNCP_ADMM) {                                                            \
     hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(1024), 0, st, a);              \
@@ -1659,8 +1623,14 @@ int norm_workgroups(int64_t I, int64_t *rows_per_wg) {
   return (int)((I + rpw - 1) / rpw);
 }
 
-hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st) {
-  return hdt == NNCP_F64 ? update_dispatch<double>(a, st) : update_dispatch<float>(a, st);
+hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st, GramJob *job) {
+  return hdt == NNCP_F64 ? update_dispatch<double>(a, st, job) : update_dispatch<float>(a, st, job);
+}
+
+hipError_t launch_gram_finish(const GramJob &j, hipStream_t st) {
+  if (j.R == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_finish, dim3(1), dim3(256), 0, st, j);
+  return hipGetLastError();
 }
 
 int64_t update_part_elems(int64_t I, int R) {
