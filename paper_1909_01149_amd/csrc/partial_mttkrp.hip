@@ -452,9 +452,10 @@ __global__ __launch_bounds__(256) void k_gemm_left_mfma(
   // batch buffers rotate with the loop unrolled over them, so the loads of
   // the next NB - 1 batches are in flight while a batch is consumed and no
   // register copy waits for them.  Steps past the end of the range re-load
-  // the last valid step and are not computed.
+  // the last valid step and are not computed.  Depths as measured best:
+  // 16-bit tensors 4 (2 with a single 16-column tile), FP32 2, FP64 3.
   constexpr int SB = KL == 8 ? 1 : 8;
-  constexpr int NB = 3;
+  constexpr int NB = KL == 8 ? (NT == 1 ? 2 : 4) : (sizeof(XT) == 4 ? 2 : 3);
   LT buf[NB][SB * KL];
   auto load_batch = [&](LT *dst, int64_t t0) {
 #pragma unroll
