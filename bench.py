@@ -383,12 +383,13 @@ def summarize_mfma(csv_path, cmd):
     print("\n".join(lines))
 
 
-def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt"):
+def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt",
+                    title="512x512x512 R=32 HALS workload (FP32 and BF16 forms)"):
     """Write profiles/<out_name>: the library's kernels from a rocprofv3
     --kernel-trace --stats run (calls, average and total duration)."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
-    lines = [f"# rocprofv3 kernel statistics, 512x512x512 R=32 HALS workload (FP32 and BF16 forms)",
+    lines = [f"# rocprofv3 kernel statistics, {title}",
              f"# command: {cmd}",
              f"# summarised with: python bench.py --summarize-trace <kernel_stats.csv>",
              f"# kernel_source_sha = {source_sha()}",
@@ -408,6 +409,14 @@ def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt"):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
+        if len(sys.argv) > 3 and sys.argv[3] == "nls":
+            # the c2bpp configuration: HALS, BPP and ADMM on the BF16 512^3 tensor
+            summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "
+                            "gpurun_out/prof_nls -o nls -- python3 bench.py --configs c2bpp",
+                            "kernels_512cube_nls.txt",
+                            "512x512x512 R=32 BF16 tensor, 50 sweeps each of HALS, BPP and ADMM "
+                            "(timed and untimed passes)")
+            return
         summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "
                         "gpurun_out/prof -o bench -- python3 bench.py --steps 10 --warmup 2 "
                         "--no-cpu-baseline")

@@ -141,26 +141,29 @@ void plan_side(Layout &L, int side) {
     p.fast_lo = lo; p.fast_hi = fhi; p.slow_lo = fhi; p.slow_hi = hi;
     const size_t stage = stage_bytes(p.Rpad, W, es, p.hl);
     if (side == 1) {
-      const size_t redb = (size_t)3 * MT * p.NT * 4 * 64 * hs;
+      const size_t redb = (size_t)(kRightWaves - 1) * MT * p.NT * 4 * 64 * hs;
       p.lds_bytes = std::max(stage, redb);
       p.tiles = (p.k + 16 * MT - 1) / (16 * MT);
       const int64_t steps = p.m / KSTEP;
-      // about two workgroups per CU in total: each one stages the Khatri-Rao
+      // about one workgroup per CU in total: each one stages the Khatri-Rao
       // operand once, so fewer, longer workgroups re-stage less per byte of X
-      int64_t ns = (512 + p.tiles - 1) / p.tiles;
+      int64_t ns = (256 + p.tiles - 1) / p.tiles;
       ns = std::min<int64_t>(ns, std::max<int64_t>(1, steps / 8));
       ns = std::min<int64_t>(ns, 4096);
       p.nsplit = (int)std::max<int64_t>(ns, 1);
     } else {
       // the epilogue stages 16 result columns of each wave's 16 QV columns
       // of T (rows padded by 16 bytes) in the same LDS
-      const size_t epi = (size_t)4 * 16 * (16 * QV * hs + 16);
+      const int WV = left_waves(es, QV, p.NT, p.Ps > 1);
+      const size_t epi = (size_t)WV * 16 * (16 * QV * hs + 16);
       p.lds_bytes = std::max(stage, epi);
-      p.tiles = (p.m + 64 * QV - 1) / (64 * QV);
+      p.tiles = (p.m + 16 * WV * QV - 1) / (16 * WV * QV);
       const int64_t steps = p.k / KSTEP;
       // no split (T written straight into the node) when the columns alone
-      // give enough workgroups; otherwise split the rows
-      int64_t ns = p.tiles >= 384 ? 1 : (768 + p.tiles - 1) / p.tiles;
+      // give enough workgroups (about 1.5 waves per SIMD); otherwise split
+      // the rows to reach about three
+      const int64_t enough = 1536 / WV;
+      int64_t ns = p.tiles >= enough ? 1 : (2 * enough + p.tiles - 1) / p.tiles;
       ns = std::min<int64_t>(ns, std::max<int64_t>(1, steps / 4));
       ns = std::min<int64_t>(ns, 4096);
       p.nsplit = (int)std::max<int64_t>(ns, 1);
