@@ -177,7 +177,7 @@ struct UpdateArgs {
 constexpr int kAdmmMaxit = 5;         // passes per ADMM update (Section 4.3.4)
 constexpr double kAdmmTol = 0.01;     // stopping tolerance of the cited method
 // workgroups of the finish kernel (R <= 64) and the rows each one normalises
-constexpr int kNormWG = 16;
+constexpr int kNormWG = 8;
 int norm_workgroups(int64_t I, int64_t *rows_per_wg);
 // scratch of the finish kernel (R <= 64): kNormWG slices of Gram tiles, then
 // the R x R Hadamard product of the Grams other than mode and next_mode
@@ -232,13 +232,14 @@ __device__ inline void gram_finish(const GramJob &j) {
   const double *sp = want_err ? j.S : j.lambda;
   const double alpha = j.alpha[0], beta = j.beta[0];  // read early (both always valid)
   double gsum = 0.0;
-  // two entries per thread and round trip
-  for (int u0 = tid; u0 < slice; u0 += 512) {
-    double v[2][kNormWG], sv[2], la[2], lb[2], pn[2];
-    int xs[2], ys[2];
-    bool ok[2];
+  // FE entries per thread and round trip (one round up to R = 32)
+  constexpr int FE = 3;
+  for (int u0 = tid; u0 < slice; u0 += 256 * FE) {
+    double v[FE][kNormWG], sv[FE], la[FE], lb[FE], pn[FE];
+    int xs[FE], ys[FE];
+    bool ok[FE];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
+    for (int kk = 0; kk < FE; ++kk) {
       const int u = u0 + 256 * kk < slice ? u0 + 256 * kk : slice - 1;
       // tile (tx, tx + q) of the upper tiles in row-major order (T <= 4)
       int tx = 0, q = u >> 8;
@@ -259,7 +260,7 @@ __device__ inline void gram_finish(const GramJob &j) {
       for (int w = 0; w < kNormWG; ++w) v[kk][w] = j.gpart[(int64_t)(w < nw ? w : nw - 1) * slice + u];
     }
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
+    for (int kk = 0; kk < FE; ++kk) {
       if (!ok[kk]) continue;
       double sum = v[kk][0];
 #pragma unroll
