@@ -335,10 +335,13 @@ hipError_t tstart(nncp_ctx *c, int k) {
   if (!c->timing) return hipSuccess;
   TimerCat &t = c->timers[k];
   if (t.used + 2 > t.ev.size()) {
+    // timing-only events: no system-scope fence (cache writeback and
+    // invalidation) around the timed launch; the stream is synchronised
+    // before the times are read
     hipEvent_t a, b;
-    hipError_t e = hipEventCreate(&a);
+    hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
     if (e != hipSuccess) return e;
-    e = hipEventCreate(&b);
+    e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
     if (e != hipSuccess) return e;
     t.ev.push_back(a);
     t.ev.push_back(b);
