@@ -31,6 +31,7 @@ MU = 0
 HALS = 1
 BPP = 2
 ADMM = 3
+NES = 4
 
 
 def build(force: bool = False) -> str:
@@ -74,6 +75,10 @@ def lib():
         L.orc_bpp_row.restype = ci
         L.orc_update_admm.argtypes = [i64, ci, pd, pd, pd, pd, ci, d]
         L.orc_update_admm.restype = ci
+        L.orc_nes_params.argtypes = [ci, pd, ci, d, pd]
+        L.orc_nes_params.restype = ci
+        L.orc_update_nes.argtypes = [i64, ci, pd, pd, pd, ci, ci, d]
+        L.orc_update_nes.restype = ci
         L.orc_sweeps.argtypes = [ci, pi64, ci, pd, ppd, pd, ci, d, ci, pd, pd, ci]
         L.orc_residual.argtypes = [ci, pi64, ci, pd, ppd, pd, pd]
         L.orc_residual.restype = d
@@ -208,6 +213,25 @@ def update_admm(Hhat, U, M, S, maxit: int = 5, tol: float = 0.01):
     n = lib().orc_update_admm(H.shape[0], H.shape[1], _pd(H), _pd(Uc), _pd(M), _pd(S), int(maxit),
                               float(tol))
     return H, Uc, int(n)
+
+
+def nes_params(S, power: int = 20, kappa: float = 100.0):
+    """Step parameters of the Nesterov-type update: (L, mu, lam, alpha, beta, ok)."""
+    S = _f64(S)
+    out = np.zeros(5)
+    rc = lib().orc_nes_params(S.shape[0], _pd(S), int(power), float(kappa), _pd(out))
+    return (*[float(v) for v in out], rc == 0)
+
+
+def update_nes(Hhat, M, S, iters: int = 20, power: int = 20, kappa: float = 100.0):
+    """Nesterov-type update from the start value Hhat (also the proximal
+    centre).  Returns (Hhat, ok)."""
+    H = _f64(Hhat).copy()
+    M = _f64(M)
+    S = _f64(S)
+    rc = lib().orc_update_nes(H.shape[0], H.shape[1], _pd(H), _pd(M), _pd(S), int(iters),
+                              int(power), float(kappa))
+    return H, rc == 0
 
 
 def normalize(Hhat):

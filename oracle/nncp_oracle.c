@@ -20,6 +20,8 @@
  *     Section 4.3.3, with the pivoting rule of the method the paper cites;
  *   - ADMM, Eqs. (eqn:admmnls), (eqn:admmupd), Section 4.3.4 (at most 5
  *     passes, rho = trace(S)/R, the stopping test of the cited method);
+ *   - the Nesterov-type update, Eqs. (eqn:nesnls), (eqn:nesinnerupd),
+ *     Section 4.3.5 (20 steps, with the step parameters read below);
  *   - column normalisation with weights lambda, Appendix "Factor Matrix
  *     Normalization" and Algorithm 4 (alg:Par-NNCP-long);
  *   - relative error through the identity
@@ -42,6 +44,10 @@
  *   - the ADMM dual U of each mode starts at zero and is kept from one
  *     update of that mode to the next (it lives with the solver, like the
  *     auxiliary variables the paper's solver classes hold);
+ *   - the Nesterov-type update: the gradient's sign is that of the objective
+ *     (the printed one is flipped); lambda, alpha, beta follow the rule in
+ *     orc_nes_params; every update takes exactly 20 steps; the outer
+ *     acceleration of Eq. (eqn:nesouterupd) is not part of the sweeps;
  *   - the squared relative error is clamped at 0 before the square root.
  *
  * Layouts: the tensor is stored with mode 0 varying fastest (the local
@@ -479,6 +485,101 @@ int orc_update_admm(int64_t I, int R, double *Hhat, double *U, const double *M,
   return rc == 0 ? pass : -1;
 }
 
+/* largest eigenvalue of a symmetric matrix by power steps (defined below) */
+double orc_power_lmax(int R, const double *A, int iters);
+
+/*
+ * Step parameters of the Nesterov-type update (Section 4.3.5).  The paper
+ * ties lambda, alpha and beta to the singular values of A (here the
+ * eigenvalues of S = A^T A) and leaves the rule to the method it cites; the
+ * reading used here:
+ *   L  = largest eigenvalue of S, by `power` power steps from the all-ones
+ *        vector (orc_power_lmax),
+ *   mu = L minus the largest eigenvalue of L I - S found the same way,
+ *        at least 0 (an estimate of the smallest eigenvalue of S from above),
+ *   lam = max(0, (L - kappa mu) / (kappa - 1)), the smallest proximal weight
+ *        that brings the condition number of S + lam I down to kappa,
+ *   alpha = 1 / (L + lam),
+ *   beta = (1 - sqrt(q)) / (1 + sqrt(q)), q = (mu + lam) / (L + lam), the
+ *        constant momentum of the accelerated gradient method for a
+ *        strongly convex objective.
+ * out: [L, mu, lam, alpha, beta].  Returns 0, or -1 when L is not positive
+ * (out[3] = out[4] = 0).
+ */
+int orc_nes_params(int R, const double *S, int power, double kappa, double *out) {
+  const double L = orc_power_lmax(R, S, power);
+  double *T = (double *)malloc(sizeof(double) * (size_t)R * R);
+  for (int a = 0; a < R; ++a)
+    for (int b = 0; b < R; ++b) T[a * R + b] = (a == b ? L : 0.0) - S[a * R + b];
+  const double lt = orc_power_lmax(R, T, power);
+  free(T);
+  double mu = L - lt;
+  if (!(mu > 0.0)) mu = 0.0;
+  double lam = (L - kappa * mu) / (kappa - 1.0);
+  if (!(lam > 0.0)) lam = 0.0;
+  out[0] = L;
+  out[1] = mu;
+  out[2] = lam;
+  if (!(L > 0.0)) {
+    out[3] = out[4] = 0.0;
+    return -1;
+  }
+  const double q = sqrt((mu + lam) / (L + lam));
+  out[3] = 1.0 / (L + lam);
+  out[4] = (1.0 - q) / (1.0 + q);
+  return 0;
+}
+
+/*
+ * Nesterov-type update, Section 4.3.5 with Eqs. (eqn:nesnls) and
+ * (eqn:nesinnerupd), written for the rows x of the factor (A^T A = S,
+ * A^T B = M^T) with x* the start value of the row:
+ *   grad(y) = y S - m + lam (y - x*)
+ * (the gradient of 1/2 ||A x - b||^2 + lam/2 ||x - x*||^2; the sign printed
+ * in the paper is flipped), and
+ *   x_0 = y_0 = x*,
+ *   x_{k+1} = max(0, y_k - alpha grad(y_k)),
+ *   y_{k+1} = x_{k+1} + beta (x_{k+1} - x_k),
+ * for exactly `iters` steps (the paper's cap is 20; the stopping tests of the
+ * cited method are not used), with the parameters of orc_nes_params.
+ * Hhat holds the start value on entry and the result on exit.  Returns 0, or
+ * -1 when L is not positive (Hhat unchanged).
+ */
+int orc_update_nes(int64_t I, int R, double *Hhat, const double *M, const double *S, int iters,
+                   int power, double kappa) {
+  double prm[5];
+  if (orc_nes_params(R, S, power, kappa, prm) != 0) return -1;
+  const double lam = prm[2], alpha = prm[3], beta = prm[4];
+  double *xs = (double *)malloc(sizeof(double) * (size_t)R);
+  double *x = (double *)malloc(sizeof(double) * (size_t)R);
+  double *y = (double *)malloc(sizeof(double) * (size_t)R);
+  double *xn = (double *)malloc(sizeof(double) * (size_t)R);
+  for (int64_t i = 0; i < I; ++i) {
+    double *h = Hhat + i * R;
+    const double *m = M + i * R;
+    for (int c = 0; c < R; ++c) xs[c] = x[c] = y[c] = h[c];
+    for (int k = 0; k < iters; ++k) {
+      for (int c = 0; c < R; ++c) {
+        double g = 0.0;
+        for (int r = 0; r < R; ++r) g += y[r] * S[r * R + c];
+        g = g - m[c] + lam * (y[c] - xs[c]);
+        const double v = y[c] - alpha * g;
+        xn[c] = v > 0.0 ? v : 0.0;
+      }
+      for (int c = 0; c < R; ++c) {
+        y[c] = xn[c] + beta * (xn[c] - x[c]);
+        x[c] = xn[c];
+      }
+    }
+    for (int c = 0; c < R; ++c) h[c] = x[c];
+  }
+  free(xs);
+  free(x);
+  free(y);
+  free(xn);
+  return 0;
+}
+
 /*
  * Column normalisation (Algorithm 4, column-norm and column-scale lines):
  * lambda_r = ||Hhat[:,r]||_2 and H[:,r] = Hhat[:,r] / lambda_r, or a zero
@@ -498,9 +599,12 @@ void orc_normalize(int64_t I, int R, const double *Hhat, double *H, double *lamb
 /* alternating-update sweeps                                            */
 /* ------------------------------------------------------------------ */
 
-enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3 };
+enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3, ORC_NES = 4 };
 #define ORC_ADMM_MAXIT 5
 #define ORC_ADMM_TOL 0.01
+#define ORC_NES_ITERS 20
+#define ORC_NES_POWER 20
+#define ORC_NES_KAPPA 100.0
 
 /*
  * nsweeps outer iterations of Algorithm 1 with the local steps of
@@ -514,7 +618,7 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
                double *lambda, int algo, double eps_mu, int nsweeps,
                double *relerr, double *relerr2_raw, int nthreads) {
   if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0) return -1;
-  if (algo != ORC_MU && algo != ORC_HALS && algo != ORC_BPP && algo != ORC_ADMM) return -1;
+  if (algo < ORC_MU || algo > ORC_NES) return -1;
   const int64_t I = prod_dims(N, dims);
   double *G[ORC_MAXN];
   int64_t maxI = 0;
@@ -546,8 +650,10 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
         orc_update_hals(In, R, Hhat, M, S);
       else if (algo == ORC_BPP)
         orc_update_bpp(In, R, Hhat, M, S);
-      else
+      else if (algo == ORC_ADMM)
         orc_update_admm(In, R, Hhat, Ud[n], M, S, ORC_ADMM_MAXIT, ORC_ADMM_TOL);
+      else
+        orc_update_nes(In, R, Hhat, M, S, ORC_NES_ITERS, ORC_NES_POWER, ORC_NES_KAPPA);
       orc_normalize(In, R, Hhat, H[n], lambda);
       orc_gram(In, R, H[n], G[n]);
       if (n == N - 1) {

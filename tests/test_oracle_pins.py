@@ -395,6 +395,103 @@ def test_admm_fixed_point_and_limit_are_the_nnls_solution():
     np.testing.assert_allclose(Ho, Xs, rtol=1e-6, atol=1e-9)
 
 
+# ---------------------------------------------------------------------------
+# Nesterov-type update (Section 4.3.5)
+# ---------------------------------------------------------------------------
+
+def test_nes_params_against_eigvalsh():
+    """L from power steps is the largest eigenvalue (LAPACK, an independent
+    routine) when the leading eigenvalue is well separated; mu is an estimate
+    of the smallest from above; the proximal weight caps the condition number
+    of S + lam I at kappa."""
+    rng = np.random.default_rng(31)
+    for R in (1, 4, 8, 16):
+        A = rng.random((3 * R + 10, R))
+        S = A.T @ A
+        ev = np.linalg.eigvalsh(S)
+        L, mu, lam, alpha, beta, ok = oracle.nes_params(S, power=20, kappa=100.0)
+        assert ok
+        np.testing.assert_allclose(L, ev[-1], rtol=1e-9)
+        assert ev[0] - 1e-9 * ev[-1] <= mu <= L * (1 + 1e-12)
+        assert lam >= 0.0
+        assert (L + lam) / (mu + lam) <= 100.0 * (1 + 1e-9)
+        assert 0.0 <= beta < 1.0 and alpha > 0.0
+    # a scaled identity: L = mu = s exactly, no momentum, no proximal term
+    L, mu, lam, alpha, beta, ok = oracle.nes_params(2.5 * np.eye(6))
+    assert (L, mu, lam, beta) == (2.5, 2.5, 0.0, 0.0)
+    np.testing.assert_allclose(alpha, 1 / 2.5, rtol=1e-15)
+    # S = 0: no step is defined, the start value is kept
+    H0 = np.random.default_rng(2).random((3, 4))
+    Ho, ok = oracle.update_nes(H0, np.ones((3, 4)), np.zeros((4, 4)))
+    assert not ok
+    np.testing.assert_array_equal(Ho, H0)
+
+
+def test_nes_diagonal_s_solves_in_one_step():
+    """For S = s I the subproblem separates and its solution is max(0, m / s);
+    with alpha = 1/s and no momentum one step reaches it, and it is a fixed
+    point afterwards."""
+    rng = np.random.default_rng(32)
+    M = rng.standard_normal((7, 5))
+    S = 3.0 * np.eye(5)
+    H0 = rng.random((7, 5))
+    want = np.maximum(0.0, M / 3.0)
+    for iters in (1, 20):
+        Ho, ok = oracle.update_nes(H0, M, S, iters=iters)
+        assert ok
+        np.testing.assert_allclose(Ho, want, rtol=1e-15, atol=1e-15)
+
+
+def test_nes_limit_is_the_nnls_solution():
+    """Without the proximal term (kappa large enough that lam = 0) many steps
+    reach the NNLS solution (scipy's active-set solver per row)."""
+    rng = np.random.default_rng(33)
+    R = 6
+    A = rng.random((20, R))
+    Bm = rng.standard_normal((9, 20)) + 0.5
+    S = A.T @ A
+    M = Bm @ A
+    L, mu, lam, alpha, beta, ok = oracle.nes_params(S, kappa=1e12)
+    assert lam == 0.0
+    Xs = np.stack([nnls(A, b)[0] for b in Bm])
+    Ho, ok = oracle.update_nes(np.zeros_like(Xs) + 0.1, M, S, iters=4000, kappa=1e12)
+    assert ok
+    np.testing.assert_allclose(Ho, Xs, rtol=1e-8, atol=1e-10)
+
+
+def test_nes_limit_with_the_proximal_term():
+    """With lam > 0 the fixed point minimises ||A x - b||^2 + lam ||x - x*||^2
+    over x >= 0, i.e. the NNLS solution of the stacked system
+    [A; sqrt(lam) I] x = [b; sqrt(lam) x*] (scipy, per row)."""
+    rng = np.random.default_rng(34)
+    R = 6
+    A = rng.random((20, R))
+    Bm = rng.standard_normal((9, 20)) + 0.5
+    S = A.T @ A
+    M = Bm @ A
+    X0 = rng.random((9, R))
+    L, mu, lam, alpha, beta, ok = oracle.nes_params(S, kappa=3.0)
+    assert lam > 0.0
+    want = np.stack([nnls(np.vstack([A, np.sqrt(lam) * np.eye(R)]),
+                          np.concatenate([b, np.sqrt(lam) * x0]))[0] for b, x0 in zip(Bm, X0)])
+    Ho, ok = oracle.update_nes(X0, M, S, iters=4000, kappa=3.0)
+    assert ok
+    np.testing.assert_allclose(Ho, want, rtol=1e-8, atol=1e-10)
+
+
+def test_nes_lowers_the_proximal_objective():
+    """Twenty steps from x* lower f_p below its value at x* (where the
+    proximal term is 0), for a general subproblem."""
+    dims = [6, 5, 4]
+    X, H, A, M, S = _subproblem(dims, 3, 1, 35)
+    Hh = H[1] * 1.7
+    Ho, ok = oracle.update_nes(Hh, M, S)
+    assert ok and np.all(Ho >= 0)
+    L, mu, lam, alpha, beta, _ = oracle.nes_params(S)
+    fp = subproblem_objective(Ho, M, S) + 0.5 * lam * np.sum((Ho - Hh) ** 2)
+    assert fp < subproblem_objective(Hh, M, S)
+
+
 def test_mu_invariants():
     dims = [6, 5, 4]
     X, H, A, M, S = _subproblem(dims, 3, 2, 10)
@@ -414,7 +511,7 @@ def test_mu_invariants():
 # sweeps: identity, monotonicity, exact low rank, KKT
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP, oracle.ADMM])
+@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP, oracle.ADMM, oracle.NES])
 @pytest.mark.parametrize("dims", [[6, 5, 4], [4, 3, 5, 2]])
 def test_sweep_relerr_identity_matches_direct_residual(algo, dims):
     X, H0 = gen.small_lowrank(dims, 3, 3, 21, noise=0.05)
