@@ -215,7 +215,9 @@ def run_configs(names):
             w = gen.workload2(keep_fp32=False)
             H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
             res = dict(config="c2bpp", workload=w["name"], sweeps=50)
-            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp"), (nn.NNCP_ADMM, "admm")):
+            algos = ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp"), (nn.NNCP_ADMM, "admm"),
+                     (nn.NNCP_NES, "nes"))
+            for algo, an in algos:
                 ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
                 mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, algo, 50)
                 res[an] = dict(ms_per_sweep=mps, sweeps_per_s=1e3 / mps, final_relerr=rel[-1],
@@ -224,14 +226,14 @@ def run_configs(names):
             # error trajectories from the start factors (the timed replays
             # above began after one warm-up sweep)
             traj = {}
-            for algo, an in ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp"), (nn.NNCP_ADMM, "admm")):
+            for algo, an in algos:
                 ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
                 traj[an] = ctx.sweep(algo, 50).cpu().tolist()
                 ctx.close()
             target = traj["hals"][-1]
             res["hals_relerr_after_50"] = target
             res["hals_ms_for_50_sweeps"] = 50 * res["hals"]["ms_per_sweep"]
-            for an in ("bpp", "admm"):
+            for an in ("bpp", "admm", "nes"):
                 rl = traj[an]
                 res[f"{an}_relerr_after_50"] = rl[-1]
                 k = next((i + 1 for i, r in enumerate(rl) if r <= target), None)

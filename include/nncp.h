@@ -76,7 +76,7 @@ enum nncp_status {
 
 enum nncp_dtype { NNCP_F64 = 0, NNCP_F32 = 1, NNCP_BF16 = 2, NNCP_F16 = 3 };
 
-enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1, NNCP_BPP = 2, NNCP_ADMM = 3 };
+enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1, NNCP_BPP = 2, NNCP_ADMM = 3, NNCP_NES = 4 };
 
 /* Options (pass NULL for the defaults, shown in brackets). */
 typedef struct nncp_options {
@@ -187,11 +187,31 @@ int nncp_update_bpp(nncp_ctx *ctx, int mode, const void *M, const double *S);
  * starting from Hhat = H^(n) diag(lambda), at most 5 passes, stopped after a
  * pass once ||Hhat - Ht||^2 / ||Hhat||^2 < 0.01 and
  * ||Hhat - Hhat_prev||^2 / ||U||^2 < 0.01 over the whole factor (the test of
- * the method the paper cites).  (S + rho I)^-1 is formed once per update from
- * its Cholesky factor.  Then normalisation and G^(n) as above.  R <= 64
- * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_ADMM as its algo.
+ * the method the paper cites).  (S + rho I)^-1 is formed once per update by
+ * Gauss-Jordan elimination (S + rho I is symmetric positive definite).  Then
+ * normalisation and G^(n) as above.  R <= 64 (NNCP_E_UNSUPPORTED otherwise);
+ * nncp_sweep accepts NNCP_ADMM as its algo.
  */
 int nncp_update_admm(nncp_ctx *ctx, int mode, const void *M, const double *S);
+
+/*
+ * Nesterov-type update of mode n (Section 4.3.5, Eqs. eqn:nesnls and
+ * eqn:nesinnerupd): every row x of Hhat takes 20 accelerated projected
+ * gradient steps on the proximal subproblem
+ *   min_{x >= 0} 0.5 x^T S x - m^T x + lam/2 ||x - x*||^2,
+ * x* = the row of H^(n) diag(lambda) on entry (also the start value):
+ *   x_{k+1} = max(0, y_k - alpha (y_k S - m + lam (y_k - x*))),
+ *   y_{k+1} = x_{k+1} + beta (x_{k+1} - x_k),  y_0 = x_0 = x*.
+ * The paper leaves lam, alpha and beta to the method it cites; here
+ * L = the largest eigenvalue of S and L - mu the largest of L I - S, each by
+ * 20 power steps from the all-ones vector; lam = max(0, (L - 100 mu) / 99)
+ * (condition number of S + lam I at most 100); alpha = 1 / (L + lam);
+ * beta = (1 - sqrt(q)) / (1 + sqrt(q)), q = (mu + lam) / (L + lam).  With
+ * L <= 0 the rows keep their values.  Then normalisation and G^(n) as above.
+ * The outer extrapolation of Eq. eqn:nesouterupd is not applied.  R <= 64
+ * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_NES as its algo.
+ */
+int nncp_update_nes(nncp_ctx *ctx, int mode, const void *M, const double *S);
 
 /*
  * Loss of the current model through the identity of the appendix:

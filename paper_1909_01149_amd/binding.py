@@ -25,7 +25,7 @@ NNCP_E_STATE = -5
 NNCP_E_UNSUPPORTED = -6
 
 NNCP_F64, NNCP_F32, NNCP_BF16, NNCP_F16 = 0, 1, 2, 3
-NNCP_MU, NNCP_HALS, NNCP_BPP, NNCP_ADMM = 0, 1, 2, 3
+NNCP_MU, NNCP_HALS, NNCP_BPP, NNCP_ADMM, NNCP_NES = 0, 1, 2, 3, 4
 NNCP_MAX_MODES = 16
 
 EXPORTS = [
@@ -33,7 +33,7 @@ EXPORTS = [
     "nncp_hadamard", "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep",
     "nncp_grad", "nncp_pgd", "nncp_destroy", "nncp_last_error", "nncp_split",
     "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read", "nncp_sweep_capture",
-    "nncp_update_bpp", "nncp_update_admm",
+    "nncp_update_bpp", "nncp_update_admm", "nncp_update_nes",
 ]
 NNCP_TIMER_CATEGORIES = 5
 
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.nncp_update_hals.argtypes = [vp, ci, vp, dp]
     L.nncp_update_bpp.argtypes = [vp, ci, vp, dp]
     L.nncp_update_admm.argtypes = [vp, ci, vp, dp]
+    L.nncp_update_nes.argtypes = [vp, ci, vp, dp]
     L.nncp_cp_loss.argtypes = [vp, dp, dp]
     L.nncp_sweep.argtypes = [vp, ci, ci, dp]
     L.nncp_sweep_capture.argtypes = [vp, ci, ci, dp]
@@ -94,7 +95,8 @@ def lib() -> ctypes.CDLL:
                  "nncp_init", "nncp_set_factors", "nncp_mttkrp", "nncp_gram", "nncp_hadamard",
                  "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep", "nncp_grad",
                  "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path",
-                 "nncp_sweep_capture", "nncp_update_bpp", "nncp_update_admm"):
+                 "nncp_sweep_capture", "nncp_update_bpp", "nncp_update_admm",
+                 "nncp_update_nes"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -181,6 +183,10 @@ def nncp_update_bpp(ctx, mode, M, S):
 
 def nncp_update_admm(ctx, mode, M, S):
     return _check(lib().nncp_update_admm(ctx, int(mode), _ptr(M), _ptr(S)))
+
+
+def nncp_update_nes(ctx, mode, M, S):
+    return _check(lib().nncp_update_nes(ctx, int(mode), _ptr(M), _ptr(S)))
 
 
 def nncp_cp_loss(ctx, loss=None, relerr=None):
@@ -301,6 +307,8 @@ class Context:
             nncp_update_bpp(self.ctx, mode, M, S)
         elif algo == NNCP_ADMM:
             nncp_update_admm(self.ctx, mode, M, S)
+        elif algo == NNCP_NES:
+            nncp_update_nes(self.ctx, mode, M, S)
         else:
             nncp_update_hals(self.ctx, mode, M, S)
 

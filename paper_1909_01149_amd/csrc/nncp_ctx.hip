@@ -524,6 +524,7 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.admmP = c->admmP;
   a.admmNorm = c->admmNorm;
   a.admmStatus = c->admmStatus;
+  a.nesParam = c->scal + 56;
   a.eps = eps;
   a.alpha = c->scal + 8;
   a.relerr_out = relerr_out;
@@ -726,6 +727,13 @@ int nncp_update_admm(nncp_ctx *c, int mode, const void *M, const double *S) {
   return update_api(c, NNCP_ADMM, mode, M, S, 0.0);
 }
 
+int nncp_update_nes(nncp_ctx *c, int mode, const void *M, const double *S) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "NES needs R <= 64 (R = %d)", c->L.R);
+  return update_api(c, NNCP_NES, mode, M, S, 0.0);
+}
+
 int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -806,9 +814,9 @@ static int build_graph(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) 
 int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo < NNCP_MU || algo > NNCP_ADMM) return fail(NNCP_E_INVAL, "algo %d", algo);
-  if ((algo == NNCP_BPP || algo == NNCP_ADMM) && c->L.R > 64)
-    return fail(NNCP_E_UNSUPPORTED, "BPP and ADMM need R <= 64 (R = %d)", c->L.R);
+  if (algo < NNCP_MU || algo > NNCP_NES) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo >= NNCP_BPP && c->L.R > 64)
+    return fail(NNCP_E_UNSUPPORTED, "BPP, ADMM and NES need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
   if (nsweeps == 0) return NNCP_OK;
   // Eager launches while timing (each launch is bracketed by events) or when
@@ -827,9 +835,9 @@ int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
 int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo < NNCP_MU || algo > NNCP_ADMM) return fail(NNCP_E_INVAL, "algo %d", algo);
-  if ((algo == NNCP_BPP || algo == NNCP_ADMM) && c->L.R > 64)
-    return fail(NNCP_E_UNSUPPORTED, "BPP and ADMM need R <= 64 (R = %d)", c->L.R);
+  if (algo < NNCP_MU || algo > NNCP_NES) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo >= NNCP_BPP && c->L.R > 64)
+    return fail(NNCP_E_UNSUPPORTED, "BPP, ADMM and NES need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 1) return fail(NNCP_E_INVAL, "nsweeps %d < 1", nsweeps);
   if (!c->L.opt.graphs) return fail(NNCP_E_INVAL, "graphs are switched off for this context");
   return build_graph(c, algo, nsweeps, relerr_hist);

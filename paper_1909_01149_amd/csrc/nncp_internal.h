@@ -173,9 +173,15 @@ struct UpdateArgs {
   // after it (R x R + 2), per-pass per-workgroup norms and per-pass status
   double *admmU, *admmMc, *admmP, *admmNorm;
   int *admmStatus;
+  // Nesterov-type update (R <= 64): [L, mu, lam, alpha, beta, ok] written by
+  // its parameter kernel; always a valid address of 6 doubles
+  double *nesParam;
 };
 constexpr int kAdmmMaxit = 5;         // passes per ADMM update (Section 4.3.4)
 constexpr double kAdmmTol = 0.01;     // stopping tolerance of the cited method
+constexpr int kNesIters = 20;         // steps per Nesterov-type update (Section 4.3.5)
+constexpr int kNesPower = 20;         // power steps for each extreme eigenvalue of S
+constexpr double kNesKappa = 100.0;   // condition number the proximal weight allows
 // workgroups of the finish kernel (R <= 64) and the rows each one normalises
 constexpr int kNormWG = 8;
 int norm_workgroups(int64_t I, int64_t *rows_per_wg);

@@ -601,6 +601,82 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
 }
 
 // ---------------------------------------------------------------------------
+// Step parameters of the Nesterov-type update (Section 4.3.5), one wave, lane
+// i holding row i of S: L = the largest eigenvalue of S and L - mu the
+// largest of L I - S, each by kNesPower power steps from the all-ones vector
+// (sums in index order, every lane forming the same scalars), then
+// lam = max(0, (L - kappa mu) / (kappa - 1)), alpha = 1 / (L + lam) and the
+// constant momentum beta = (1 - sqrt(q)) / (1 + sqrt(q)), q = (mu + lam) /
+// (L + lam).  Writes [L, mu, lam, alpha, beta, ok]; ok = 0 when L <= 0.
+// ---------------------------------------------------------------------------
+template <int RB>
+__device__ double nes_power(const double (&sr)[RB], int R, int lane, double shift, double sgn) {
+  const bool own = lane < R;
+  // row `lane` of shift I + sgn S
+  auto row = [&](int j) { return (j == lane ? shift : 0.0) + sgn * sr[j]; };
+  double v = own ? 1.0 / sqrt((double)R) : 0.0;
+  for (int t = 0; t < kNesPower; ++t) {
+    double w = 0.0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < R) w += row(j) * bcast(v, j);
+    double nrm = 0.0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < R) {
+        const double wj = bcast(w, j);
+        nrm += wj * wj;
+      }
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0)) break;
+    v = own ? w / nrm : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+    if (j < R) s += row(j) * bcast(v, j);
+  double num = 0.0;
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+    if (j < R) num += bcast(v, j) * bcast(s, j);
+  return num;
+}
+
+template <int RB>
+__global__ __launch_bounds__(64) void k_nes_prep(UpdateArgs a) {
+  const int R = a.R, lane = threadIdx.x;
+  const bool own = lane < R;
+  double sr[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) sr[j] = (own && j < R) ? a.S[lane * R + j] : 0.0;
+  if (!own) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j) sr[j] = 0.0;
+  }
+  const double L = nes_power<RB>(sr, R, lane, 0.0, 1.0);
+  const double lt = nes_power<RB>(sr, R, lane, L, -1.0);
+  double mu = L - lt;
+  if (!(mu > 0.0)) mu = 0.0;
+  double lam = (L - kNesKappa * mu) / (kNesKappa - 1.0);
+  if (!(lam > 0.0)) lam = 0.0;
+  double alpha = 0.0, beta = 0.0, ok = 0.0;
+  if (L > 0.0) {
+    const double q = sqrt((mu + lam) / (L + lam));
+    alpha = 1.0 / (L + lam);
+    beta = (1.0 - q) / (1.0 + q);
+    ok = 1.0;
+  }
+  if (lane < 6) {
+    const double vals[6] = {L, mu, lam, alpha, beta, ok};
+    double v = vals[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+      if (lane == k) v = vals[k];
+    a.nesParam[lane] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row update for R <= RB <= 64: one row per wave, lane c owns column c and
 // keeps column c of S in registers.  HALS (Alg 2) visits the columns in
 // order; at step r every lane forms its candidate, the value of lane r is
@@ -634,6 +710,8 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   const double d_raw = a.S[c * R + c];
   const double lam_raw = a.lambda[c];
   const HT h_raw = H[ir * R + c];
+  const double nes_lam = a.nesParam[2], nes_alpha = a.nesParam[3], nes_beta = a.nesParam[4];
+  const bool nes_ok = a.nesParam[5] > 0.0;
   HT macc = mv[0];
 #pragma unroll
   for (int k = 1; k < 32; ++k)
@@ -647,6 +725,26 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   const double d = own ? d_raw : 0.0;
   double h = ok ? (double)h_raw * lam_raw : 0.0;
   const double m = ok ? (double)macc : 0.0;
+  if (a.algo == NNCP_NES) {
+    // Nesterov-type steps (Section 4.3.5) from x* = Hhat, the gradient of
+    // the proximal objective y S - m + lam (y - x*) with y S in order
+    if (nes_ok) {
+      const double xs = h;
+      double x = h, y = h;
+      for (int k = 0; k < kNesIters; ++k) {
+        double gy = 0.0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+          if (j < R) gy += bcast(y, j) * sc[j];
+        gy = gy - m + nes_lam * (y - xs);
+        const double v = y - nes_alpha * gy;
+        const double xn = v > 0.0 ? v : 0.0;
+        y = xn + nes_beta * (xn - x);
+        x = xn;
+      }
+      h = x;
+    }
+  } else {
   // g = (Hhat S)(i, c), j in order
   double g = 0.0;
 #pragma unroll
@@ -669,6 +767,7 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
         g -= delta * sc[r];
       }
     }
+  }
   }
   double sq = 0.0, beta = 0.0;
   if (live && own) {
@@ -1584,7 +1683,11 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     job->next_mode = a.next_mode;
     job->nw = nw;
 #define NNCP_UPDATE_SMALL(RBV)                                                           \
-  if (a.algo == NNCP_ADMM) {                                                            \
+  if (a.algo == NNCP_NES) {                                                             \
+    hipLaunchKernelGGL((k_nes_prep<RBV>), dim3(1), dim3(64), 0, st, a);                 \
+    hipLaunchKernelGGL((k_update_rows_small<HT, RBV>), grid, block, 0, st, a);          \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+  } else if (a.algo == NNCP_ADMM) {                                                     \
     hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(1024), 0, st, a);              \
     for (int p = 0; p < kAdmmMaxit; ++p)                                                \
       hipLaunchKernelGGL((k_admm_pass<HT, RBV>), grid, block, 0, st, a, p, nb);         \
@@ -1607,7 +1710,7 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     }
 #undef NNCP_UPDATE_SMALL
   } else {
-    if (a.algo == NNCP_BPP || a.algo == NNCP_ADMM) return hipErrorInvalidValue;
+    if (a.algo == NNCP_BPP || a.algo == NNCP_ADMM || a.algo == NNCP_NES) return hipErrorInvalidValue;
     if (a.R <= 128) hipLaunchKernelGGL((k_update_rows<HT, 2>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_update_rows<HT, 4>), grid, block, 0, st, a);
     hipLaunchKernelGGL((k_update_finish<HT>), dim3(1), dim3(1024), 0, st, a, nb);

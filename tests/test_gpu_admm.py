@@ -2,8 +2,9 @@
 eqn:admmupd: rho = trace(S)/R, at most 5 passes, the stopping test of the
 cited method, the dual kept per mode) against the CPU oracle, through the C
 ABI.  Tolerances (normwise relative): FP64 1e-10 (the GPU applies the
-inverse of S + rho I formed from its Cholesky factor, the oracle solves with
-the factor; the condition number is at most R + 1); FP32 factors 1e-6."""
+inverse of S + rho I formed by Gauss-Jordan elimination, the oracle solves
+with its Cholesky factor; the condition number is at most R + 1); FP32
+factors 1e-6."""
 import numpy as np
 import pytest
 
