@@ -32,6 +32,7 @@ HALS = 1
 BPP = 2
 ADMM = 3
 NES = 4
+NES_OUTER = 5
 
 
 def build(force: bool = False) -> str:

@@ -46,8 +46,11 @@
  *     auxiliary variables the paper's solver classes hold);
  *   - the Nesterov-type update: the gradient's sign is that of the objective
  *     (the printed one is flipped); lambda, alpha, beta follow the rule in
- *     orc_nes_params; every update takes exactly 20 steps; the outer
- *     acceleration of Eq. (eqn:nesouterupd) is not part of the sweeps;
+ *     orc_nes_params; every update takes exactly 20 steps;
+ *   - the outer extrapolation of Eq. (eqn:nesouterupd) (sweeps with
+ *     ORC_NES_OUTER) acts on H^(n) for n < N-1 and H^(N-1) diag(lambda),
+ *     clips the candidate at 0 and normalises it, uses s_i = i^(1/N) with
+ *     i the sweep number from 1, and compares squared relative errors;
  *   - the squared relative error is clamped at 0 before the square root.
  *
  * Layouts: the tensor is stored with mode 0 varying fastest (the local
@@ -599,7 +602,7 @@ void orc_normalize(int64_t I, int R, const double *Hhat, double *H, double *lamb
 /* alternating-update sweeps                                            */
 /* ------------------------------------------------------------------ */
 
-enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3, ORC_NES = 4 };
+enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3, ORC_NES = 4, ORC_NES_OUTER = 5 };
 #define ORC_ADMM_MAXIT 5
 #define ORC_ADMM_TOL 0.01
 #define ORC_NES_ITERS 20
@@ -610,6 +613,8 @@ enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3, ORC_NES = 4 };
  * nsweeps outer iterations of Algorithm 1 with the local steps of
  * Algorithm 4 (normalisation and relative error).  H[n] (I_n x R) and
  * lambda (R) are the start iterate on entry and the result on exit.
+ * algo: ORC_MU, ORC_HALS, ORC_BPP, ORC_ADMM, ORC_NES, or ORC_NES_OUTER (the
+ * Nesterov-type updates plus the outer extrapolation after every sweep).
  * relerr[s] receives the relative error after sweep s from the identity;
  * relerr2_raw[s] (may be NULL) the unclamped squared relative error.
  * Returns 0, or a negative value on bad arguments.
@@ -618,7 +623,7 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
                double *lambda, int algo, double eps_mu, int nsweeps,
                double *relerr, double *relerr2_raw, int nthreads) {
   if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0) return -1;
-  if (algo < ORC_MU || algo > ORC_NES) return -1;
+  if (algo < ORC_MU || algo > ORC_NES_OUTER) return -1;
   const int64_t I = prod_dims(N, dims);
   double *G[ORC_MAXN];
   int64_t maxI = 0;
@@ -635,9 +640,23 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
     Ud[k] = algo == ORC_ADMM ? (double *)calloc((size_t)(dims[k] * R), sizeof(double)) : NULL;
   double *S = (double *)malloc(sizeof(double) * (size_t)R * R);
   const double alpha = orc_sumsq(I, X);
+  /* outer extrapolation: the iterate before the sweep and the candidate */
+  const int outer = algo == ORC_NES_OUTER;
+  double *Hp[ORC_MAXN], *Hc[ORC_MAXN], *Gc[ORC_MAXN];
+  double *lamp = (double *)malloc(sizeof(double) * (size_t)R);
+  double *lamc = (double *)malloc(sizeof(double) * (size_t)R);
+  for (int k = 0; k < N; ++k) {
+    Hp[k] = outer ? (double *)malloc(sizeof(double) * (size_t)(dims[k] * R)) : NULL;
+    Hc[k] = outer ? (double *)malloc(sizeof(double) * (size_t)(dims[k] * R)) : NULL;
+    Gc[k] = outer ? (double *)malloc(sizeof(double) * (size_t)R * R) : NULL;
+  }
 
   for (int s = 0; s < nsweeps; ++s) {
     double beta = 0.0, gamma = 0.0;
+    if (outer) {
+      for (int k = 0; k < N; ++k) memcpy(Hp[k], H[k], sizeof(double) * (size_t)(dims[k] * R));
+      memcpy(lamp, lambda, sizeof(double) * (size_t)R);
+    }
     for (int n = 0; n < N; ++n) {
       const int64_t In = dims[n];
       orc_mttkrp(N, dims, R, X, (const double *const *)H, n, M, nthreads);
@@ -664,10 +683,62 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
             gamma += lambda[a] * S[a * R + b] * G[n][a * R + b] * lambda[b];
       }
     }
-    const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+    double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+    if (outer) {
+      /* Eq. (eqn:nesouterupd) on F^(n) = H^(n) (n < N-1) and
+       * F^(N-1) = H^(N-1) diag(lambda): Fc = max(0, F + s_i (F - F_prev)),
+       * s_i = i^(1/N) for sweep i = s + 1; each Fc^(n) is normalised, the
+       * column norms multiply into lambda_c; the candidate replaces the
+       * iterate when its squared relative error is lower. */
+      const double si = pow((double)(s + 1), 1.0 / N);
+      for (int r = 0; r < R; ++r) lamc[r] = 1.0;
+      for (int k = 0; k < N; ++k) {
+        const int last = k == N - 1;
+        for (int64_t i = 0; i < dims[k]; ++i)
+          for (int r = 0; r < R; ++r) {
+            const double f = H[k][i * R + r] * (last ? lambda[r] : 1.0);
+            const double fp = Hp[k][i * R + r] * (last ? lamp[r] : 1.0);
+            const double v = f + si * (f - fp);
+            Hc[k][i * R + r] = v > 0.0 ? v : 0.0;
+          }
+        double *nrm = (double *)malloc(sizeof(double) * (size_t)R);
+        orc_normalize(dims[k], R, Hc[k], Hc[k], nrm);
+        for (int r = 0; r < R; ++r) lamc[r] *= nrm[r];
+        free(nrm);
+        orc_gram(dims[k], R, Hc[k], Gc[k]);
+      }
+      const int n = N - 1;
+      const int64_t In = dims[n];
+      orc_mttkrp(N, dims, R, X, (const double *const *)Hc, n, M, nthreads);
+      double bc = 0.0, gc = 0.0;
+      for (int64_t i = 0; i < In; ++i)
+        for (int r = 0; r < R; ++r) bc += M[i * R + r] * Hc[n][i * R + r] * lamc[r];
+      for (int a = 0; a < R; ++a)
+        for (int b = 0; b < R; ++b) {
+          double p = 1.0;
+          for (int k = 0; k < N; ++k) p *= Gc[k][a * R + b];
+          gc += lamc[a] * p * lamc[b];
+        }
+      const double e2c = (alpha - 2.0 * bc + gc) / alpha;
+      if (e2c < e2) {
+        for (int k = 0; k < N; ++k) {
+          memcpy(H[k], Hc[k], sizeof(double) * (size_t)(dims[k] * R));
+          memcpy(G[k], Gc[k], sizeof(double) * (size_t)R * R);
+        }
+        memcpy(lambda, lamc, sizeof(double) * (size_t)R);
+        e2 = e2c;
+      }
+    }
     if (relerr2_raw) relerr2_raw[s] = e2;
     relerr[s] = sqrt(e2 > 0.0 ? e2 : 0.0);
   }
+  for (int k = 0; k < N; ++k) {
+    free(Hp[k]);
+    free(Hc[k]);
+    free(Gc[k]);
+  }
+  free(lamp);
+  free(lamc);
   for (int k = 0; k < N; ++k) {
     free(G[k]);
     free(Ud[k]);

@@ -492,6 +492,26 @@ def test_nes_lowers_the_proximal_objective():
     assert fp < subproblem_objective(Hh, M, S)
 
 
+def test_nes_outer_extrapolation_never_raises_the_error():
+    """The first sweep of NES with the outer step starts like plain NES; the
+    candidate is taken only when its error is lower, so the error after the
+    sweep is at most the plain one, and equal when the candidate is refused.
+    Over several sweeps the candidate is accepted at least once here, and
+    every reported error is that of the returned factors (the identity test
+    above covers the latter for NES_OUTER as well)."""
+    dims = [12, 10, 9]
+    X, H0 = gen.small_lowrank(dims, 4, 4, 36, noise=0.02)
+    lam0 = np.ones(4)
+    _, _, rel_plain, _ = oracle.sweeps(X, H0, lam0, oracle.NES, 1)
+    _, _, rel_outer, _ = oracle.sweeps(X, H0, lam0, oracle.NES_OUTER, 1)
+    assert rel_outer[0] <= rel_plain[0]
+    _, _, rp, _ = oracle.sweeps(X, H0, lam0, oracle.NES, 12)
+    Ho, lo, ro, _ = oracle.sweeps(X, H0, lam0, oracle.NES_OUTER, 12)
+    assert not np.array_equal(ro, rp)                    # some candidate was taken
+    direct = np.linalg.norm(X - reconstruct(Ho, lo)) / np.linalg.norm(X)
+    np.testing.assert_allclose(ro[-1], direct, rtol=1e-8)
+
+
 def test_mu_invariants():
     dims = [6, 5, 4]
     X, H, A, M, S = _subproblem(dims, 3, 2, 10)
@@ -511,7 +531,8 @@ def test_mu_invariants():
 # sweeps: identity, monotonicity, exact low rank, KKT
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP, oracle.ADMM, oracle.NES])
+@pytest.mark.parametrize("algo", [oracle.MU, oracle.HALS, oracle.BPP, oracle.ADMM, oracle.NES,
+                                  oracle.NES_OUTER])
 @pytest.mark.parametrize("dims", [[6, 5, 4], [4, 3, 5, 2]])
 def test_sweep_relerr_identity_matches_direct_residual(algo, dims):
     X, H0 = gen.small_lowrank(dims, 3, 3, 21, noise=0.05)
