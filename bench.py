@@ -216,7 +216,7 @@ def run_configs(names):
             H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
             res = dict(config="c2bpp", workload=w["name"], sweeps=50)
             algos = ((nn.NNCP_HALS, "hals"), (nn.NNCP_BPP, "bpp"), (nn.NNCP_ADMM, "admm"),
-                     (nn.NNCP_NES, "nes"))
+                     (nn.NNCP_NES, "nes"), (nn.NNCP_NES_OUTER, "nes_outer"))
             for algo, an in algos:
                 ctx = nn.Context(w["Xbf16"], [h.clone() for h in H0])
                 mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, algo, 50)
@@ -233,7 +233,7 @@ def run_configs(names):
             target = traj["hals"][-1]
             res["hals_relerr_after_50"] = target
             res["hals_ms_for_50_sweeps"] = 50 * res["hals"]["ms_per_sweep"]
-            for an in ("bpp", "admm", "nes"):
+            for an in ("bpp", "admm", "nes", "nes_outer"):
                 rl = traj[an]
                 res[f"{an}_relerr_after_50"] = rl[-1]
                 k = next((i + 1 for i, r in enumerate(rl) if r <= target), None)
@@ -412,11 +412,12 @@ def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt",
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
         if len(sys.argv) > 3 and sys.argv[3] == "nls":
-            # the c2bpp configuration: HALS, BPP and ADMM on the BF16 512^3 tensor
+            # the c2bpp configuration: HALS, BPP, ADMM and NES on the BF16 512^3 tensor
             summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "
                             "gpurun_out/prof_nls -o nls -- python3 bench.py --configs c2bpp",
                             "kernels_512cube_nls.txt",
-                            "512x512x512 R=32 BF16 tensor, 50 sweeps each of HALS, BPP and ADMM "
+                            "512x512x512 R=32 BF16 tensor, 50 sweeps each of HALS, BPP, ADMM, NES "
+                            "and NES with the outer step "
                             "(timed and untimed passes)")
             return
         summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "

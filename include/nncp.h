@@ -76,7 +76,16 @@ enum nncp_status {
 
 enum nncp_dtype { NNCP_F64 = 0, NNCP_F32 = 1, NNCP_BF16 = 2, NNCP_F16 = 3 };
 
-enum nncp_algo { NNCP_MU = 0, NNCP_HALS = 1, NNCP_BPP = 2, NNCP_ADMM = 3, NNCP_NES = 4 };
+/* NNCP_NES_OUTER (nncp_sweep only): the Nesterov-type updates plus the outer
+ * extrapolation of Section 4.3.5 (Eq. eqn:nesouterupd) after every sweep. */
+enum nncp_algo {
+  NNCP_MU = 0,
+  NNCP_HALS = 1,
+  NNCP_BPP = 2,
+  NNCP_ADMM = 3,
+  NNCP_NES = 4,
+  NNCP_NES_OUTER = 5
+};
 
 /* Options (pass NULL for the defaults, shown in brackets). */
 typedef struct nncp_options {
@@ -208,8 +217,16 @@ int nncp_update_admm(nncp_ctx *ctx, int mode, const void *M, const double *S);
  * (condition number of S + lam I at most 100); alpha = 1 / (L + lam);
  * beta = (1 - sqrt(q)) / (1 + sqrt(q)), q = (mu + lam) / (L + lam).  With
  * L <= 0 the rows keep their values.  Then normalisation and G^(n) as above.
- * The outer extrapolation of Eq. eqn:nesouterupd is not applied.  R <= 64
- * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_NES as its algo.
+ * The outer extrapolation of Eq. eqn:nesouterupd is not part of this call.
+ * R <= 64 (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_NES as its
+ * algo, and NNCP_NES_OUTER for these updates plus, after every sweep i
+ * (from 1), the outer step: with F^(n) = H^(n) for n < N-1 and
+ * F^(N-1) = H^(N-1) diag(lambda), and F_prev the iterate before the sweep,
+ * the candidate max(0, F + i^(1/N) (F - F_prev)) is normalised (lambda = the
+ * product of its column norms) and replaces the iterate when its squared
+ * relative error, from one extra MTTKRP of mode N-1, is lower; relerr_hist
+ * then holds the candidate's error.  The outer step uses the workspace of
+ * nncp_pgd for its copies.
  */
 int nncp_update_nes(nncp_ctx *ctx, int mode, const void *M, const double *S);
 

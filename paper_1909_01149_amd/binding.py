@@ -25,7 +25,7 @@ NNCP_E_STATE = -5
 NNCP_E_UNSUPPORTED = -6
 
 NNCP_F64, NNCP_F32, NNCP_BF16, NNCP_F16 = 0, 1, 2, 3
-NNCP_MU, NNCP_HALS, NNCP_BPP, NNCP_ADMM, NNCP_NES = 0, 1, 2, 3, 4
+NNCP_MU, NNCP_HALS, NNCP_BPP, NNCP_ADMM, NNCP_NES, NNCP_NES_OUTER = 0, 1, 2, 3, 4, 5
 NNCP_MAX_MODES = 16
 
 EXPORTS = [

@@ -50,7 +50,7 @@ struct Layout {
   int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
   // byte offsets into the workspace
   size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart,
-      off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_admmU,
+      off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_outer, off_admmU,
       off_admmMc, off_admmP, off_admmNorm, off_admmStatus, total;
 };
 
@@ -266,6 +266,9 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_ks = take(hs * L.kslow_elems);
   L.off_pgdH = take(hs * L.sumI * R);
   L.off_pgdG = take(hs * L.sumI * R);
+  // NES outer extrapolation (R <= 64): lambda before the sweep, the
+  // candidate's lambda, its scalars, and per-mode column norms
+  L.off_outer = take(R <= 64 ? sizeof(double) * ((NNCP_MAX_MODES + 2) * R + 16) : 0);
   // ADMM (R <= 64): duals of every mode, the kept M sum, P and rho, norms
   const bool admm = R <= 64;
   L.off_admmU = take(admm ? sizeof(double) * L.sumI * R : 0);
@@ -313,6 +316,7 @@ struct nncp_ctx {
   GramJob pending{};          // Gram step of the last update, not yet run (R == 0: none)
   double *admmU, *admmMc, *admmP, *admmNorm;
   int *admmStatus;
+  double *outer;
   void *M, *nodeA, *nodeB, *part, *kf, *ks;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
 };
@@ -590,6 +594,7 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->upart = (double *)(c->ws + L.off_upart);
   c->gpart = (double *)(c->ws + L.off_gpart);
   c->admmU = (double *)(c->ws + L.off_admmU);
+  c->outer = (double *)(c->ws + L.off_outer);
   c->admmMc = (double *)(c->ws + L.off_admmMc);
   c->admmP = (double *)(c->ws + L.off_admmP);
   c->admmNorm = (double *)(c->ws + L.off_admmNorm);
@@ -746,12 +751,82 @@ int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
   return NNCP_OK;
 }
 
+// Outer extrapolation after sweep s (from 0) of the Nesterov-type sweeps
+// (Section 4.3.5, Eq. eqn:nesouterupd), on F^(n) = H^(n) (n < N-1) and
+// F^(N-1) = H^(N-1) diag(lambda) with the iterate saved before the sweep
+// (c->pgdG, lambda in c->outer): candidate max(0, F + s_i (F - F_prev)),
+// s_i = (s+1)^(1/N), normalised into c->pgdH with its Grams in c->Gt and
+// lambda_c the product of the column norms; its error from the identity
+// (an extra MTTKRP of mode N-1); taken when its squared relative error is
+// lower than the sweep's (c->scal[2]).  All on the stream, no host decision.
+static int nes_outer_step(nncp_ctx *c, int s, double *hist) {
+  const Layout &L = c->L;
+  const int N = L.N, R = L.R;
+  const size_t hs = xsize(L.hdt);
+  double *lamp = c->outer, *lamc = c->outer + R, *cand = c->outer + 2 * R;
+  double *lamk = c->outer + 2 * R + 16;
+  const double si = pow((double)(s + 1), 1.0 / N);
+  for (int k = 0; k < N; ++k) {
+    int nb = 0;
+    TIMED(4, launch_nes_extrap(L.hdt, c->H[k], c->pgdG[k], c->lambda, lamp, k == N - 1, si,
+                               L.dims[k], R, c->hhat, c->upart, &nb, c->st));
+    UpdateArgs a{};
+    a.algo = NNCP_NES;
+    a.I = L.dims[k];
+    a.R = R;
+    a.N = N;
+    a.mode = k;
+    a.next_mode = (k + 1) % N;
+    a.S = c->S;
+    a.S_next = nullptr;
+    a.G = c->Gt;
+    a.H = c->pgdH[k];
+    a.lambda = lamk + (int64_t)k * R;
+    a.hhat = c->hhat;
+    a.part = c->upart;
+    a.gpart = c->gpart;
+    a.beta_out = cand + 8;
+    a.alpha = c->scal + 8;
+    a.relerr_out = nullptr;
+    a.scal = nullptr;
+    a.nesParam = c->scal + 56;
+    GramJob job;
+    TIMED(4, launch_norm_only(L.hdt, a, nb, c->st, &job));
+    TIMED(4, launch_gram_finish(job, c->st));
+  }
+  TIMED(4, launch_nes_lamc(lamk, N, R, lamc, c->st));
+  const FactorSet Fc = factors_of(c, c->pgdH);
+  int rc = mttkrp_tree(c, Fc, N - 1, c->M, true);
+  if (rc) return rc;
+  // cand: [1] relerr, [2..4] beta, gamma, raw squared relative error
+  TIMED(4, launch_loss(L.hdt, N, R, L.dims[N - 1], c->M, c->pgdH[N - 1], lamc, c->Gt,
+                       c->scal + 8, nullptr, cand + 1, cand + 2, c->st));
+  const double *ce2 = cand + 4, *e2 = c->scal + 2;
+  for (int k = 0; k < N; ++k)
+    TIMED(4, launch_nes_accept(hs, c->pgdH[k], c->H[k], L.dims[k] * R, ce2, e2, c->st));
+  TIMED(4, launch_nes_accept(sizeof(double), lamc, c->lambda, R, ce2, e2, c->st));
+  TIMED(4, launch_nes_accept(sizeof(double), c->Gt, c->G, (int64_t)N * R * R, ce2, e2, c->st));
+  TIMED(4, launch_nes_accept_hist(ce2, e2, cand + 1, hist, c->st));
+  return NNCP_OK;
+}
+
 static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   const Layout &L = c->L;
   const FactorSet F = factors_of(c, c->H);
+  const bool outer = algo == NNCP_NES_OUTER;
+  if (outer) algo = NNCP_NES;
+  const size_t hs = xsize(L.hdt);
   // S^(0) here; every update then leaves S of the next mode in c->S
   HIPCHK(launch_hadamard(c->G, L.N, L.R, 0, c->S, c->st));
   for (int s = 0; s < nsweeps; ++s) {
+    if (outer) {
+      // the iterate before the sweep; S^(0) again (the Grams may have been
+      // replaced by the previous sweep's candidate)
+      if (s > 0) HIPCHK(launch_hadamard(c->G, L.N, L.R, 0, c->S, c->st));
+      for (int k = 0; k < L.N; ++k)
+        HIPCHK(launch_copy(hs, c->H[k], c->pgdG[k], L.dims[k] * L.R, c->st));
+      HIPCHK(launch_copy(sizeof(double), c->lambda, c->outer, L.R, c->st));
+    }
     for (int n = 0; n < L.N; ++n) {
       MRef M;
       int rc = mttkrp_tree(c, F, n, c->M, false, &M);
@@ -767,6 +842,11 @@ static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_his
         c->pending.R = 0;
         return rc;
       }
+    }
+    if (outer) {
+      HIPCHK(flush_gram(c));
+      int rc = nes_outer_step(c, s, relerr_hist ? relerr_hist + s : nullptr);
+      if (rc) return rc;
     }
   }
   HIPCHK(flush_gram(c));
@@ -814,7 +894,7 @@ static int build_graph(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) 
 int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo < NNCP_MU || algo > NNCP_NES) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo < NNCP_MU || algo > NNCP_NES_OUTER) return fail(NNCP_E_INVAL, "algo %d", algo);
   if (algo >= NNCP_BPP && c->L.R > 64)
     return fail(NNCP_E_UNSUPPORTED, "BPP, ADMM and NES need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
@@ -835,7 +915,7 @@ int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
 int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (algo < NNCP_MU || algo > NNCP_NES) return fail(NNCP_E_INVAL, "algo %d", algo);
+  if (algo < NNCP_MU || algo > NNCP_NES_OUTER) return fail(NNCP_E_INVAL, "algo %d", algo);
   if (algo >= NNCP_BPP && c->L.R > 64)
     return fail(NNCP_E_UNSUPPORTED, "BPP, ADMM and NES need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 1) return fail(NNCP_E_INVAL, "nsweeps %d < 1", nsweeps);

@@ -306,6 +306,24 @@ __device__ inline void gram_finish(const GramJob &j) {
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st, GramJob *job);
 // the Gram step as a kernel of its own (no-op for an empty job)
 hipError_t launch_gram_finish(const GramJob &j, hipStream_t st);
+// the norm kernel alone on rows left in a.hhat with nblocks per-workgroup
+// partials in a.part (R <= 64); *job as for launch_update
+hipError_t launch_norm_only(int hdt, const UpdateArgs &a, int nblocks, hipStream_t st,
+                            GramJob *job);
+
+// Outer extrapolation of the Nesterov-type sweeps (Eq. eqn:nesouterupd)
+hipError_t launch_copy(size_t elem_bytes, const void *src, void *dst, int64_t n, hipStream_t st);
+// raw = max(0, F + s (F - F_prev)), F = H (times lambda if last), FP64, with
+// per-4-row column sums of squares in part; *nblocks receives their count
+hipError_t launch_nes_extrap(int hdt, const void *H, const void *Hp, const double *lam,
+                             const double *lamp, int last, double s, int64_t I, int R, double *raw,
+                             double *part, int *nblocks, hipStream_t st);
+hipError_t launch_nes_lamc(const double *lamk, int N, int R, double *lamc, hipStream_t st);
+// dst = src when cand_e2 < cur_e2 (device scalars)
+hipError_t launch_nes_accept(size_t elem_bytes, const void *src, void *dst, int64_t n,
+                             const double *cand_e2, const double *cur_e2, hipStream_t st);
+hipError_t launch_nes_accept_hist(const double *cand_e2, const double *cur_e2,
+                                  const double *cand_rel, double *hist, hipStream_t st);
 
 // loss of [[lambda; H]] from M^(N-1): loss = 0.5 (alpha - 2 beta + gamma)
 hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const void *H,

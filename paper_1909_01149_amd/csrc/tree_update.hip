@@ -1736,6 +1736,167 @@ hipError_t launch_gram_finish(const GramJob &j, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Outer extrapolation of the Nesterov-type sweeps (Section 4.3.5, Eq.
+// eqn:nesouterupd): the candidate F + s (F - F_prev), clipped at 0, for
+// F = H (and H diag(lambda) for the last mode), its normalisation and Gram
+// through the update's norm kernel and Gram step, then an accept step that
+// takes the candidate only when its squared relative error is lower.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const T *__restrict__ src, T *__restrict__ dst,
+                                              int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+
+// one row per wave, 4 rows per workgroup; lane c owns entry c.  Writes the
+// clipped candidate (FP64) and, per workgroup, the column sums of squares of
+// its rows added in wave order (the row kernel's partial layout, beta = 0).
+template <typename HT>
+__global__ __launch_bounds__(256) void k_nes_extrap(const HT *__restrict__ H,
+                                                    const HT *__restrict__ Hp,
+                                                    const double *__restrict__ lam,
+                                                    const double *__restrict__ lamp, int last,
+                                                    double s, int64_t I, int R,
+                                                    double *__restrict__ raw,
+                                                    double *__restrict__ part) {
+  __shared__ double wred[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  const bool ok = i < I && lane < R;
+  double sq = 0.0;
+  if (ok) {
+    const double f = (double)H[i * R + lane] * (last ? lam[lane] : 1.0);
+    const double fp = (double)Hp[i * R + lane] * (last ? lamp[lane] : 1.0);
+    double v = f + s * (f - fp);
+    v = v > 0.0 ? v : 0.0;
+    raw[i * R + lane] = v;
+    sq = v * v;
+  }
+  wred[wave][lane] = sq;
+  __syncthreads();
+  double *cpart = part + (int64_t)blockIdx.x * (R + 1);
+  if (threadIdx.x < R)
+    cpart[threadIdx.x] = wred[0][threadIdx.x] + wred[1][threadIdx.x] + wred[2][threadIdx.x] +
+                         wred[3][threadIdx.x];
+  if (threadIdx.x == 0) cpart[R] = 0.0;
+}
+
+// lambda_c(r) = prod over modes of the candidate's column norms, in mode order
+__global__ __launch_bounds__(64) void k_nes_lamc(const double *__restrict__ lamk, int N, int R,
+                                                 double *__restrict__ lamc) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double p = 1.0;
+  for (int k = 0; k < N; ++k) p *= lamk[(int64_t)k * R + r];
+  lamc[r] = p;
+}
+
+// every thread takes the same decision from the two squared errors
+template <typename T>
+__global__ __launch_bounds__(256) void k_nes_accept(const T *__restrict__ src, T *__restrict__ dst,
+                                                    int64_t n, const double *__restrict__ cand_e2,
+                                                    const double *__restrict__ cur_e2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n && cand_e2[0] < cur_e2[0]) dst[e] = src[e];
+}
+
+__global__ __launch_bounds__(256) void k_nes_accept_hist(const double *__restrict__ cand_e2,
+                                                         const double *__restrict__ cur_e2,
+                                                         const double *__restrict__ cand_rel,
+                                                         double *__restrict__ hist) {
+  if (threadIdx.x == 0 && cand_e2[0] < cur_e2[0]) hist[0] = cand_rel[0];
+}
+
+hipError_t launch_copy(size_t elem_bytes, const void *src, void *dst, int64_t n, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (n <= 0) return hipSuccess;
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_copy<double>, grid, block, 0, st, (const double *)src, (double *)dst, n);
+  else
+    hipLaunchKernelGGL(k_copy<float>, grid, block, 0, st, (const float *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_extrap(int hdt, const void *H, const void *Hp, const double *lam,
+                             const double *lamp, int last, double s, int64_t I, int R, double *raw,
+                             double *part, int *nblocks, hipStream_t st) {
+  if (R > 64) return hipErrorInvalidValue;
+  const int nb = (int)((I + 3) / 4);
+  *nblocks = nb;
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_nes_extrap<double>, dim3(nb), dim3(256), 0, st, (const double *)H,
+                       (const double *)Hp, lam, lamp, last, s, I, R, raw, part);
+  else
+    hipLaunchKernelGGL(k_nes_extrap<float>, dim3(nb), dim3(256), 0, st, (const float *)H,
+                       (const float *)Hp, lam, lamp, last, s, I, R, raw, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_lamc(const double *lamk, int N, int R, double *lamc, hipStream_t st) {
+  hipLaunchKernelGGL(k_nes_lamc, dim3(1), dim3(64), 0, st, lamk, N, R, lamc);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_accept(size_t elem_bytes, const void *src, void *dst, int64_t n,
+                             const double *cand_e2, const double *cur_e2, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_nes_accept<double>, grid, block, 0, st, (const double *)src,
+                       (double *)dst, n, cand_e2, cur_e2);
+  else
+    hipLaunchKernelGGL(k_nes_accept<float>, grid, block, 0, st, (const float *)src, (float *)dst,
+                       n, cand_e2, cur_e2);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_accept_hist(const double *cand_e2, const double *cur_e2,
+                                  const double *cand_rel, double *hist, hipStream_t st) {
+  if (!hist) return hipSuccess;
+  hipLaunchKernelGGL(k_nes_accept_hist, dim3(1), dim3(64), 0, st, cand_e2, cur_e2, cand_rel, hist);
+  return hipGetLastError();
+}
+
+// The norm kernel and Gram job alone (R <= 64), for rows given as Hhat and
+// per-workgroup partials from another kernel.
+hipError_t launch_norm_only(int hdt, const UpdateArgs &a, int nblocks, hipStream_t st,
+                            GramJob *job) {
+  if (a.R > 64) return hipErrorInvalidValue;
+  int64_t rpw;
+  const int nw = norm_workgroups(a.I, &rpw);
+  *job = GramJob{};
+  job->gpart = a.gpart;
+  job->pn = a.gpart + norm_pn_offset(a.R);
+  job->G = a.G;
+  job->S = a.S;
+  job->S_next = a.S_next;
+  job->lambda = a.lambda;
+  job->beta = a.beta_out;
+  job->alpha = a.alpha;
+  job->relerr_out = a.relerr_out;
+  job->scal = a.scal;
+  job->R = a.R;
+  job->N = a.N;
+  job->mode = a.mode;
+  job->next_mode = a.next_mode;
+  job->nw = nw;
+#define NNCP_NORM_ONLY(HTV, RBV) \
+  hipLaunchKernelGGL((k_update_norm<HTV, RBV>), dim3(nw), dim3(256), 0, st, a, nblocks, rpw)
+  if (hdt == NNCP_F64) {
+    if (a.R <= 16) NNCP_NORM_ONLY(double, 16);
+    else if (a.R <= 32) NNCP_NORM_ONLY(double, 32);
+    else NNCP_NORM_ONLY(double, 64);
+  } else {
+    if (a.R <= 16) NNCP_NORM_ONLY(float, 16);
+    else if (a.R <= 32) NNCP_NORM_ONLY(float, 32);
+    else NNCP_NORM_ONLY(float, 64);
+  }
+#undef NNCP_NORM_ONLY
+  return hipGetLastError();
+}
+
 int64_t update_part_elems(int64_t I, int R) {
   // one row per workgroup at the most (the BPP kernel at R > 32)
   return I * (int64_t)(R + 1);

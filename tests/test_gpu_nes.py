@@ -167,3 +167,60 @@ def test_nes_graph_replay_matches_eager(nn):
             assert torch.equal(a, b), rep
     cg.close()
     ce.close()
+
+
+# ---------------------------------------------------------------------------
+# sweeps with the outer extrapolation (Eq. eqn:nesouterupd)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims,R,split", [([12, 10, 14], 4, 0), ([6, 5, 4, 7], 3, 1),
+                                          ([4, 5, 3, 4, 5], 4, 0), ([40, 30, 20], 24, 0)])
+def test_nes_outer_sweep_fp64_trajectory(nn, dims, R, split):
+    banner("nes outer sweep fp64", dims, R, split)
+    X64, H64 = gen.small_lowrank(dims, R, R, 81, noise=0.03)
+    X, H, Xo, Ho = prepare(X64, H64, "f64")
+    ctx = nn.Context(X, H, split=split)
+    rel = ctx.sweep(nn.NNCP_NES_OUTER, 8).cpu().numpy()
+    Hr, lam, rel_o, _ = oracle.sweeps(Xo, Ho, np.ones(R), oracle.NES_OUTER, 8)
+    _, _, rel_p, _ = oracle.sweeps(Xo, Ho, np.ones(R), oracle.NES, 8)
+    print("gpu", rel, "oracle", rel_o, "plain", rel_p, flush=True)
+    np.testing.assert_allclose(rel, rel_o, rtol=1e-9, atol=1e-12)
+    for x, y in zip(ctx.factors, Hr):
+        assert relerr(x.cpu().numpy(), y) <= 1e-9
+    assert relerr(ctx.lam.cpu().numpy(), lam) <= 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("xdt", ["f32", "bf16"])
+def test_nes_outer_sweep_low_precision(nn, xdt):
+    banner("nes outer sweep", xdt)
+    dims = [64, 64, 64]
+    X64, H64 = gen.small_lowrank(dims, 8, 8, 99, noise=0.02)
+    X, H, Xo, Ho = prepare(X64, H64, xdt)
+    ctx = nn.Context(X, H)
+    rel = ctx.sweep(nn.NNCP_NES_OUTER, 8).cpu().numpy()
+    _, _, rel_o, _ = oracle.sweeps(Xo, Ho, np.ones(8), oracle.NES_OUTER, 8, nthreads=4)
+    print("gpu", rel, "oracle", rel_o, flush=True)
+    assert np.max(np.abs(rel - rel_o)) <= (1e-5 if xdt == "f32" else 3e-5), (rel, rel_o)
+    ctx.close()
+
+
+def test_nes_outer_graph_replay_matches_eager(nn):
+    banner("nes outer graph")
+    dims = [64, 48, 40]
+    X64, H64 = gen.small_lowrank(dims, 6, 12, 23, noise=0.05)
+    X, H, _, _ = prepare(X64, H64, "bf16")
+    cg = nn.Context(X, [h.clone() for h in H], graphs=1)
+    ce = nn.Context(X, [h.clone() for h in H], graphs=0)
+    hg = torch.empty(3, dtype=torch.float64, device="cuda")
+    he = torch.empty(3, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        cg.sweep(nn.NNCP_NES_OUTER, 3, hg)
+        ce.sweep(nn.NNCP_NES_OUTER, 3, he)
+        torch.cuda.synchronize()
+        assert torch.equal(hg, he), (rep, hg, he)
+        for a, b in zip(cg.factors, ce.factors):
+            assert torch.equal(a, b), rep
+        assert torch.equal(cg.lam, ce.lam), rep
+    cg.close()
+    ce.close()
