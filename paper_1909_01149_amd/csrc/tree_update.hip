@@ -601,82 +601,6 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
 }
 
 // ---------------------------------------------------------------------------
-// Step parameters of the Nesterov-type update (Section 4.3.5), one wave, lane
-// i holding row i of S: L = the largest eigenvalue of S and L - mu the
-// largest of L I - S, each by kNesPower power steps from the all-ones vector
-// (sums in index order, every lane forming the same scalars), then
-// lam = max(0, (L - kappa mu) / (kappa - 1)), alpha = 1 / (L + lam) and the
-// constant momentum beta = (1 - sqrt(q)) / (1 + sqrt(q)), q = (mu + lam) /
-// (L + lam).  Writes [L, mu, lam, alpha, beta, ok]; ok = 0 when L <= 0.
-// ---------------------------------------------------------------------------
-template <int RB>
-__device__ double nes_power(const double (&sr)[RB], int R, int lane, double shift, double sgn) {
-  const bool own = lane < R;
-  // row `lane` of shift I + sgn S
-  auto row = [&](int j) { return (j == lane ? shift : 0.0) + sgn * sr[j]; };
-  double v = own ? 1.0 / sqrt((double)R) : 0.0;
-  for (int t = 0; t < kNesPower; ++t) {
-    double w = 0.0;
-#pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (j < R) w += row(j) * bcast(v, j);
-    double nrm = 0.0;
-#pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (j < R) {
-        const double wj = bcast(w, j);
-        nrm += wj * wj;
-      }
-    nrm = sqrt(nrm);
-    if (!(nrm > 0.0)) break;
-    v = own ? w / nrm : 0.0;
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int j = 0; j < RB; ++j)
-    if (j < R) s += row(j) * bcast(v, j);
-  double num = 0.0;
-#pragma unroll
-  for (int j = 0; j < RB; ++j)
-    if (j < R) num += bcast(v, j) * bcast(s, j);
-  return num;
-}
-
-template <int RB>
-__global__ __launch_bounds__(64) void k_nes_prep(UpdateArgs a) {
-  const int R = a.R, lane = threadIdx.x;
-  const bool own = lane < R;
-  double sr[RB];
-#pragma unroll
-  for (int j = 0; j < RB; ++j) sr[j] = (own && j < R) ? a.S[lane * R + j] : 0.0;
-  if (!own) {
-#pragma unroll
-    for (int j = 0; j < RB; ++j) sr[j] = 0.0;
-  }
-  const double L = nes_power<RB>(sr, R, lane, 0.0, 1.0);
-  const double lt = nes_power<RB>(sr, R, lane, L, -1.0);
-  double mu = L - lt;
-  if (!(mu > 0.0)) mu = 0.0;
-  double lam = (L - kNesKappa * mu) / (kNesKappa - 1.0);
-  if (!(lam > 0.0)) lam = 0.0;
-  double alpha = 0.0, beta = 0.0, ok = 0.0;
-  if (L > 0.0) {
-    const double q = sqrt((mu + lam) / (L + lam));
-    alpha = 1.0 / (L + lam);
-    beta = (1.0 - q) / (1.0 + q);
-    ok = 1.0;
-  }
-  if (lane < 6) {
-    const double vals[6] = {L, mu, lam, alpha, beta, ok};
-    double v = vals[0];
-#pragma unroll
-    for (int k = 1; k < 6; ++k)
-      if (lane == k) v = vals[k];
-    a.nesParam[lane] = v;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Row update for R <= RB <= 64: one row per wave, lane c owns column c and
 // keeps column c of S in registers.  HALS (Alg 2) visits the columns in
 // order; at step r every lane forms its candidate, the value of lane r is
@@ -794,6 +718,77 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Step parameters of the Nesterov-type update (Section 4.3.5), one wave, lane
+// i holding row i of S: L = the largest eigenvalue of S and L - mu the
+// largest of L I - S, each by kNesPower power steps from the all-ones vector
+// (the vector goes through LDS for the matrix-vector product, four partial
+// sums per lane; norms by a wave reduction), then
+// lam = max(0, (L - kappa mu) / (kappa - 1)), alpha = 1 / (L + lam) and the
+// constant momentum beta = (1 - sqrt(q)) / (1 + sqrt(q)), q = (mu + lam) /
+// (L + lam).  Writes [L, mu, lam, alpha, beta, ok]; ok = 0 when L <= 0.
+// ---------------------------------------------------------------------------
+template <int RB>
+__device__ double nes_power(const double (&sr)[RB], int R, int lane, double shift, double sgn,
+                            double *vs) {
+  const bool own = lane < R;
+  // row `lane` of shift I + sgn S, times the vector in vs
+  auto matvec = [&](double v) {
+    vs[lane] = v;
+    wave_sync();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < R) acc[j & 3] += ((j == lane ? shift : 0.0) + sgn * sr[j]) * vs[j];
+    wave_sync();
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  };
+  double v = own ? 1.0 / sqrt((double)R) : 0.0;
+  for (int t = 0; t < kNesPower; ++t) {
+    const double w = matvec(v);
+    const double nrm = sqrt(wave_sum(own ? w * w : 0.0));
+    if (!(nrm > 0.0)) break;
+    v = own ? w / nrm : 0.0;
+  }
+  const double sv = matvec(v);
+  return wave_sum(own ? v * sv : 0.0);
+}
+
+template <int RB>
+__global__ __launch_bounds__(64) void k_nes_prep(UpdateArgs a) {
+  __shared__ double vs[64];
+  const int R = a.R, lane = threadIdx.x;
+  const bool own = lane < R;
+  double sr[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) sr[j] = (own && j < R) ? a.S[lane * R + j] : 0.0;
+  if (!own) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j) sr[j] = 0.0;
+  }
+  const double L = nes_power<RB>(sr, R, lane, 0.0, 1.0, vs);
+  const double lt = nes_power<RB>(sr, R, lane, L, -1.0, vs);
+  double mu = L - lt;
+  if (!(mu > 0.0)) mu = 0.0;
+  double lam = (L - kNesKappa * mu) / (kNesKappa - 1.0);
+  if (!(lam > 0.0)) lam = 0.0;
+  double alpha = 0.0, beta = 0.0, ok = 0.0;
+  if (L > 0.0) {
+    const double q = sqrt((mu + lam) / (L + lam));
+    alpha = 1.0 / (L + lam);
+    beta = (1.0 - q) / (1.0 + q);
+    ok = 1.0;
+  }
+  if (lane < 6) {
+    const double vals[6] = {L, mu, lam, alpha, beta, ok};
+    double v = vals[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+      if (lane == k) v = vals[k];
+    a.nesParam[lane] = v;
+  }
 }
 
 // BPP rows for R <= RB <= 64 (Section 4.3.3, Eq. eqn:snls): every row x of

@@ -2,9 +2,9 @@
 eqn:nesinnerupd: 20 accelerated projected-gradient steps on the proximal
 subproblem, step parameters from power-step estimates of the extreme
 eigenvalues of S) against the CPU oracle, through the C ABI.  Tolerances
-(normwise relative): FP64 1e-10 (both sides form the parameters with the
-same sums in the same order; they differ by rounding, e.g. fused
-multiply-adds on the GPU); FP32 factors 1e-6."""
+(normwise relative): FP64 1e-10 (both sides take the same power steps; the
+GPU adds each matrix-vector product in four partial sums and the norms by a
+wave reduction, so the parameters differ by rounding); FP32 factors 1e-6."""
 import numpy as np
 import pytest
 
