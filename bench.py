@@ -409,31 +409,39 @@ def summarize_trace(stats_csv, cmd, out_name="kernels_512cube_hals.txt",
     print("\n".join(lines))
 
 
+def _prof_args(csv_path):
+    """`-d <dir> -o <prefix>` of the rocprofv3 run that wrote csv_path (the
+    directory holding it and the file-name prefix before the first '_')."""
+    d = os.path.relpath(os.path.dirname(os.path.abspath(csv_path)), ROOT)
+    prefix = os.path.basename(csv_path).split("_")[0]
+    return f"-d {d} -o {prefix}"
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
+        pa = _prof_args(sys.argv[2])
         if len(sys.argv) > 3 and sys.argv[3] == "nls":
             # the c2bpp configuration: HALS, BPP, ADMM and NES on the BF16 512^3 tensor
-            summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "
-                            "gpurun_out/prof_nls -o nls -- python3 bench.py --configs c2bpp",
+            summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
+                            f"{pa} -- python3 bench.py --configs c2bpp",
                             "kernels_512cube_nls.txt",
                             "512x512x512 R=32 BF16 tensor, 50 sweeps each of HALS, BPP, ADMM, NES "
                             "and NES with the outer step "
                             "(timed and untimed passes)")
             return
-        summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv -d "
-                        "gpurun_out/prof -o bench -- python3 bench.py --steps 10 --warmup 2 "
-                        "--no-cpu-baseline")
+        summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
+                        f"{pa} -- python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         fetch_csv, write_csv = sys.argv[2], sys.argv[3]
-        cmd_f = ("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- "
-                 "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe")
-        cmd_w = cmd_f.replace("FETCH_SIZE", "WRITE_SIZE").replace("pmc_fetch", "pmc_write").replace("-o f", "-o w")
+        run = "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe"
+        cmd_f = f"rocprofv3 --pmc FETCH_SIZE --output-format csv {_prof_args(fetch_csv)} {run}"
+        cmd_w = f"rocprofv3 --pmc WRITE_SIZE --output-format csv {_prof_args(write_csv)} {run}"
         summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w)
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-mfma":
         summarize_mfma(sys.argv[2], "rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE "
-                       "--output-format csv -d gpurun_out/pmc_mfma -o m -- python3 bench.py "
+                       f"--output-format csv {_prof_args(sys.argv[2])} -- python3 bench.py "
                        "--steps 3 --warmup 1 --no-cpu-baseline")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--configs":

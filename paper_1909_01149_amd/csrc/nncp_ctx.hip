@@ -1,7 +1,7 @@
 // Host side of the NNCP library: the C ABI declared in include/nncp.h, the
 // planner (root split, Khatri-Rao factoring, grids), the workspace carve-up,
 // the dimension-tree walk of Algorithm 3, the sweep of Algorithm 1 and the
-// projected-gradient driver.  All device work is launched on the context's
+// projected-gradient loop.  All device work is launched on the context's
 // stream; nothing here allocates device memory.
 #include <stdarg.h>
 #include <stdio.h>

@@ -578,7 +578,7 @@ def test_objective_nonincreasing_after_every_mode(algo):
             fn = np.linalg.norm(X - reconstruct(Hs, lam))
             assert fn <= f * (1 + 1e-12)
             f = fn
-    # and the oracle's own sweep driver follows the same trajectory
+    # and the oracle's own sweep loop follows the same trajectory
     Ho, lo, rel, _ = oracle.sweeps(X, H, np.ones(3), algo, 4)
     for a, b in zip(Ho, Hs):
         np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
