@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_mttv_contig_wide(const HT *__restrict__
   }
 }
 
-// Same reduction for Ia % V == 0 and Ia <= 64 V CPL: a wave owns QB = 16 / CPL
+// Same reduction for Ia % V == 0 and Ia <= 64 V CPL: a wave owns QB = 8 / CPL
 // outputs (q, r).  Each lane issues its loads of the QB rows of T first, the
 // workgroup then stages H(:, r) in LDS, and the products are added in the
 // order of the kernel above; a workgroup costs one memory round trip.
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_mttv_contig_reg(const HT *__restrict__ 
                                                          HT *__restrict__ out, int leaf,
                                                          GramJob job) {
   constexpr int V = 16 / (int)sizeof(HT);
-  constexpr int QB = 16 / CPL;
+  constexpr int QB = 8 / CPL;
   typedef HT vt __attribute__((ext_vector_type(V)));
   __shared__ vt hs[64 * CPL];
   // an extra column of workgroups when carrying the Gram step
@@ -1500,7 +1500,7 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
   if (carry) carry->R = 0;
   if (Ia % V == 0 && Ia <= 8 * 64 * V) {
     const int CPL = Ia <= 64 * V ? 1 : Ia <= 128 * V ? 2 : Ia <= 256 * V ? 4 : 8;
-    const int QB = 16 / CPL;
+    const int QB = 8 / CPL;
     dim3 grid((unsigned)R + (job.R ? 1 : 0), (unsigned)((Q + 4 * QB - 1) / (4 * QB))), block(256);
 #define NNCP_CONTIG_REG(HTV, C)                                                            \
   hipLaunchKernelGGL((k_mttv_contig_reg<HTV, C>), grid, block, 0, st, (const HTV *)T, Ia, Q, R, \
