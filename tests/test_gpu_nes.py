@@ -115,6 +115,12 @@ def test_nes_needs_r_at_most_64(nn):
     ctx = nn.Context(X, H)
     with pytest.raises(nn.NNCPError):
         ctx.sweep(nn.NNCP_NES, 1)
+    with pytest.raises(nn.NNCPError):
+        ctx.sweep(nn.NNCP_NES_OUTER, 1)
+    M = torch.zeros(20, 70, dtype=torch.float32, device="cuda")
+    S = torch.eye(70, dtype=torch.float64, device="cuda")
+    with pytest.raises(nn.NNCPError):
+        ctx.update(nn.NNCP_NES, 0, M, S)
     ctx.close()
 
 
