@@ -296,13 +296,40 @@ __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
   };
 
   // batches of U steps, the next batch's loads issued before the current
-  // batch is consumed (the last batch re-reads itself instead of running past
-  // the wave's range)
+  // batch is consumed.  16-bit and FP64 tensors: current/next buffers with a
+  // copy (the last batch re-reads itself instead of running past the wave's
+  // range).  FP32 tensors: two buffers used in turn with the loop unrolled
+  // over them, so no copy waits for the loads (measured 5% faster for FP32,
+  // slower for BF16); loads past the last full batch re-read it.
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) xp[mt] += w_lo * KSTEP;
   int64_t t = w_lo;
   const int64_t nb = (w_hi - w_lo) / U;
-  if (nb > 0) {
+  if (nb > 0 && sizeof(XT) == 4) {
+    u32x4 buf[2][U][MT];
+    auto load = [&](u32x4 (&dst)[U][MT], int64_t bidx) {
+      const int64_t bc = bidx < nb ? bidx : nb - 1;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          dst[u][mt] = gload_c<u32x4>(xp[mt] + (bc * U + u) * KSTEP);
+    };
+    load(buf[0], 0);
+    for (int64_t b0 = 0; b0 < nb; b0 += 2) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t b = b0 + j;
+        load(buf[j ^ 1], b + 1);
+        if (b >= nb) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) step(buf[j][u]);
+      }
+    }
+    t += nb * U;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) xp[mt] += nb * U * KSTEP;
+  } else if (nb > 0) {
     u32x4 cur[U][MT], nxt[U][MT];
 #pragma unroll
     for (int u = 0; u < U; ++u)
