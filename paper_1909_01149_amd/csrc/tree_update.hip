@@ -1563,8 +1563,10 @@ static int strided_vec(int hdt, int64_t Ia) {
 
 static void strided_shape(int64_t Ia, int V, int64_t Q, int R, int &IT, int &QS, int &ns,
                           int64_t &gx) {
+  // at most 64 column threads, so at least 4 q-lanes per workgroup (the two
+  // multi-TTVs of a 512^3 sweep took 19.0 us against 20.4 us with 128 x 2)
   IT = 1;
-  while (IT < 256 && IT * V < Ia) IT *= 2;
+  while (IT < 64 && IT * V < Ia) IT *= 2;
   QS = 256 / IT;
   gx = (Ia + (int64_t)IT * V - 1) / ((int64_t)IT * V);
   int64_t want = (512 + gx * R - 1) / (gx * R);
