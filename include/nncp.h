@@ -243,7 +243,8 @@ int nncp_cp_loss(nncp_ctx *ctx, double *loss, double *relerr);
 /*
  * nsweeps outer iterations of Algorithm 1 (modes 0..N-1 in order), each mode
  * as nncp_mttkrp + nncp_update_*, with the dimension-tree temporaries reused
- * across modes as in Algorithm 3 (two passes over X per sweep).  After mode
+ * across modes as in Algorithm 3 (two passes over X per sweep, three with
+ * NNCP_NES_OUTER).  algo is one of enum nncp_algo.  After mode
  * N-1 the relative error is formed from that mode's M and Hhat (Algorithm 4):
  *   relerr_hist  nsweeps FP64: relative error after each sweep (may be NULL)
  * With options.graphs (the default) and timers off, the launches are captured
@@ -291,7 +292,11 @@ int nncp_pgd(nncp_ctx *ctx, int nsteps, double armijo_c, int max_halvings, int p
  *   1  right partial MTTKRP kernel (GEMM over modes 0..S-1)
  *   2  Khatri-Rao operands of the partial MTTKRPs
  *   3  multi-TTVs and split-reduction finalize
- *   4  factor update (MU/HALS, normalisation, Gram, relative error)
+ *   4  factor update (MU, HALS, BPP, ADMM, NES, normalisation, Gram,
+ *      relative error, the NES outer step except its MTTKRP)
+ * Inside nncp_sweep the Gram step of an update (slice sum, G^(n), gamma and
+ * the next mode's S) runs as an extra workgroup of the next Khatri-Rao or
+ * multi-TTV launch, so its time counts in category 2 or 3 there.
  * nncp_timers_enable(ctx, 1) starts recording (and clears the totals);
  * nncp_timers_read synchronises the stream and returns the totals in
  * milliseconds and the number of timed launches per category (host arrays of
