@@ -456,7 +456,7 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "one GPU per run: this benchmark measures a single MI355X; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

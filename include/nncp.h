@@ -71,7 +71,8 @@ enum nncp_status {
   NNCP_E_WORKSPACE = -3,   /* workspace smaller than nncp_workspace_size()       */
   NNCP_E_HIP = -4,         /* a HIP call or kernel launch failed                 */
   NNCP_E_STATE = -5,       /* context is NULL or already destroyed               */
-  NNCP_E_UNSUPPORTED = -6  /* valid request outside this build's limits (R>256)  */
+  NNCP_E_UNSUPPORTED = -6  /* valid request outside the library's limits (R > 256, or
+                              R > 64 for BPP, ADMM, NES and PGD)     */
 };
 
 enum nncp_dtype { NNCP_F64 = 0, NNCP_F32 = 1, NNCP_BF16 = 2, NNCP_F16 = 3 };

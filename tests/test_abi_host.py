@@ -91,3 +91,22 @@ def test_calls_on_null_context_fail(B):
     assert L.nncp_sweep(None, 0, 1, None) == B.NNCP_E_STATE
     assert L.nncp_destroy(None) == B.NNCP_E_STATE
     assert L.nncp_split(None) == B.NNCP_E_STATE
+
+
+def test_update_entry_points_on_null_context_fail(B):
+    L = B.lib()
+    for name in ("nncp_update_hals", "nncp_update_bpp", "nncp_update_admm", "nncp_update_nes"):
+        assert getattr(L, name)(None, 0, ctypes.c_void_p(16), ctypes.c_void_p(16)) == B.NNCP_E_STATE
+    assert L.nncp_update_mu(None, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 1e-16) == B.NNCP_E_STATE
+    assert L.nncp_sweep(None, B.NNCP_NES_OUTER, 1, None) == B.NNCP_E_STATE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
