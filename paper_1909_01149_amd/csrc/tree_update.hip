@@ -602,12 +602,12 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
 
 // ---------------------------------------------------------------------------
 // Row update for R <= RB <= 64: one row per wave, lane c owns column c and
-// keeps column c of S in registers.  HALS (Alg 2) visits the columns in
+// keeps column c of S in registers.  HALS (Eq. eqn:halsupd) visits the columns in
 // order; at step r every lane forms its candidate, the value of lane r is
 // broadcast and every lane folds the change into its entry of the gradient,
 // so a step costs a few dependent instructions.  The HALS quotient uses the
 // reciprocal of S(r, r) (within one rounding of the quotient).
-template <typename HT, int RB>
+template <typename HT, int RB, bool NES>
 __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   __shared__ double wred[4][64];
   __shared__ double bred[4];
@@ -634,8 +634,9 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   const double d_raw = a.S[c * R + c];
   const double lam_raw = a.lambda[c];
   const HT h_raw = H[ir * R + c];
-  const double nes_lam = a.nesParam[2], nes_alpha = a.nesParam[3], nes_beta = a.nesParam[4];
-  const bool nes_ok = a.nesParam[5] > 0.0;
+  const double nes_lam = NES ? a.nesParam[2] : 0.0, nes_alpha = NES ? a.nesParam[3] : 0.0;
+  const double nes_beta = NES ? a.nesParam[4] : 0.0;
+  const bool nes_ok = NES && a.nesParam[5] > 0.0;
   HT macc = mv[0];
 #pragma unroll
   for (int k = 1; k < 32; ++k)
@@ -649,7 +650,7 @@ __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   const double d = own ? d_raw : 0.0;
   double h = ok ? (double)h_raw * lam_raw : 0.0;
   const double m = ok ? (double)macc : 0.0;
-  if (a.algo == NNCP_NES) {
+  if constexpr (NES) {
     // Nesterov-type steps (Section 4.3.5) from x* = Hhat, the gradient of
     // the proximal objective y S - m + lam (y - x*) with y S in order
     if (nes_ok) {
@@ -1682,7 +1683,7 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
 #define NNCP_UPDATE_SMALL(RBV)                                                           \
   if (a.algo == NNCP_NES) {                                                             \
     hipLaunchKernelGGL((k_nes_prep<RBV>), dim3(1), dim3(64), 0, st, a);                 \
-    hipLaunchKernelGGL((k_update_rows_small<HT, RBV>), grid, block, 0, st, a);          \
+    hipLaunchKernelGGL((k_update_rows_small<HT, RBV, true>), grid, block, 0, st, a);    \
     hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
   } else if (a.algo == NNCP_ADMM) {                                                     \
     hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(1024), 0, st, a);              \
@@ -1695,7 +1696,7 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     hipLaunchKernelGGL((k_update_bpp<HT, RBV>), dim3(nbb), dim3(64 * WPB), 0, st, a);   \
     hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nbb, rpw); \
   } else {                                                                               \
-    hipLaunchKernelGGL((k_update_rows_small<HT, RBV>), grid, block, 0, st, a);          \
+    hipLaunchKernelGGL((k_update_rows_small<HT, RBV, false>), grid, block, 0, st, a);   \
     hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
   }
     if (a.R <= 16) {
