@@ -43,8 +43,10 @@
  *
  * Streams: every kernel is launched on the stream given to nncp_init (a
  * hipStream_t passed as void*; NULL is the default stream).  Calls are
- * asynchronous and outputs are valid once the stream has been synchronised,
- * except nncp_pgd, which synchronises to take its step-size decisions.
+ * asynchronous and outputs are valid once the stream has been synchronised.
+ * No call waits for the device except nncp_pgd, which synchronises to take
+ * its step-size decisions, and the timer calls nncp_timers_enable and
+ * nncp_timers_read.
  *
  * Errors: every call returns an int status.  Arguments are validated before
  * anything is launched, so a failing call launches nothing.  A HIP launch
@@ -101,8 +103,8 @@ typedef struct nncp_options {
                        about 2^-16 instead of 2^-8), 0 = single rounding [1]. */
   int generic;      /* 1 = force the portable vector-ALU partial-MTTKRP kernels
                        instead of the matrix-core ones [0].                    */
-  double eps_mu;    /* MU denominator guard (Eq. eqn:muupd: "a small value is
-                       added to the denominator") [1e-16].                     */
+  double eps_mu;    /* MU denominator guard, added to the denominator of
+                       Eq. eqn:muupd [1e-16].                                  */
   int graphs;       /* 1 = nncp_sweep replays its launches as a HIP graph
                        (captured once per (algo, nsweeps, relerr_hist) and
                        factor binding), 0 = plain launches [1].                */
@@ -161,7 +163,7 @@ int nncp_hadamard(nncp_ctx *ctx, int mode, double *S);
 /*
  * One factor update of mode n from M = M^(n) (I_n x R, h_dtype) and
  * S = S^(n) (R x R FP64):  Hhat = H^(n) diag(lambda) (lambda folded into the
- * factor being solved for, Appendix A), then
+ * factor being solved for, Appendix B), then
  *   MU   (Eq. eqn:muupd):  Hhat <- Hhat * M / (Hhat S + eps)   [eps < 0: the
  *                          context's eps_mu]
  *   HALS (Eq. eqn:halsupd): for r = 0..R-1 in order, if S(r,r) > 0,
@@ -181,8 +183,12 @@ int nncp_update_hals(nncp_ctx *ctx, int mode, const void *M, const double *S);
  * pivoting rule is that of the method the paper cites: full switches while
  * the number of violating indices falls, three more, then the largest index
  * alone; at most 5 R + 10 solves per row, and a row whose S_FF is not
- * positive definite keeps its last solution clipped at 0).  The start values
- * of H^(n) are not used.  Then normalisation and G^(n) as above.  R <= 64
+ * positive definite keeps its last solution clipped at 0).  Each row's
+ * search starts from the support (the positive entries) of its current value
+ * H^(n) diag(lambda), solved once; an empty support starts from x = 0.  The
+ * NNLS solution does not depend on the start when S is positive definite;
+ * the start only changes the number of solves.  Then normalisation and
+ * G^(n) as above.  R <= 64
  * (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_BPP as its algo.
  */
 int nncp_update_bpp(nncp_ctx *ctx, int mode, const void *M, const double *S);
@@ -220,8 +226,10 @@ int nncp_update_admm(nncp_ctx *ctx, int mode, const void *M, const double *S);
  * L <= 0 the rows keep their values.  Then normalisation and G^(n) as above.
  * The outer extrapolation of Eq. eqn:nesouterupd is not part of this call.
  * R <= 64 (NNCP_E_UNSUPPORTED otherwise); nncp_sweep accepts NNCP_NES as its
- * algo, and NNCP_NES_OUTER for these updates plus, after every sweep i
- * (from 1), the outer step: with F^(n) = H^(n) for n < N-1 and
+ * algo, and NNCP_NES_OUTER for these updates plus, after every sweep, the
+ * outer step of outer iteration i (i counts the NNCP_NES_OUTER sweeps since
+ * nncp_init or the last nncp_set_factors, from 1, on the device, so it
+ * continues across calls and graph replays): with F^(n) = H^(n) for n < N-1 and
  * F^(N-1) = H^(N-1) diag(lambda), and F_prev the iterate before the sweep,
  * the candidate max(0, F + i^(1/N) (F - F_prev)) is normalised (lambda = the
  * product of its column norms) and replaces the iterate when its squared

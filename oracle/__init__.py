@@ -6,9 +6,9 @@ with the GPU library (``paper_1909_01149_amd``) and neither imports the other.
 
 The arithmetic lives in ``nncp_oracle.c`` (plain C, FP64), which follows the
 paper's definitions (PLANC, arXiv 1909.01149): MTTKRP by its entrywise
-definition (Section 4.2.1, Appendix A), Algorithm 1 with the MU rule
+definition (Section 4.2.1, Appendix B), Algorithm 1 with the MU rule
 (Eq. eqn:muupd) and the HALS rule (Eq. eqn:halsupd), column normalisation and
-the relative-error identity (Appendix A, Algorithm 4).  This module only
+the relative-error identity (Appendix B, Algorithm 4).  This module only
 marshals NumPy arrays into that library.
 
 Layout conventions: a tensor with dims (I_0, ..., I_{N-1}) is a 1-D float64
@@ -49,48 +49,114 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def _load(path: str) -> ctypes.CDLL:
+    """Open an oracle shared library and declare its entry points."""
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    d = ctypes.c_double
+    i64 = ctypes.c_int64
+    ci = ctypes.c_int
+    pd = P(d)
+    ppd = P(pd)
+    pi64 = P(i64)
+    L.orc_mttkrp.argtypes = [ci, pi64, ci, pd, ppd, ci, pd, ci]
+    L.orc_mttkrp_rows.argtypes = [ci, pi64, ci, pd, ppd, ci, pi64, ci, pd, ci]
+    L.orc_gram.argtypes = [i64, ci, pd, pd]
+    L.orc_hadamard_except.argtypes = [ci, ci, ppd, ci, pd]
+    L.orc_sumsq.argtypes = [i64, pd]
+    L.orc_sumsq.restype = d
+    L.orc_update_mu.argtypes = [i64, ci, pd, pd, pd, d]
+    L.orc_update_hals.argtypes = [i64, ci, pd, pd, pd]
+    L.orc_normalize.argtypes = [i64, ci, pd, pd, pd]
+    L.orc_update_bpp.argtypes = [i64, ci, pd, pd, pd]
+    L.orc_update_bpp.restype = i64
+    L.orc_bpp_row.argtypes = [ci, pd, pd, pd, pd]
+    L.orc_bpp_row.restype = ci
+    L.orc_update_admm.argtypes = [i64, ci, pd, pd, pd, pd, ci, d]
+    L.orc_update_admm.restype = ci
+    L.orc_nes_params.argtypes = [ci, pd, ci, d, pd]
+    L.orc_nes_params.restype = ci
+    L.orc_update_nes.argtypes = [i64, ci, pd, pd, pd, ci, ci, d]
+    L.orc_update_nes.restype = ci
+    L.orc_nes_outer_candidate.argtypes = [ci, pi64, ci, pd, ppd, pd, ppd, pd, d, d, ppd, pd, ci]
+    L.orc_nes_outer_candidate.restype = d
+    L.orc_sweeps.argtypes = [ci, pi64, ci, pd, ppd, pd, ci, d, ci, pd, pd, ci]
+    L.orc_sweeps_from.argtypes = [ci, pi64, ci, pd, ppd, pd, ci, d, ci, i64, pd, pd, ci]
+    L.orc_residual.argtypes = [ci, pi64, ci, pd, ppd, pd, pd]
+    L.orc_residual.restype = d
+    L.orc_grad.argtypes = [ci, pi64, ci, pd, ppd, ppd, ci]
+    L.orc_grad.restype = d
+    L.orc_power_lmax.argtypes = [ci, pd, ci]
+    L.orc_power_lmax.restype = d
+    L.orc_pgd.argtypes = [ci, pi64, ci, pd, ppd, ci, d, ci, ci, pd, pd, ci]
+    L.orc_max_threads.restype = ci
+    return L
+
+
+# a different build of the same source (the sanitizer build) can be selected
+# for a whole process through this environment variable
+_ENV_LIB = "NNCP_ORACLE_LIB"
+
+
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
-        P = ctypes.POINTER
-        d = ctypes.c_double
-        i64 = ctypes.c_int64
-        ci = ctypes.c_int
-        pd = P(d)
-        ppd = P(pd)
-        pi64 = P(i64)
-        L.orc_mttkrp.argtypes = [ci, pi64, ci, pd, ppd, ci, pd, ci]
-        L.orc_mttkrp_rows.argtypes = [ci, pi64, ci, pd, ppd, ci, pi64, ci, pd, ci]
-        L.orc_gram.argtypes = [i64, ci, pd, pd]
-        L.orc_hadamard_except.argtypes = [ci, ci, ppd, ci, pd]
-        L.orc_sumsq.argtypes = [i64, pd]
-        L.orc_sumsq.restype = d
-        L.orc_update_mu.argtypes = [i64, ci, pd, pd, pd, d]
-        L.orc_update_hals.argtypes = [i64, ci, pd, pd, pd]
-        L.orc_normalize.argtypes = [i64, ci, pd, pd, pd]
-        L.orc_update_bpp.argtypes = [i64, ci, pd, pd, pd]
-        L.orc_update_bpp.restype = i64
-        L.orc_bpp_row.argtypes = [ci, pd, pd, pd, pd]
-        L.orc_bpp_row.restype = ci
-        L.orc_update_admm.argtypes = [i64, ci, pd, pd, pd, pd, ci, d]
-        L.orc_update_admm.restype = ci
-        L.orc_nes_params.argtypes = [ci, pd, ci, d, pd]
-        L.orc_nes_params.restype = ci
-        L.orc_update_nes.argtypes = [i64, ci, pd, pd, pd, ci, ci, d]
-        L.orc_update_nes.restype = ci
-        L.orc_sweeps.argtypes = [ci, pi64, ci, pd, ppd, pd, ci, d, ci, pd, pd, ci]
-        L.orc_residual.argtypes = [ci, pi64, ci, pd, ppd, pd, pd]
-        L.orc_residual.restype = d
-        L.orc_grad.argtypes = [ci, pi64, ci, pd, ppd, ppd, ci]
-        L.orc_grad.restype = d
-        L.orc_power_lmax.argtypes = [ci, pd, ci]
-        L.orc_power_lmax.restype = d
-        L.orc_pgd.argtypes = [ci, pi64, ci, pd, ppd, ci, d, ci, ci, pd, pd, ci]
-        L.orc_max_threads.restype = ci
-        _lib = L
+        path = os.environ.get(_ENV_LIB)
+        if not path:
+            path = build()
+        _lib = _load(path)
     return _lib
+
+
+SANITIZE_FLAGS = ("-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                  "-fno-omit-frame-pointer")
+
+
+def build_sanitized(out_path: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only; load it into a process started with libasan preloaded
+    and NNCP_ORACLE_LIB pointing at it)."""
+    return build_variant(out_path, extra_flags=SANITIZE_FLAGS)
+
+
+class using_library:
+    """Context manager: route every oracle call through another build of the
+    oracle source (the sanitizer build, or a deliberately altered copy that
+    the pin tests use to show that a planted mistake is caught)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _load(self.path)
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def build_variant(out_path: str, source: str | None = None, extra_flags=()) -> str:
+    """Compile the oracle (or the given replacement source text) into
+    out_path with extra compiler flags; returns out_path."""
+    src = _SRC
+    tmp_src = None
+    if source is not None:
+        tmp_src = out_path + ".c"
+        with open(tmp_src, "w") as f:
+            f.write(source)
+        src = tmp_src
+    subprocess.check_call(["gcc", "-O1", "-g", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                           *extra_flags, src, "-o", out_path, "-lm"])
+    return out_path
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
 
 
 def max_threads() -> int:
@@ -243,8 +309,11 @@ def normalize(Hhat):
     return H, lam
 
 
-def sweeps(X, factors, lam, algo: int, nsweeps: int, eps_mu: float = 1e-16, nthreads: int = 1):
-    """Run nsweeps outer iterations.  Returns (factors, lambda, relerr, relerr2_raw)."""
+def sweeps(X, factors, lam, algo: int, nsweeps: int, eps_mu: float = 1e-16, nthreads: int = 1,
+           first_sweep: int = 1):
+    """Run nsweeps outer iterations, the first being outer iteration
+    first_sweep (it sets s_i of the outer extrapolation).  Returns
+    (factors, lambda, relerr, relerr2_raw)."""
     dims = [f.shape[0] for f in factors]
     R = factors[0].shape[1]
     X = _f64(X).reshape(-1)
@@ -253,11 +322,31 @@ def sweeps(X, factors, lam, algo: int, nsweeps: int, eps_mu: float = 1e-16, nthr
     d, dp = _dims(dims)
     rel = np.zeros(nsweeps, dtype=np.float64)
     raw = np.zeros(nsweeps, dtype=np.float64)
-    rc = lib().orc_sweeps(len(dims), dp, R, _pd(X), _ptr_array(Hs), _pd(lam), algo,
-                          eps_mu, nsweeps, _pd(rel), _pd(raw), nthreads)
+    rc = lib().orc_sweeps_from(len(dims), dp, R, _pd(X), _ptr_array(Hs), _pd(lam), algo,
+                               eps_mu, nsweeps, int(first_sweep), _pd(rel), _pd(raw), nthreads)
     if rc != 0:
         raise ValueError(f"orc_sweeps failed ({rc})")
     return Hs, lam, rel, raw
+
+
+def nes_outer_candidate(X, factors, lam, prev_factors, prev_lam, si: float, nthreads: int = 1):
+    """Candidate of the outer extrapolation (Eq. eqn:nesouterupd) from the
+    iterate after a sweep and the one before it, with step si.  Returns
+    (normalised candidate factors, lambda_c, squared relative error)."""
+    dims = [f.shape[0] for f in factors]
+    R = factors[0].shape[1]
+    X = _f64(X).reshape(-1)
+    Hs = [_f64(f) for f in factors]
+    Hp = [_f64(f) for f in prev_factors]
+    lam = _f64(lam)
+    lamp = _f64(prev_lam)
+    Hc = [np.zeros_like(h) for h in Hs]
+    lamc = np.zeros(R)
+    d, dp = _dims(dims)
+    e2 = lib().orc_nes_outer_candidate(len(dims), dp, R, _pd(X), _ptr_array(Hs), _pd(lam),
+                                       _ptr_array(Hp), _pd(lamp), float(si), sumsq(X),
+                                       _ptr_array(Hc), _pd(lamc), nthreads)
+    return Hc, lamc, float(e2)
 
 
 def residual(X, factors, lam=None, want_tensor: bool = False):

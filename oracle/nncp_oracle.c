@@ -50,7 +50,9 @@
  *   - the outer extrapolation of Eq. (eqn:nesouterupd) (sweeps with
  *     ORC_NES_OUTER) acts on H^(n) for n < N-1 and H^(N-1) diag(lambda),
  *     clips the candidate at 0 and normalises it, uses s_i = i^(1/N) with
- *     i the sweep number from 1, and compares squared relative errors;
+ *     i the outer-iteration number (1 for the first sweep from a fresh
+ *     start; a caller continuing an earlier run passes its next number),
+ *     and compares squared relative errors;
  *   - the squared relative error is clamped at 0 before the square root.
  *
  * Layouts: the tensor is stored with mode 0 varying fastest (the local
@@ -610,6 +612,60 @@ enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3, ORC_NES = 4, ORC_NES
 #define ORC_NES_KAPPA 100.0
 
 /*
+ * The candidate of the outer extrapolation, Eq. (eqn:nesouterupd), from the
+ * iterate after a sweep (H, lambda) and the iterate before it (Hp, lamp),
+ * with step s_i: on F^(n) = H^(n) for n < N-1 and F^(N-1) = H^(N-1)
+ * diag(lambda) (the same model with one set of weights),
+ *   Fc^(n) = max(0, F^(n) + s_i (F^(n) - F_prev^(n))),
+ * each Fc^(n) normalised into Hc[n] with its column norms multiplied into
+ * lamc (so [[lamc; Hc]] = [[Fc]]).  Returns the candidate's squared relative
+ * error through the identity of the appendix (one MTTKRP of mode N-1 and the
+ * Grams of the candidate), alpha = ||X||^2.
+ */
+double orc_nes_outer_candidate(int N, const int64_t *dims, int R, const double *X,
+                               const double *const *H, const double *lambda,
+                               const double *const *Hp, const double *lamp, double si,
+                               double alpha, double *const *Hc, double *lamc, int nthreads) {
+  int64_t maxI = 0;
+  for (int k = 0; k < N; ++k)
+    if (dims[k] > maxI) maxI = dims[k];
+  double *nrm = (double *)malloc(sizeof(double) * (size_t)R);
+  double *Gc[ORC_MAXN];
+  for (int r = 0; r < R; ++r) lamc[r] = 1.0;
+  for (int k = 0; k < N; ++k) {
+    const int last = k == N - 1;
+    for (int64_t i = 0; i < dims[k]; ++i)
+      for (int r = 0; r < R; ++r) {
+        const double f = H[k][i * R + r] * (last ? lambda[r] : 1.0);
+        const double fp = Hp[k][i * R + r] * (last ? lamp[r] : 1.0);
+        const double v = f + si * (f - fp);
+        Hc[k][i * R + r] = v > 0.0 ? v : 0.0;
+      }
+    orc_normalize(dims[k], R, Hc[k], Hc[k], nrm);
+    for (int r = 0; r < R; ++r) lamc[r] *= nrm[r];
+    Gc[k] = (double *)malloc(sizeof(double) * (size_t)R * R);
+    orc_gram(dims[k], R, Hc[k], Gc[k]);
+  }
+  const int n = N - 1;
+  const int64_t In = dims[n];
+  double *M = (double *)malloc(sizeof(double) * (size_t)(maxI * R));
+  orc_mttkrp(N, dims, R, X, (const double *const *)Hc, n, M, nthreads);
+  double bc = 0.0, gc = 0.0;
+  for (int64_t i = 0; i < In; ++i)
+    for (int r = 0; r < R; ++r) bc += M[i * R + r] * Hc[n][i * R + r] * lamc[r];
+  for (int a = 0; a < R; ++a)
+    for (int b = 0; b < R; ++b) {
+      double p = 1.0;
+      for (int k = 0; k < N; ++k) p *= Gc[k][a * R + b];
+      gc += lamc[a] * p * lamc[b];
+    }
+  for (int k = 0; k < N; ++k) free(Gc[k]);
+  free(M);
+  free(nrm);
+  return (alpha - 2.0 * bc + gc) / alpha;
+}
+
+/*
  * nsweeps outer iterations of Algorithm 1 with the local steps of
  * Algorithm 4 (normalisation and relative error).  H[n] (I_n x R) and
  * lambda (R) are the start iterate on entry and the result on exit.
@@ -617,12 +673,14 @@ enum { ORC_MU = 0, ORC_HALS = 1, ORC_BPP = 2, ORC_ADMM = 3, ORC_NES = 4, ORC_NES
  * Nesterov-type updates plus the outer extrapolation after every sweep).
  * relerr[s] receives the relative error after sweep s from the identity;
  * relerr2_raw[s] (may be NULL) the unclamped squared relative error.
+ * first_sweep is the outer-iteration number i of the first of these sweeps
+ * (1 for a fresh start); only the outer extrapolation uses it.
  * Returns 0, or a negative value on bad arguments.
  */
-int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const *H,
-               double *lambda, int algo, double eps_mu, int nsweeps,
-               double *relerr, double *relerr2_raw, int nthreads) {
-  if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0) return -1;
+int orc_sweeps_from(int N, const int64_t *dims, int R, const double *X, double *const *H,
+                    double *lambda, int algo, double eps_mu, int nsweeps, int64_t first_sweep,
+                    double *relerr, double *relerr2_raw, int nthreads) {
+  if (N < 2 || N > ORC_MAXN || R < 1 || nsweeps < 0 || first_sweep < 1) return -1;
   if (algo < ORC_MU || algo > ORC_NES_OUTER) return -1;
   const int64_t I = prod_dims(N, dims);
   double *G[ORC_MAXN];
@@ -642,13 +700,12 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
   const double alpha = orc_sumsq(I, X);
   /* outer extrapolation: the iterate before the sweep and the candidate */
   const int outer = algo == ORC_NES_OUTER;
-  double *Hp[ORC_MAXN], *Hc[ORC_MAXN], *Gc[ORC_MAXN];
+  double *Hp[ORC_MAXN], *Hc[ORC_MAXN];
   double *lamp = (double *)malloc(sizeof(double) * (size_t)R);
   double *lamc = (double *)malloc(sizeof(double) * (size_t)R);
   for (int k = 0; k < N; ++k) {
     Hp[k] = outer ? (double *)malloc(sizeof(double) * (size_t)(dims[k] * R)) : NULL;
     Hc[k] = outer ? (double *)malloc(sizeof(double) * (size_t)(dims[k] * R)) : NULL;
-    Gc[k] = outer ? (double *)malloc(sizeof(double) * (size_t)R * R) : NULL;
   }
 
   for (int s = 0; s < nsweeps; ++s) {
@@ -685,45 +742,16 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
     }
     double e2 = (alpha - 2.0 * beta + gamma) / alpha;
     if (outer) {
-      /* Eq. (eqn:nesouterupd) on F^(n) = H^(n) (n < N-1) and
-       * F^(N-1) = H^(N-1) diag(lambda): Fc = max(0, F + s_i (F - F_prev)),
-       * s_i = i^(1/N) for sweep i = s + 1; each Fc^(n) is normalised, the
-       * column norms multiply into lambda_c; the candidate replaces the
-       * iterate when its squared relative error is lower. */
-      const double si = pow((double)(s + 1), 1.0 / N);
-      for (int r = 0; r < R; ++r) lamc[r] = 1.0;
-      for (int k = 0; k < N; ++k) {
-        const int last = k == N - 1;
-        for (int64_t i = 0; i < dims[k]; ++i)
-          for (int r = 0; r < R; ++r) {
-            const double f = H[k][i * R + r] * (last ? lambda[r] : 1.0);
-            const double fp = Hp[k][i * R + r] * (last ? lamp[r] : 1.0);
-            const double v = f + si * (f - fp);
-            Hc[k][i * R + r] = v > 0.0 ? v : 0.0;
-          }
-        double *nrm = (double *)malloc(sizeof(double) * (size_t)R);
-        orc_normalize(dims[k], R, Hc[k], Hc[k], nrm);
-        for (int r = 0; r < R; ++r) lamc[r] *= nrm[r];
-        free(nrm);
-        orc_gram(dims[k], R, Hc[k], Gc[k]);
-      }
-      const int n = N - 1;
-      const int64_t In = dims[n];
-      orc_mttkrp(N, dims, R, X, (const double *const *)Hc, n, M, nthreads);
-      double bc = 0.0, gc = 0.0;
-      for (int64_t i = 0; i < In; ++i)
-        for (int r = 0; r < R; ++r) bc += M[i * R + r] * Hc[n][i * R + r] * lamc[r];
-      for (int a = 0; a < R; ++a)
-        for (int b = 0; b < R; ++b) {
-          double p = 1.0;
-          for (int k = 0; k < N; ++k) p *= Gc[k][a * R + b];
-          gc += lamc[a] * p * lamc[b];
-        }
-      const double e2c = (alpha - 2.0 * bc + gc) / alpha;
+      /* s_i = i^(1/N) for outer iteration i; the candidate replaces the
+       * iterate (and its Grams) when its squared relative error is lower */
+      const double si = pow((double)(first_sweep + s), 1.0 / N);
+      const double e2c = orc_nes_outer_candidate(N, dims, R, X, (const double *const *)H, lambda,
+                                                 (const double *const *)Hp, lamp, si, alpha, Hc,
+                                                 lamc, nthreads);
       if (e2c < e2) {
         for (int k = 0; k < N; ++k) {
           memcpy(H[k], Hc[k], sizeof(double) * (size_t)(dims[k] * R));
-          memcpy(G[k], Gc[k], sizeof(double) * (size_t)R * R);
+          orc_gram(dims[k], R, H[k], G[k]);
         }
         memcpy(lambda, lamc, sizeof(double) * (size_t)R);
         e2 = e2c;
@@ -735,7 +763,6 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
   for (int k = 0; k < N; ++k) {
     free(Hp[k]);
     free(Hc[k]);
-    free(Gc[k]);
   }
   free(lamp);
   free(lamc);
@@ -747,6 +774,14 @@ int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const
   free(Hhat);
   free(S);
   return 0;
+}
+
+/* orc_sweeps_from from a fresh start (outer iteration 1) */
+int orc_sweeps(int N, const int64_t *dims, int R, const double *X, double *const *H,
+               double *lambda, int algo, double eps_mu, int nsweeps,
+               double *relerr, double *relerr2_raw, int nthreads) {
+  return orc_sweeps_from(N, dims, R, X, H, lambda, algo, eps_mu, nsweeps, 1, relerr, relerr2_raw,
+                         nthreads);
 }
 
 /* ------------------------------------------------------------------ */

@@ -241,19 +241,81 @@ def nncp_timers_read(ctx):
 # convenience: a context that owns references to its torch buffers
 # ---------------------------------------------------------------------------
 
+def _need(t, name, shape, dtype, device):
+    """Raise ValueError unless t is a contiguous tensor of this shape, dtype
+    and device (checked on the host, before anything is launched: the C ABI
+    only sees pointers, so a wrong size would become an out-of-bounds access)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _factor_dtype(x_dtype):
+    return torch.float64 if x_dtype == torch.float64 else torch.float32
+
+
+def check_problem(X, factors, lam=None):
+    """Check a tensor, its factors and lambda against each other (shapes,
+    dtypes, one device, contiguity) and return (dims, R); raises ValueError.
+    Runs on the host before anything is launched."""
+    if not isinstance(X, torch.Tensor):
+        raise ValueError("X must be a torch tensor")
+    if X.dtype not in _DT:
+        raise ValueError(f"X has unsupported dtype {X.dtype}")
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous")
+    factors = list(factors)
+    if not 2 <= len(factors) <= NNCP_MAX_MODES:
+        raise ValueError(f"need 2..{NNCP_MAX_MODES} factors, got {len(factors)}")
+    for n, f in enumerate(factors):
+        if not isinstance(f, torch.Tensor) or f.dim() != 2:
+            raise ValueError(f"factor {n} must be a 2-D tensor")
+    dims = [int(f.shape[0]) for f in factors]
+    R = int(factors[0].shape[1])
+    hdt = _factor_dtype(X.dtype)
+    for n, f in enumerate(factors):
+        _need(f, f"factor {n}", (dims[n], R), hdt, X.device)
+    total = 1
+    for d in dims:
+        total *= d
+    if X.numel() != total:
+        raise ValueError(f"X has {X.numel()} entries, the factors need {total}")
+    if X.dim() > 1 and tuple(X.shape) != tuple(dims[::-1]):
+        raise ValueError(f"X has shape {tuple(X.shape)}, expected {tuple(dims[::-1])} "
+                         "(mode 0 fastest) or a flat tensor")
+    if lam is not None and (not isinstance(lam, torch.Tensor) or lam.numel() != R):
+        raise ValueError(f"lam must be a tensor of {R} entries")
+    return dims, R
+
+
 class Context:
     """Holds X, the factors, lambda and the workspace (torch tensors on one
-    GPU) for an nncp context.  Factors are updated in place."""
+    GPU) for an nncp context.  Factors are updated in place.
+
+    X is a contiguous GPU tensor of shape (I_{N-1}, ..., I_0) or flat with
+    prod(I) entries (float64, float32, bfloat16 or float16); the factors are
+    contiguous (I_n, R) tensors on the same GPU, float64 for a float64 X and
+    float32 otherwise; lam has R entries.  Shapes, dtypes and devices are
+    checked here and in every method before the library is called."""
 
     def __init__(self, X, factors, lam=None, *, split=0, krp_split=1, generic=0, eps_mu=1e-16,
                  graphs=1):
-        if not X.is_cuda:
+        if not isinstance(X, torch.Tensor) or not X.is_cuda:
             raise ValueError("X must be a GPU tensor")
-        self.dims = [int(f.shape[0]) for f in factors]
-        self.R = int(factors[0].shape[1])
-        self.X = X.contiguous()
-        self.factors = [f.contiguous() for f in factors]
+        dims, R = check_problem(X, factors, lam)
+        factors = list(factors)
         dev = X.device
+        self.dims = dims
+        self.R = R
+        self.X = X
+        self.factors = factors
         self.lam = (lam.to(device=dev, dtype=torch.float64).contiguous() if lam is not None
                     else torch.ones(self.R, dtype=torch.float64, device=dev))
         self.opts = dict(split=split, krp_split=krp_split, generic=generic, eps_mu=eps_mu,
@@ -278,15 +340,36 @@ class Context:
     def gemm_path(self, side: int) -> int:
         return nncp_gemm_path(self.ctx, side)
 
+    def _mode(self, mode):
+        if not 0 <= int(mode) < self.N:
+            raise ValueError(f"mode {mode} outside [0, {self.N})")
+        return int(mode)
+
+    def _check_factors(self, factors, what="factor"):
+        factors = list(factors)
+        if len(factors) != self.N:
+            raise ValueError(f"need {self.N} {what}s, got {len(factors)}")
+        for n, f in enumerate(factors):
+            _need(f, f"{what} {n}", (self.dims[n], self.R), self.hdtype, self.X.device)
+        return factors
+
     def set_factors(self, factors, lam=None):
-        self.factors = [f.contiguous() for f in factors]
+        factors = self._check_factors(factors)
         if lam is not None:
-            self.lam = lam.contiguous()
+            _need(lam, "lam", (self.R,), torch.float64, self.X.device)
+        self.factors = factors
+        if lam is not None:
+            self.lam = lam
         nncp_set_factors(self.ctx, self.factors, self.lam if lam is not None else None)
 
     def mttkrp(self, mode: int, out=None):
-        M = out if out is not None else torch.empty(self.dims[mode], self.R, dtype=self.hdtype,
-                                                    device=self.X.device)
+        mode = self._mode(mode)
+        shape = (self.dims[mode], self.R)
+        if out is None:
+            M = torch.empty(*shape, dtype=self.hdtype, device=self.X.device)
+        else:
+            _need(out, "out", shape, self.hdtype, self.X.device)
+            M = out
         nncp_mttkrp(self.ctx, mode, M)
         return M
 
@@ -301,6 +384,9 @@ class Context:
         return S
 
     def update(self, algo: int, mode: int, M, S, eps: float = -1.0):
+        mode = self._mode(mode)
+        _need(M, "M", (self.dims[mode], self.R), self.hdtype, self.X.device)
+        _need(S, "S", (self.R, self.R), torch.float64, self.X.device)
         if algo == NNCP_MU:
             nncp_update_mu(self.ctx, mode, M, S, eps)
         elif algo == NNCP_BPP:
@@ -317,13 +403,24 @@ class Context:
         nncp_cp_loss(self.ctx, out[0:1], out[1:2])
         return out
 
+    def _check_hist(self, relerr_hist, nsweeps):
+        if relerr_hist is None:
+            return
+        if (not isinstance(relerr_hist, torch.Tensor) or relerr_hist.dtype != torch.float64
+                or relerr_hist.device != self.X.device or not relerr_hist.is_contiguous()
+                or relerr_hist.numel() < nsweeps):
+            raise ValueError(f"relerr_hist must be a contiguous float64 tensor on {self.X.device} "
+                             f"with at least {nsweeps} entries")
+
     def sweep(self, algo: int, nsweeps: int, relerr_hist=None):
         if relerr_hist is None:
             relerr_hist = torch.empty(max(1, nsweeps), dtype=torch.float64, device=self.X.device)
+        self._check_hist(relerr_hist, nsweeps)
         nncp_sweep(self.ctx, algo, nsweeps, relerr_hist)
         return relerr_hist
 
     def capture(self, algo: int, nsweeps: int, relerr_hist):
+        self._check_hist(relerr_hist, nsweeps)
         nncp_sweep_capture(self.ctx, algo, nsweeps, relerr_hist)
 
     def refresh_grams(self):
@@ -335,8 +432,10 @@ class Context:
     def grad(self, grads=None, loss=None):
         if grads is None:
             grads = [torch.empty_like(f) for f in self.factors]
+        grads = self._check_factors(grads, "gradient")
         if loss is None:
             loss = torch.empty(1, dtype=torch.float64, device=self.X.device)
+        _need(loss, "loss", (1,), torch.float64, self.X.device)
         nncp_grad(self.ctx, grads, loss)
         return grads, loss
 
@@ -370,6 +469,7 @@ class CPLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(fctx, ctx: Context, *factors):
+        # set_factors checks every factor against the context's shapes
         ctx.set_factors([f.detach() for f in factors])
         grads = [torch.empty_like(f) for f in factors]
         loss = torch.empty(1, dtype=torch.float64, device=factors[0].device)

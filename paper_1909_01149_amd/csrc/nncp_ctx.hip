@@ -31,6 +31,9 @@ int fail(int code, const char *fmt, ...) {
 }
 
 const int kMagic = 0x4E4E4350;  // "NNCP"
+// index into the context's scalar block of the count of outer extrapolation
+// steps (NNCP_NES_OUTER sweeps) since init / set_factors
+const int kOuterCount = 62;
 const size_t kAlign = 256;
 const size_t kLdsMax = 64 * 1024;
 
@@ -616,18 +619,16 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
       og += hs * L.dims[n] * R;
     }
   }
-  // ones (for lambda-free losses), Grams, alpha
+  // ones (for lambda-free losses), the ADMM duals and the count of outer
+  // extrapolation steps (both start at zero), Grams, alpha: all by kernels on
+  // the stream, so that nothing here waits for the device
   {
-    double onesh[256];
-    for (int r = 0; r < R; ++r) onesh[r] = 1.0;
-    hipError_t e = hipMemcpyAsync(c->ones, onesh, sizeof(double) * R, hipMemcpyHostToDevice, c->st);
-    // ADMM duals start at zero
-    if (e == hipSuccess && R <= 64)
-      e = hipMemsetAsync(c->admmU, 0, sizeof(double) * L.sumI * R, c->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipError_t e = launch_fill(c->ones, 1.0, R, c->st);
+    if (e == hipSuccess && R <= 64) e = launch_fill(c->admmU, 0.0, L.sumI * R, c->st);
+    if (e == hipSuccess) e = launch_fill(c->scal + kOuterCount, 0.0, 1, c->st);
     if (e != hipSuccess) {
       delete c;
-      return fail(NNCP_E_HIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+      return fail(NNCP_E_HIP, "fill: %s", hipGetErrorString(e));
     }
   }
   FactorSet F = factors_of(c, c->H);
@@ -654,9 +655,10 @@ int nncp_set_factors(nncp_ctx *c, void *const *H, double *lambda) {
   for (int n = 0; n < c->L.N; ++n) c->H[n] = H[n];
   if (lambda) c->lambda = lambda;
   ++c->binding;
-  // a new start point: the ADMM duals start again from zero
-  if (c->L.R <= 64)
-    HIPCHK(hipMemsetAsync(c->admmU, 0, sizeof(double) * c->L.sumI * c->L.R, c->st));
+  // a new start point: the ADMM duals and the outer-step count start again
+  // from zero
+  if (c->L.R <= 64) HIPCHK(launch_fill(c->admmU, 0.0, c->L.sumI * c->L.R, c->st));
+  HIPCHK(launch_fill(c->scal + kOuterCount, 0.0, 1, c->st));
   return refresh_grams(c, factors_of(c, c->H), c->G);
 }
 
@@ -755,21 +757,23 @@ int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
 // (Section 4.3.5, Eq. eqn:nesouterupd), on F^(n) = H^(n) (n < N-1) and
 // F^(N-1) = H^(N-1) diag(lambda) with the iterate saved before the sweep
 // (c->pgdG, lambda in c->outer): candidate max(0, F + s_i (F - F_prev)),
-// s_i = (s+1)^(1/N), normalised into c->pgdH with its Grams in c->Gt and
+// s_i = i^(1/N) with i the outer iteration (the device count of outer steps
+// taken since init / set_factors, plus one), normalised into c->pgdH with its
+// Grams in c->Gt and
 // lambda_c the product of the column norms; its error from the identity
 // (an extra MTTKRP of mode N-1); taken when its squared relative error is
 // lower than the sweep's (c->scal[2]).  All on the stream, no host decision.
-static int nes_outer_step(nncp_ctx *c, int s, double *hist) {
+static int nes_outer_step(nncp_ctx *c, double *hist) {
   const Layout &L = c->L;
   const int N = L.N, R = L.R;
   const size_t hs = xsize(L.hdt);
   double *lamp = c->outer, *lamc = c->outer + R, *cand = c->outer + 2 * R;
   double *lamk = c->outer + 2 * R + 16;
-  const double si = pow((double)(s + 1), 1.0 / N);
+  double *count = c->scal + kOuterCount;
   for (int k = 0; k < N; ++k) {
     int nb = 0;
-    TIMED(4, launch_nes_extrap(L.hdt, c->H[k], c->pgdG[k], c->lambda, lamp, k == N - 1, si,
-                               L.dims[k], R, c->hhat, c->upart, &nb, c->st));
+    TIMED(4, launch_nes_extrap(L.hdt, c->H[k], c->pgdG[k], c->lambda, lamp, k == N - 1, count,
+                               N, L.dims[k], R, c->hhat, c->upart, &nb, c->st));
     UpdateArgs a{};
     a.algo = NNCP_NES;
     a.I = L.dims[k];
@@ -794,7 +798,7 @@ static int nes_outer_step(nncp_ctx *c, int s, double *hist) {
     TIMED(4, launch_norm_only(L.hdt, a, nb, c->st, &job));
     TIMED(4, launch_gram_finish(job, c->st));
   }
-  TIMED(4, launch_nes_lamc(lamk, N, R, lamc, c->st));
+  TIMED(4, launch_nes_lamc(lamk, N, R, lamc, count, c->st));
   const FactorSet Fc = factors_of(c, c->pgdH);
   int rc = mttkrp_tree(c, Fc, N - 1, c->M, true);
   if (rc) return rc;
@@ -845,7 +849,7 @@ static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_his
     }
     if (outer) {
       HIPCHK(flush_gram(c));
-      int rc = nes_outer_step(c, s, relerr_hist ? relerr_hist + s : nullptr);
+      int rc = nes_outer_step(c, relerr_hist ? relerr_hist + s : nullptr);
       if (rc) return rc;
     }
   }

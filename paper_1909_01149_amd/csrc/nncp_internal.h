@@ -314,11 +314,16 @@ hipError_t launch_norm_only(int hdt, const UpdateArgs &a, int nblocks, hipStream
 // Outer extrapolation of the Nesterov-type sweeps (Eq. eqn:nesouterupd)
 hipError_t launch_copy(size_t elem_bytes, const void *src, void *dst, int64_t n, hipStream_t st);
 // raw = max(0, F + s (F - F_prev)), F = H (times lambda if last), FP64, with
-// per-4-row column sums of squares in part; *nblocks receives their count
+// s = (count[0] + 1)^(1/N) and per-4-row column sums of squares in part;
+// *nblocks receives their count
 hipError_t launch_nes_extrap(int hdt, const void *H, const void *Hp, const double *lam,
-                             const double *lamp, int last, double s, int64_t I, int R, double *raw,
-                             double *part, int *nblocks, hipStream_t st);
-hipError_t launch_nes_lamc(const double *lamk, int N, int R, double *lamc, hipStream_t st);
+                             const double *lamp, int last, const double *count, int N, int64_t I,
+                             int R, double *raw, double *part, int *nblocks, hipStream_t st);
+// lamc = product of the per-mode column norms; count[0] += 1
+hipError_t launch_nes_lamc(const double *lamk, int N, int R, double *lamc, double *count,
+                           hipStream_t st);
+// p[0 .. n) = v (a kernel, so that it can sit in a captured graph)
+hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st);
 // dst = src when cand_e2 < cur_e2 (device scalars)
 hipError_t launch_nes_accept(size_t elem_bytes, const void *src, void *dst, int64_t n,
                              const double *cand_e2, const double *cur_e2, hipStream_t st);

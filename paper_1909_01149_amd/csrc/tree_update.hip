@@ -1,7 +1,7 @@
 // Dimension-tree multi-TTVs (Section 4.2, Algorithm 3 multi-TTV lines), Gram
 // and Hadamard products (Algorithm 1), the per-mode factor update with
 // column normalisation and the relative-error identity (Eqs. eqn:muupd,
-// eqn:halsupd; Appendix A, Algorithm 4), the loss, the gradient of the loss
+// eqn:halsupd; Appendix B, Algorithm 4), the loss, the gradient of the loss
 // and the projected-gradient helpers.
 //
 // Node layout (as in the paper's Figure 3): a node T over modes a..b is
@@ -1756,13 +1756,16 @@ __global__ __launch_bounds__(256) void k_nes_extrap(const HT *__restrict__ H,
                                                     const HT *__restrict__ Hp,
                                                     const double *__restrict__ lam,
                                                     const double *__restrict__ lamp, int last,
-                                                    double s, int64_t I, int R,
+                                                    const double *__restrict__ count, double invN,
+                                                    int64_t I, int R,
                                                     double *__restrict__ raw,
                                                     double *__restrict__ part) {
   __shared__ double wred[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   const bool ok = i < I && lane < R;
+  // s_i = i^(1/N) for outer iteration i = (outer steps taken so far) + 1
+  const double s = pow(count[0] + 1.0, invN);
   double sq = 0.0;
   if (ok) {
     const double f = (double)H[i * R + lane] * (last ? lam[lane] : 1.0);
@@ -1781,10 +1784,13 @@ __global__ __launch_bounds__(256) void k_nes_extrap(const HT *__restrict__ H,
   if (threadIdx.x == 0) cpart[R] = 0.0;
 }
 
-// lambda_c(r) = prod over modes of the candidate's column norms, in mode order
+// lambda_c(r) = prod over modes of the candidate's column norms, in mode order;
+// also counts the outer step (every extrapolation kernel of this step has run)
 __global__ __launch_bounds__(64) void k_nes_lamc(const double *__restrict__ lamk, int N, int R,
-                                                 double *__restrict__ lamc) {
+                                                 double *__restrict__ lamc,
+                                                 double *__restrict__ count) {
   const int r = threadIdx.x;
+  if (r == 0) count[0] += 1.0;
   if (r >= R) return;
   double p = 1.0;
   for (int k = 0; k < N; ++k) p *= lamk[(int64_t)k * R + r];
@@ -1818,22 +1824,36 @@ hipError_t launch_copy(size_t elem_bytes, const void *src, void *dst, int64_t n,
 }
 
 hipError_t launch_nes_extrap(int hdt, const void *H, const void *Hp, const double *lam,
-                             const double *lamp, int last, double s, int64_t I, int R, double *raw,
-                             double *part, int *nblocks, hipStream_t st) {
+                             const double *lamp, int last, const double *count, int N, int64_t I,
+                             int R, double *raw, double *part, int *nblocks, hipStream_t st) {
   if (R > 64) return hipErrorInvalidValue;
   const int nb = (int)((I + 3) / 4);
   *nblocks = nb;
+  const double invN = 1.0 / N;
   if (hdt == NNCP_F64)
     hipLaunchKernelGGL(k_nes_extrap<double>, dim3(nb), dim3(256), 0, st, (const double *)H,
-                       (const double *)Hp, lam, lamp, last, s, I, R, raw, part);
+                       (const double *)Hp, lam, lamp, last, count, invN, I, R, raw, part);
   else
     hipLaunchKernelGGL(k_nes_extrap<float>, dim3(nb), dim3(256), 0, st, (const float *)H,
-                       (const float *)Hp, lam, lamp, last, s, I, R, raw, part);
+                       (const float *)Hp, lam, lamp, last, count, invN, I, R, raw, part);
   return hipGetLastError();
 }
 
-hipError_t launch_nes_lamc(const double *lamk, int N, int R, double *lamc, hipStream_t st) {
-  hipLaunchKernelGGL(k_nes_lamc, dim3(1), dim3(64), 0, st, lamk, N, R, lamc);
+hipError_t launch_nes_lamc(const double *lamk, int N, int R, double *lamc, double *count,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_nes_lamc, dim3(1), dim3(64), 0, st, lamk, N, R, lamc, count);
+  return hipGetLastError();
+}
+
+// p[0 .. n) = v
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ p, double v, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
   return hipGetLastError();
 }
 

@@ -110,3 +110,33 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode != 0
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_binding_checks_shapes_before_any_call(B):
+    """The binding compares X, the factors and lambda on the host (the C ABI
+    sees only pointers, so a mismatch would otherwise become an out-of-bounds
+    access on the device)."""
+    import torch
+    dims, R = [4, 3, 5], 2
+    X = torch.rand(5, 3, 4)
+    H = [torch.rand(d, R) for d in dims]
+    assert B.check_problem(X, H) == (dims, R)
+    assert B.check_problem(X.reshape(-1), H, torch.ones(R)) == (dims, R)
+    bad = [
+        (X.reshape(4, 3, 5), H, None),                      # shape not (I_2, I_1, I_0)
+        (X[:4], [torch.rand(d, R) for d in dims], None),    # too few entries
+        (X.transpose(0, 2), H, None),                       # not contiguous
+        (X.to(torch.int32), H, None),                       # unsupported dtype
+        (X, [H[0], H[1], torch.rand(5, R + 1)], None),      # ranks differ
+        (X, [H[0], H[1].double(), H[2]], None),             # factor dtype
+        (X.double(), H, None),                              # FP64 tensor needs FP64 factors
+        (X, [h.t().contiguous().t() for h in H], None),     # non-contiguous factors
+        (X, H, torch.ones(R + 1)),                          # lambda length
+        (X, H[:1], None),                                   # one factor
+        (X, [h.reshape(-1) for h in H], None),              # not 2-D
+    ]
+    for Xb, Hb, lb in bad:
+        with pytest.raises(ValueError):
+            B.check_problem(Xb, Hb, lb)
+    with pytest.raises(ValueError):
+        B.Context(X, H)                                     # host tensor: not a GPU tensor

@@ -230,3 +230,28 @@ def test_nes_outer_graph_replay_matches_eager(nn):
         assert torch.equal(cg.lam, ce.lam), rep
     cg.close()
     ce.close()
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_nes_outer_iteration_count_continues_across_calls(nn, graphs):
+    """The outer iteration i of s_i = i^(1/N) is counted on the device from
+    nncp_init / nncp_set_factors, so two calls continue one run (the oracle
+    is told the first iteration number of its second call)."""
+    banner("nes outer count", graphs)
+    dims, R = [12, 10, 14], 4
+    X64, H64 = gen.small_lowrank(dims, R, R, 81, noise=0.03)
+    X, H, Xo, Ho = prepare(X64, H64, "f64")
+    ctx = nn.Context(X, [h.clone() for h in H], graphs=graphs)
+    r1 = ctx.sweep(nn.NNCP_NES_OUTER, 3).cpu().numpy()
+    r2 = ctx.sweep(nn.NNCP_NES_OUTER, 5).cpu().numpy()
+    Ha, la, ra, _ = oracle.sweeps(Xo, Ho, np.ones(R), oracle.NES_OUTER, 3)
+    Hb, lb, rb, _ = oracle.sweeps(Xo, Ha, la, oracle.NES_OUTER, 5, first_sweep=4)
+    np.testing.assert_allclose(np.concatenate([r1, r2]), np.concatenate([ra, rb]), rtol=1e-9,
+                               atol=1e-12)
+    for x, y in zip(ctx.factors, Hb):
+        assert relerr(x.cpu().numpy(), y) <= 1e-9
+    # new factors: the count starts again from 1
+    ctx.set_factors([h.clone() for h in H], torch.ones(R, dtype=torch.float64, device="cuda"))
+    r3 = ctx.sweep(nn.NNCP_NES_OUTER, 3).cpu().numpy()
+    np.testing.assert_allclose(r3, ra, rtol=1e-9, atol=1e-12)
+    ctx.close()
