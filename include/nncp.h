@@ -153,6 +153,35 @@ int nncp_set_factors(nncp_ctx *ctx, void *const *H, double *lambda);
  */
 int nncp_mttkrp(nncp_ctx *ctx, int mode, void *M);
 
+/*
+ * nncp_mttkrp without a context or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Computes the same M^(n) with the same
+ * kernels, grids and summation order as nncp_mttkrp on a context of the same
+ * problem and options (so the two agree bitwise), from the root of n's
+ * subtree.  The dimension-tree temporaries (Khatri-Rao operands, nodes,
+ * split partials) live in a library-owned device array of
+ * NNCP_NOALLOC_SCRATCH_BYTES, one per GPU, held from the first call on that
+ * GPU until the process ends; nothing in it needs to start at zero, and it
+ * keeps the last call's contents.  The call allocates nothing.
+ *   N, dims, R, x_dtype, h_dtype, opt   as for nncp_init (opt may be NULL)
+ *   X      tensor (layout above), read only
+ *   H      host array of N device pointers to the factors, read only
+ *   mode   0 .. N-1
+ *   M      output, I_mode x R row-major, h_dtype
+ *   stream hipStream_t of the current device (NULL: the default stream)
+ * Returns NNCP_E_WORKSPACE when the temporaries of this problem exceed
+ * NNCP_NOALLOC_SCRATCH_BYTES (nothing is launched), NNCP_E_INVAL when the
+ * stream belongs to another device.  Calls on one GPU share its array, so
+ * calls whose launches overlap on that GPU (on different streams, or from
+ * different threads) race; calls that follow one another on one stream do
+ * not.
+ */
+#define NNCP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nncp_mttkrp_noalloc(int N, const int64_t *dims, int R, int x_dtype, const void *X,
+                        int h_dtype, void *const *H, int mode, void *M, void *stream,
+                        const nncp_options *opt);
+
 /* G^(n) = H^(n)^T H^(n) (R x R, FP64, row-major) of the current factor; also
  * refreshes the context's copy used for S^(n). */
 int nncp_gram(nncp_ctx *ctx, int mode, double *G);

@@ -10,5 +10,6 @@ from .binding import (  # noqa: F401
     EXPORTS, LIB_PATH, check_problem, lib, nncp_cp_loss, nncp_destroy, nncp_gemm_path, nncp_grad, nncp_gram,
     nncp_hadamard, nncp_init, nncp_mttkrp, nncp_pgd, nncp_set_factors, nncp_split, nncp_sweep,
     nncp_update_hals, nncp_update_mu, nncp_workspace_size, nncp_timers_enable, nncp_timers_read,
-    nncp_sweep_capture, nncp_update_bpp, nncp_update_admm, nncp_update_nes,
+    nncp_sweep_capture, nncp_update_bpp, nncp_update_admm, nncp_update_nes, nncp_mttkrp_noalloc,
+    NNCP_NOALLOC_SCRATCH_BYTES,
 )

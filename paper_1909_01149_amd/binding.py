@@ -33,8 +33,9 @@ EXPORTS = [
     "nncp_hadamard", "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep",
     "nncp_grad", "nncp_pgd", "nncp_destroy", "nncp_last_error", "nncp_split",
     "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read", "nncp_sweep_capture",
-    "nncp_update_bpp", "nncp_update_admm", "nncp_update_nes",
+    "nncp_update_bpp", "nncp_update_admm", "nncp_update_nes", "nncp_mttkrp_noalloc",
 ]
+NNCP_NOALLOC_SCRATCH_BYTES = 64 << 20
 NNCP_TIMER_CATEGORIES = 5
 
 _DT = {torch.float64: NNCP_F64, torch.float32: NNCP_F32, torch.bfloat16: NNCP_BF16,
@@ -73,6 +74,8 @@ def lib() -> ctypes.CDLL:
                             ctypes.c_size_t, vp, optp]
     L.nncp_set_factors.argtypes = [vp, ctypes.POINTER(vp), dp]
     L.nncp_mttkrp.argtypes = [vp, ci, vp]
+    L.nncp_mttkrp_noalloc.argtypes = [ci, i64p, ci, ci, vp, ci, ctypes.POINTER(vp), ci, vp, vp,
+                                      optp]
     L.nncp_gram.argtypes = [vp, ci, dp]
     L.nncp_hadamard.argtypes = [vp, ci, dp]
     L.nncp_update_mu.argtypes = [vp, ci, vp, dp, cd]
@@ -96,7 +99,7 @@ def lib() -> ctypes.CDLL:
                  "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep", "nncp_grad",
                  "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path",
                  "nncp_sweep_capture", "nncp_update_bpp", "nncp_update_admm",
-                 "nncp_update_nes"):
+                 "nncp_update_nes", "nncp_mttkrp_noalloc"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -159,6 +162,19 @@ def nncp_set_factors(ctx, factors, lam=None):
 
 def nncp_mttkrp(ctx, mode, M):
     return _check(lib().nncp_mttkrp(ctx, int(mode), _ptr(M)))
+
+
+def nncp_mttkrp_noalloc(X, factors, mode, M, **opts):
+    """MTTKRP of one mode without a context or workspace (the library's
+    per-GPU scratch array holds the temporaries); checked like Context."""
+    dims, R = check_problem(X, factors)
+    if not 0 <= int(mode) < len(dims):
+        raise ValueError(f"mode {mode} outside [0, {len(dims)})")
+    _need(M, "M", (dims[int(mode)], R), factors[0].dtype, X.device)
+    o = _opts(**opts)
+    return _check(lib().nncp_mttkrp_noalloc(len(dims), _dims(dims), int(R), _DT[X.dtype], _ptr(X),
+                                            _DT[factors[0].dtype], _ptr_array(factors), int(mode),
+                                            _ptr(M), _stream_handle(X.device), ctypes.byref(o)))
 
 
 def nncp_gram(ctx, mode, G):

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -545,6 +546,74 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
+// Buffers that one MTTKRP from the root touches (Khatri-Rao operands, the
+// two node buffers, the split partials), packed at 256-byte boundaries.  The
+// partial buffer is sized only for the launches that write partials: a root
+// product written straight into its node needs none.
+struct MttkrpCarve {
+  size_t kf, ks, A, B, part, total;
+  int64_t part_elems;
+};
+
+MttkrpCarve mttkrp_carve(const Layout &L) {
+  const int N = L.N, S = L.S, R = L.R;
+  int64_t part = 1;
+  for (int side = 0; side < 2; ++side) {
+    const GemmPlan &p = L.gp[side];
+    const int lo = side == 0 ? 0 : S, hi = side == 0 ? S : N;
+    const bool leaf = hi - lo == 1;
+    const bool direct = p.nsplit == 1 && ((side == 0 && !leaf) || (side == 1 && leaf));
+    if (!direct) part = std::max(part, (int64_t)p.nsplit * (side == 1 ? p.k : p.m) * R);
+    for (int a = lo; a < hi - 1; ++a)
+      part = std::max(part, mttv_strided_part_elems(L.hdt, L.dims[a], L.dims + a + 1, hi - a - 1, R));
+  }
+  const size_t hs = xsize(L.hdt), es = xsize(L.xdt);
+  MttkrpCarve c;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  c.kf = take(es * L.kfast_elems);
+  c.ks = take(hs * L.kslow_elems);
+  c.A = take(hs * L.nodeA);
+  c.B = take(hs * L.nodeB);
+  c.part = take(hs * part);
+  c.part_elems = part;
+  c.total = o;
+  return c;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Scratch of nncp_mttkrp_noalloc: one copy of this array per GPU, held from
+// the library's first use on that GPU until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it takes the device address that
+// hipGetSymbolAddress returns for the current device, once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NNCP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the scratch array on device `dev` (the current device).
+int scratch_base(int dev, char **base) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(NNCP_E_UNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(NNCP_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *base = (char *)g_scratch_ptr[dev];
+  return NNCP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -679,6 +748,52 @@ int nncp_mttkrp(nncp_ctx *c, int mode, void *M) {
   if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
   if (!M) return fail(NNCP_E_INVAL, "M is NULL");
   return mttkrp_tree(c, factors_of(c, c->H), mode, M, true);
+}
+
+int nncp_mttkrp_noalloc(int N, const int64_t *dims, int R, int x_dtype, const void *X,
+                        int h_dtype, void *const *H, int mode, void *M, void *stream,
+                        const nncp_options *opt) {
+  Layout L;
+  int rc = make_layout(L, N, dims, R, x_dtype, h_dtype, opt);
+  if (rc) return rc;
+  if (mode < 0 || mode >= N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, N);
+  if (!X || !H || !M) return fail(NNCP_E_INVAL, "NULL X, H or M");
+  if (!aligned16(X) || !aligned16(M)) return fail(NNCP_E_INVAL, "X and M must be 16-byte aligned");
+  for (int n = 0; n < N; ++n)
+    if (!H[n] || !aligned16(H[n])) return fail(NNCP_E_INVAL, "H[%d] is NULL or misaligned", n);
+  const MttkrpCarve cv = mttkrp_carve(L);
+  if (cv.total > (size_t)NNCP_NOALLOC_SCRATCH_BYTES)
+    return fail(NNCP_E_WORKSPACE, "this MTTKRP needs %zu bytes of scratch, more than the %zu "
+                "of nncp_mttkrp_noalloc", cv.total, (size_t)NNCP_NOALLOC_SCRATCH_BYTES);
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (stream) {
+    hipDevice_t sd = -1;
+    HIPCHK(hipStreamGetDevice((hipStream_t)stream, &sd));
+    if (sd != dev)
+      return fail(NNCP_E_INVAL, "the stream belongs to device %d, the current device is %d", (int)sd, dev);
+  }
+  char *base = nullptr;
+  rc = scratch_base(dev, &base);
+  if (rc) return rc;
+  // a context on the host stack over the scratch: only the MTTKRP buffers are
+  // set, no Gram step is pending and nothing is timed
+  nncp_ctx c;
+  c.magic = kMagic;
+  c.L = L;
+  c.L.part_elems = cv.part_elems;
+  c.X = X;
+  for (int n = 0; n < NNCP_MAX_MODES; ++n) c.H[n] = n < N ? H[n] : nullptr;
+  c.lambda = nullptr;
+  c.st = (hipStream_t)stream;
+  c.ws = base;
+  c.kf = base + cv.kf;
+  c.ks = base + cv.ks;
+  c.nodeA = base + cv.A;
+  c.nodeB = base + cv.B;
+  c.part = base + cv.part;
+  c.pending.R = 0;
+  return mttkrp_tree(&c, factors_of(&c, c.H), mode, M, true);
 }
 
 int nncp_gram(nncp_ctx *c, int mode, double *G) {

@@ -140,3 +140,29 @@ def test_binding_checks_shapes_before_any_call(B):
             B.check_problem(Xb, Hb, lb)
     with pytest.raises(ValueError):
         B.Context(X, H)                                     # host tensor: not a GPU tensor
+
+
+def test_mttkrp_noalloc_rejects_before_launch(B):
+    """nncp_mttkrp_noalloc validates its arguments and the scratch it would
+    need before touching the GPU (fake, aligned, never dereferenced
+    pointers are enough to reach every rejection)."""
+    L = B.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    H = (ctypes.c_void_p * 3)(1 << 20, 1 << 20, 1 << 20)
+    dims = (ctypes.c_int64 * 3)(8, 8, 8)
+    f32 = B.NNCP_F32
+    assert L.nncp_mttkrp_noalloc(3, dims, 4, f32, fake, f32, H, 3, fake, None, None) == B.NNCP_E_INVAL
+    assert b"mode" in L.nncp_last_error()
+    assert L.nncp_mttkrp_noalloc(3, dims, 4, f32, None, f32, H, 0, fake, None, None) == B.NNCP_E_INVAL
+    assert L.nncp_mttkrp_noalloc(3, dims, 4, f32, fake, f32, H, 0, ctypes.c_void_p((1 << 20) + 4),
+                                 None, None) == B.NNCP_E_INVAL
+    assert L.nncp_mttkrp_noalloc(3, dims, 4, B.NNCP_BF16, fake, B.NNCP_BF16, H, 0, fake, None,
+                                 None) == B.NNCP_E_DTYPE
+    # 2048 x 2048 x 64 at R = 64: the left node alone is 1 GiB
+    big = (ctypes.c_int64 * 3)(2048, 2048, 64)
+    assert L.nncp_mttkrp_noalloc(3, big, 64, f32, fake, f32, H, 0, fake, None,
+                                 None) == B.NNCP_E_WORKSPACE
+    assert b"scratch" in L.nncp_last_error()
+    assert B.NNCP_NOALLOC_SCRATCH_BYTES == 64 << 20
+    src = open(HEADER).read()
+    assert "#define NNCP_NOALLOC_SCRATCH_BYTES (64u << 20)" in src
