@@ -10,10 +10,14 @@ factors, for two forms of the same problem on the same GPU:
   fp32  FP32 tensor, FP32 matrix-core partial MTTKRP
   bf16  the tensor rounded once to BF16, BF16 matrix-core partial MTTKRP with
         FP32 accumulation (the reported `value`)
-Inputs are resident in HBM before timing starts.  The reported rate times the
-sweeps replayed as one HIP graph; per-kernel times (for the roofline) come
-from HIP events around every launch in a second timed pass of the same
-sweeps with plain launches.  Prints one JSON line.
+Inputs are resident in HBM before timing starts.  The reported rate is the
+median of `--reps` timed replays (each from the start factors) of the sweeps
+captured as one HIP graph; per-kernel times (for the roofline) come from HIP
+events around every launch in a further pass of the same sweeps with plain
+launches.  Beside them: the device's streaming-read ceiling
+(nncp_read_probe), the BF16 partial MTTKRPs with the last-level cache evicted
+first, and the same kernels on the 8 GiB 256^4 workload (DRAM-only rates);
+and the oracle on the host's CPU share.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -30,7 +35,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "MTTKRP HBM GB/s and NNCP sweeps/s, BF16-MFMA vs FP32 at stated rel error"
-WORKLOAD = "512x512x512 rank-32 uniform + 5% |gaussian| noise, R=32, HALS, 50 sweeps"
+WORKLOAD = "512x512x512 rank-32 uniform + 5% |gaussian| noise, R=32, HALS, {n} sweeps"
+ANCHOR = "256x256x256x256 bf16 rank-64 exponential + 2% |gaussian| noise, R=64, HALS"
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_01149_amd", "csrc", "partial_mttkrp.hip")
 CAT_NAMES = ["gemm_left", "gemm_right", "krp", "mttv", "update"]
 
@@ -63,10 +69,11 @@ def read_traffic(kernel: str):
         return None
 
 
-def run_form(nn, torch, X, H0, steps, warmup, algo):
-    """Warm up; time `steps` sweeps from the start factors replayed as a HIP
-    graph (the reported rate); then time the same sweeps again with plain
-    launches and per-launch HIP events (the per-kernel times)."""
+def run_form(nn, torch, X, H0, steps, warmup, algo, reps):
+    """Warm up; time `reps` replays of `steps` sweeps from the start factors
+    (one HIP graph; the factors are reset before each replay, outside the
+    timed region) and take the median; then time the same sweeps again with
+    plain launches and per-launch HIP events (the per-kernel times)."""
     dev = X.device
     H = [h.clone() for h in H0]
     lam = torch.ones(H0[0].shape[1], dtype=torch.float64, device=dev)
@@ -87,14 +94,20 @@ def run_form(nn, torch, X, H0, steps, warmup, algo):
     reset()
     ctx.capture(algo, n, rel)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    ctx.sweep(algo, n, rel)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
+    times, walls, rels = [], [], []
+    for _ in range(max(1, reps)):
+        reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        ctx.sweep(algo, n, rel)
+        e1.record()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        times.append(e0.elapsed_time(e1))
+        rels.append(rel.clone())
+    ms = statistics.median(times)
+    reps_equal = all(torch.equal(rels[0], r) for r in rels[1:])
     # same sweeps, plain launches with per-launch events
     rel2 = torch.empty(n, dtype=torch.float64, device=dev)
     reset()
@@ -107,8 +120,10 @@ def run_form(nn, torch, X, H0, steps, warmup, algo):
     ms_eager = f0.elapsed_time(f1)
     cat_ms, cat_n = ctx.timers_read()
     ctx.timers_enable(False)
-    same = bool(torch.equal(rel, rel2))
-    return ctx, dict(ms=ms, wall_s=wall, ms_eager_timed=ms_eager, relerr=rel.cpu().tolist()[:steps],
+    # the factors are left at the result of `steps` sweeps from the start
+    same = bool(torch.equal(rel, rel2)) and reps_equal
+    return ctx, dict(ms=ms, ms_reps=times, wall_s=statistics.median(walls),
+                     ms_eager_timed=ms_eager, relerr=rel.cpu().tolist()[:steps],
                      graph_equals_eager=same, cat_ms=cat_ms, cat_n=cat_n)
 
 
@@ -318,7 +333,8 @@ def _read_counter_csv(path, counter):
     return {int(r["Dispatch_Id"]): (r["Kernel_Name"], float(r["Counter_Value"])) for r in rows}
 
 
-def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write):
+def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write, prefix="",
+                       workload="512x512x512, R=32, HALS (bench.py default workload)"):
     """Write profiles/traffic_<kernel>.txt: HBM bytes per launch from FETCH_SIZE
     and WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for
     the --copy-probe device copy of COPY_PROBE_BYTES (found as the copy dispatch
@@ -341,9 +357,9 @@ def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write):
         fkib = statistics.mean(fe[d][1] for d in ids)
         wkib = statistics.mean(wr[d][1] for d in ids)
         hbm = (fkib * f_read + wkib * f_write) * 1024
-        with open(os.path.join(ROOT, "profiles", f"traffic_{kname}.txt"), "w") as fh:
+        with open(os.path.join(ROOT, "profiles", f"traffic_{prefix}{kname}.txt"), "w") as fh:
             fh.write(f"# HBM traffic per launch of the {kname.replace('_', ' ')} partial MTTKRP kernel\n")
-            fh.write("# workload: 512x512x512, R=32, HALS (bench.py default workload)\n")
+            fh.write(f"# workload: {workload}\n")
             fh.write(f"# fetch run: {cmd_fetch}\n# write run: {cmd_write}\n")
             fh.write(f"# summarised with: python bench.py --summarize-counters <fetch csv> <write csv>\n")
             fh.write(f"# calibration: the --copy-probe device copy of {COPY_PROBE_BYTES} bytes reads "
@@ -353,7 +369,7 @@ def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write):
             fh.write(f"read_scale = {f_read:.5f}\nwrite_scale = {f_write:.5f}\n")
             fh.write(f"hbm_bytes_per_launch = {hbm:.0f}\n")
             fh.write(f"kernel_source_sha = {source_sha()}\n")
-        print(f"{kname}: {len(ids)} dispatches, {hbm / 2**20:.1f} MiB per launch")
+        print(f"{prefix}{kname}: {len(ids)} dispatches, {hbm / 2**20:.1f} MiB per launch")
 
 
 def summarize_mfma(csv_path, cmd):
@@ -429,20 +445,32 @@ def main():
                             "and NES with the outer step "
                             "(timed and untimed passes)")
             return
+        if len(sys.argv) > 3 and sys.argv[3] == "anchor":
+            summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
+                            f"{pa} -- python3 bench.py --anchor-only", "kernels_256x4_hals.txt",
+                            ANCHOR + " (5 graph-replayed and 5 event-timed sweeps)")
+            return
         summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
-                        f"{pa} -- python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline")
+                        f"{pa} -- python3 bench.py --steps 10 --warmup 2 --reps 5 "
+                        "--no-cpu-baseline --no-dram")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         fetch_csv, write_csv = sys.argv[2], sys.argv[3]
-        run = "-- python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --copy-probe"
+        anchor = len(sys.argv) > 4 and sys.argv[4] == "anchor"
+        run = ("-- python3 bench.py --anchor-only --copy-probe" if anchor else
+               "-- python3 bench.py --steps 3 --warmup 1 --reps 1 --no-cpu-baseline --no-dram "
+               "--copy-probe")
         cmd_f = f"rocprofv3 --pmc FETCH_SIZE --output-format csv {_prof_args(fetch_csv)} {run}"
         cmd_w = f"rocprofv3 --pmc WRITE_SIZE --output-format csv {_prof_args(write_csv)} {run}"
-        summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w)
+        if anchor:
+            summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w, "anchor_", ANCHOR)
+        else:
+            summarize_counters(fetch_csv, write_csv, cmd_f, cmd_w)
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-mfma":
         summarize_mfma(sys.argv[2], "rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE "
                        f"--output-format csv {_prof_args(sys.argv[2])} -- python3 bench.py "
-                       "--steps 3 --warmup 1 --no-cpu-baseline")
+                       "--steps 3 --warmup 1 --reps 1 --no-cpu-baseline --no-dram")
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--configs":
         run_configs(sys.argv[2].split(","))
@@ -451,7 +479,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5, help="timed replays (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dram", action="store_true",
+                    help="skip the DRAM-only measurements (LLC-cold 512^3 products, 256^4 workload)")
+    ap.add_argument("--anchor-only", action="store_true",
+                    help="only the 256^4 measurement (for its counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -466,11 +499,6 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log("generating 512^3 workload on the GPU")
-    w = gen.workload2(device="cuda:0", keep_fp32=False)
-    dims, R = w["dims"], w["R"]
-    H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
-    torch.cuda.synchronize()
 
     if args.copy_probe:
         src = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device=dev)
@@ -479,15 +507,26 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.anchor_only:
+        print(json.dumps({"dram_anchor": dram_anchor(nn, torch, gen, dev)}), flush=True)
+        return
+
+    log("generating 512^3 workload on the GPU")
+    w = gen.workload2(device="cuda:0", keep_fp32=False)
+    dims, R = w["dims"], w["R"]
+    H0 = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+    torch.cuda.synchronize()
+
     res = {}
     ctxs = {}
     for form, X in (("fp32", w["X32"]), ("bf16", w["Xbf16"])):
-        log(f"timing {form}: {args.warmup} warmup + {args.steps} sweeps")
-        ctx, r = run_form(nn, torch, X, H0, args.steps, args.warmup, nn.NNCP_HALS)
+        log(f"timing {form}: {args.warmup} warmup + {args.reps} x {args.steps} sweeps")
+        ctx, r = run_form(nn, torch, X, H0, args.steps, args.warmup, nn.NNCP_HALS, args.reps)
         r["paths"] = [ctx.gemm_path(0), ctx.gemm_path(1)]
         res[form] = r
         ctxs[form] = ctx
-        log(form, f"{r['ms'] / max(1, args.steps):.4f} ms/sweep", "cat_ms", [round(x, 3) for x in r["cat_ms"]],
+        log(form, f"{r['ms'] / max(1, args.steps):.4f} ms/sweep (median of {len(r['ms_reps'])})",
+            "cat_ms", [round(x, 3) for x in r["cat_ms"]],
             "launches", r["cat_n"], "final relerr", r["relerr"][-1] if r["relerr"] else None)
 
     # BF16 run's final error measured against the unrounded FP32 tensor
@@ -518,6 +557,17 @@ def main():
         for side, name in ((0, "gemm_left"), (1, "gemm_right")):
             g, a = gbps(form, side)
             mt[f"{form}_{name}"] = {"GBps": g, "avg_ms": a}
+
+    log("streaming-read ceiling")
+    ceiling = stream_ceiling(nn, torch, dev)
+    cold = None
+    if not args.no_dram:
+        log("LLC-cold partial MTTKRPs")
+        cold = llc_cold_gemms(nn, torch, ctxs["bf16"], dims, R)
+    for c in ctxs.values():
+        c.close()
+    del ctxs
+
     # dominant kernel of the reported (bf16) form
     dom_side = 0 if b["cat_ms"][0] >= b["cat_ms"][1] else 1
     dom_name = CAT_NAMES[dom_side]
@@ -526,14 +576,25 @@ def main():
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": (ach / HBM_PEAK_GBPS) if ach else None, "traffic": traffic,
             "kernel": f"bf16 {dom_name} partial MTTKRP", "avg_launch_ms": avg_ms,
-            "algorithmic_bytes_per_launch": gemm_bytes(dims, R, 2, dom_side)}
+            "algorithmic_bytes_per_launch": gemm_bytes(dims, R, 2, dom_side),
+            "frac_of_stream_read_ceiling": ach / ceiling["ceiling_GBps"],
+            "note": "the 256 MiB BF16 tensor fits the 256 MB last-level cache, so this rate is "
+                    "partly cache bandwidth; llc_cold and dram_anchor give the DRAM-only rates"}
+
+    anchor = None
+    if not args.no_dram:
+        anchor = dram_anchor(nn, torch, gen, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        nthr = min(16, os.cpu_count() or 1)
-        log(f"timing the oracle on {nthr} host threads (one sweep)")
-        cpu = cpu_baseline(w["X32"], H0, oracle.HALS, nthr)
+        info = host_info()
+        log(f"timing the oracle on {info['threads']} host threads "
+            f"({info['cpu_model']}, {info['logical_cpus']} logical CPUs)")
+        cpu = cpu_baseline(w["X32"], H0, oracle.HALS, info["threads"])
+        cpu["cpu_model"] = info["cpu_model"]
+        cpu["host_logical_cpus"] = info["logical_cpus"]
+        cpu["threads_from"] = info["threads_from"]
 
     out = {
         "metric": METRIC,
@@ -548,13 +609,16 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic (seeded; rank-32 uniform factors + 5% |gaussian| noise)",
-        "config": {"workload": WORKLOAD, "dims": dims, "R": R, "algo": "hals",
+        "config": {"workload": WORKLOAD.format(n=args.steps), "dims": dims, "R": R, "algo": "hals",
                    "tensor_dtype": "bf16", "accumulate": "fp32", "factors": "fp32",
-                   "krp_operand": "bf16 hi+lo", "parallelism": "single GPU"},
+                   "krp_operand": "bf16 hi+lo", "parallelism": "single GPU",
+                   "timed_replays": args.reps, "statistic": "median"},
         "fp32_form": {"sweeps_per_s": sweeps_fp32, "ms_per_step": f["ms"] / steps,
+                      "ms_per_step_reps": [t / steps for t in f["ms_reps"]],
                       "final_relerr": f["relerr"][-1] if f["relerr"] else None,
                       "ms_per_step_eager_timed": f["ms_eager_timed"] / steps},
         "bf16_form": {"sweeps_per_s": sweeps_bf16,
+                      "ms_per_step_reps": [t / steps for t in b["ms_reps"]],
                       "final_relerr": b["relerr"][-1] if b["relerr"] else None,
                       "final_relerr_vs_fp32_tensor": rel_bf16_vs_fp32,
                       "ms_per_step_eager_timed": b["ms_eager_timed"] / steps},
@@ -564,10 +628,109 @@ def main():
         "category_ms_per_sweep": {form: {CAT_NAMES[k]: res[form]["cat_ms"][k] / steps for k in range(5)}
                                   for form in res},
         "wall_s": {form: res[form]["wall_s"] for form in res},
+        "stream_read": ceiling,
+        "llc_cold": cold,
+        "dram_anchor": anchor,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def host_info():
+    """CPU model, logical CPUs, and the oracle's thread count: OMP_NUM_THREADS
+    when set (the host's CPU share for this GPU), else the CPUs this process
+    may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        threads, src = min(int(env), avail), "OMP_NUM_THREADS"
+    else:
+        threads, src = avail, "sched_getaffinity"
+    return dict(cpu_model=model, logical_cpus=os.cpu_count(), threads=threads, threads_from=src)
+
+
+def stream_ceiling(nn, torch, dev, sizes=(1 << 28, 1 << 32), iters=10, wgs=(4096, 8192, 16384)):
+    """Streaming-read rate (nncp_read_probe, best of a few grid sizes) of a
+    256 MiB buffer (about the last-level cache) and of a 4 GiB one (DRAM);
+    the 4 GiB rate is the attainable ceiling reported beside the 8 TB/s
+    datasheet figure."""
+    out = {}
+    for nbytes in sizes:
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        best = 0.0
+        for wg in wgs:
+            for _ in range(3):
+                nn.nncp_read_probe(buf, wg)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(iters):
+                nn.nncp_read_probe(buf, wg)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / iters
+            best = max(best, nbytes / (ms / 1e3) / 1e9)
+        out[f"{nbytes >> 20}MiB_GBps"] = best
+        del buf
+    out["ceiling_GBps"] = out[f"{sizes[-1] >> 20}MiB_GBps"]
+    out["ceiling_frac_of_8TBps"] = out["ceiling_GBps"] / HBM_PEAK_GBPS
+    out["probe"] = "nncp_read_probe: 16-byte non-temporal loads, 8 in flight per lane, best of %s workgroups" % (list(wgs),)
+    torch.cuda.empty_cache()
+    return out
+
+
+def llc_cold_gemms(nn, torch, ctx, dims, R, reps=5):
+    """The BF16 512^3 partial MTTKRPs with the last-level cache evicted first
+    (a streaming read of another 1 GiB before each product: clean lines, so
+    the product pays no write-back), timed by the library's events: the
+    DRAM-only rate of the headline kernels."""
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=ctx.X.device)
+    ctx.timers_enable(True)
+    for k in range(reps):
+        for mode in (0, 2):
+            nn.nncp_read_probe(flush)
+            ctx.mttkrp(mode)
+    ms, n = ctx.timers_read()
+    ctx.timers_enable(False)
+    del flush
+    out = {}
+    for side, name in ((0, "gemm_left"), (1, "gemm_right")):
+        avg = ms[side] / n[side]
+        gb = gemm_bytes(dims, R, 2, side) / (avg / 1e3) / 1e9
+        out[name] = {"avg_ms": avg, "GBps": gb, "frac": gb / HBM_PEAK_GBPS, "launches": n[side]}
+    return out
+
+
+def dram_anchor(nn, torch, gen, dev, nsweeps=5):
+    """The 256^4 BF16 R = 64 HALS workload (8 GiB, far beyond the last-level
+    cache): sweeps/s by graph replay, and the partial MTTKRPs' event-timed
+    rates (algorithmic bytes: the tensor once plus the output temporary)."""
+    log("generating the 256^4 workload on the GPU")
+    w = gen.workload3(device=str(dev))
+    H = [torch.from_numpy(h).float().to(dev) for h in w["H0"]]
+    ctx = nn.Context(w["X"], H)
+    mps, rel, cm, cn = _timed_sweeps(nn, torch, ctx, nn.NNCP_HALS, nsweeps)
+    rates = _gemm_rates(w["dims"], w["R"], 2, ctx.split(), cm, cn)
+    for name in rates:
+        rates[name]["frac"] = rates[name]["GBps"] / HBM_PEAK_GBPS
+        rates[name]["bytes"] = _side_bytes(w["dims"], w["R"], 2, ctx.split(),
+                                           0 if name == "gemm_left" else 1)
+        rates[name]["traffic"] = read_traffic(f"anchor_bf16_{name}")
+    ctx.close()
+    del w, H
+    torch.cuda.empty_cache()
+    log(f"256^4: {mps:.3f} ms/sweep, " + ", ".join(
+        f"{k} {v['GBps']:.0f} GB/s" for k, v in rates.items()))
+    return {"workload": ANCHOR, "sweeps": nsweeps, "ms_per_sweep": mps, "sweeps_per_s": 1e3 / mps,
+            "relerr": rel, **rates}
 
 
 if __name__ == "__main__":

@@ -108,6 +108,13 @@ typedef struct nncp_options {
   int graphs;       /* 1 = nncp_sweep replays its launches as a HIP graph
                        (captured once per (algo, nsweeps, relerr_hist) and
                        factor binding), 0 = plain launches [1].                */
+  int fused_grad;   /* 1 = nncp_grad computes both root partial MTTKRPs in one
+                       pass over X where that path applies (BF16 tensor,
+                       R <= 32, at least two modes on the left of the root
+                       split) and the grid is large enough to fill the GPU
+                       (at least 192 workgroups of 1024 columns), 2 = wherever
+                       it applies, whatever the grid, 0 = one pass per root
+                       product [1].                                            */
 } nncp_options;
 
 typedef struct nncp_ctx nncp_ctx;
@@ -148,10 +155,24 @@ int nncp_set_factors(nncp_ctx *ctx, void *const *H, double *lambda);
  *   M^(n) = X_(n) (H^(N-1) kr ... kr H^(n+1) kr H^(n-1) kr ... kr H^(0)),
  * computed through the dimension tree (Algorithm 3 with the transposes and
  * Khatri-Rao ranges corrected): the partial MTTKRP at the root of n's
- * subtree, then multi-TTVs down to n.  One pass over X.
+ * subtree, then multi-TTVs down to n.
+ * Nodes of the tree that an earlier nncp_mttkrp left in the workspace are
+ * reused when every factor they were contracted with is unchanged since
+ * (the reuse of Algorithm 3): the context keeps a version per factor, bumped
+ * by every call that writes factors (nncp_update_*, nncp_sweep, nncp_pgd,
+ * nncp_set_factors) and by nncp_factors_changed, which a caller must use
+ * after writing a factor buffer itself.  Calls for modes 0..N-1 in order at
+ * fixed factors therefore read X twice, not N times; a call whose nodes are
+ * stale reads X once.  Any other entry point that uses the workspace drops
+ * the cached nodes.  The result does not depend on the call order.
  *   M  I_n x R, row-major, h_dtype.
  */
 int nncp_mttkrp(nncp_ctx *ctx, int mode, void *M);
+
+/* The caller has written factor `mode` (every factor when mode = -1) in its
+ * own buffer: bump its version (so no cached node built from the old values
+ * is reused) and recompute its Gram matrix. */
+int nncp_factors_changed(nncp_ctx *ctx, int mode);
 
 /*
  * nncp_mttkrp without a context or workspace, for callers that cannot
@@ -301,11 +322,20 @@ int nncp_sweep_capture(nncp_ctx *ctx, int algo, int nsweeps, double *relerr_hist
  * Gradient of L = 0.5 ||X - [[H]]||^2 (lambda treated as all ones, no
  * normalisation) with respect to every factor at the current point:
  *   dL/dH^(n) = H^(n) S^(n) - M^(n),
- * with all N MTTKRPs at the same point (two passes over X).
+ * with all N MTTKRPs at the same point, through the dimension tree from its
+ * two root partial MTTKRPs.  Both roots come from one pass over X when
+ * options.fused_grad is set and the fused path applies (BF16 tensor,
+ * R <= 32, at least two modes left of the root split, its buffers within the
+ * LDS; see options.fused_grad for the grid size); otherwise one pass per root
+ * (two passes).  nncp_uses_fused_grad tells which.
  *   grads  host array of N device pointers, each I_n x R h_dtype
  *   loss   1 FP64: L via the identity (may be NULL)
  */
 int nncp_grad(nncp_ctx *ctx, void *const *grads, double *loss);
+
+/* 1 if nncp_grad on this context reads X once (both root partial MTTKRPs in
+ * one kernel), 0 if it reads X once per root product. */
+int nncp_uses_fused_grad(const nncp_ctx *ctx);
 
 /*
  * nsteps projected-gradient steps on L = 0.5 ||X - [[H]]||^2 (lambda = 1):
@@ -326,7 +356,8 @@ int nncp_pgd(nncp_ctx *ctx, int nsteps, double armijo_c, int max_halvings, int p
  * Per-category GPU time, from HIP events recorded on the context's stream
  * around each launch while timing is enabled (the time-breakdown categories
  * of the paper's experiments, restricted to one GPU):
- *   0  left partial MTTKRP kernel (GEMM over modes S..N-1)
+ *   0  left partial MTTKRP kernel (GEMM over modes S..N-1); in nncp_grad
+ *      with the fused path, the kernel computing both root products
  *   1  right partial MTTKRP kernel (GEMM over modes 0..S-1)
  *   2  Khatri-Rao operands of the partial MTTKRPs
  *   3  multi-TTVs and split-reduction finalize
@@ -360,6 +391,34 @@ int nncp_split(const nncp_ctx *ctx);
  * (MFMA), 0 = vector ALU.  Returns NNCP_E_INVAL for a bad side.
  */
 int nncp_gemm_path(const nncp_ctx *ctx, int side);
+
+/*
+ * Launch plan of one partial MTTKRP (side as for nncp_gemm_path), for
+ * inspection and for bounding its rounding error.  info is a host array of 7
+ * entries:
+ *   [0] 1 = matrix cores, 0 = vector ALU
+ *   [1] Pf      length of the fast part of the reduced index (the Khatri-Rao
+ *               rows held on chip; one accumulator block)
+ *   [2] Ps      number of fast blocks (Pf * Ps = the reduced length)
+ *   [3] nsplit  workgroups the reduction is split over (partials added in
+ *               split order)
+ *   [4] tiles   output tiles (the other grid dimension)
+ *   [5] W       left side: fast indices staged in LDS at a time
+ *   [6] hl      1 = the Khatri-Rao operand is a hi + lo pair of the tensor's
+ *               16-bit type
+ */
+int nncp_gemm_plan(const nncp_ctx *ctx, int side, int64_t *info);
+
+/*
+ * Measurement helper: one streaming read of a device buffer (16-byte
+ * non-temporal loads, grid-stride over `workgroups` workgroups of 256 threads), the attainable
+ * read bandwidth that the partial MTTKRP's HBM rate is compared with.
+ *   buf    device buffer of `bytes` bytes (a positive multiple of 16), read only
+ *   out4   4 device bytes, written only if the XOR of everything read equals
+ *          a fixed value (so the loads cannot be dropped)
+ * Asynchronous on `stream`; time it with events on that stream.
+ */
+int nncp_read_probe(const void *buf, size_t bytes, int workgroups, void *out4, void *stream);
 
 #ifdef __cplusplus
 }

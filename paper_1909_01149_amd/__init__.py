@@ -11,5 +11,6 @@ from .binding import (  # noqa: F401
     nncp_hadamard, nncp_init, nncp_mttkrp, nncp_pgd, nncp_set_factors, nncp_split, nncp_sweep,
     nncp_update_hals, nncp_update_mu, nncp_workspace_size, nncp_timers_enable, nncp_timers_read,
     nncp_sweep_capture, nncp_update_bpp, nncp_update_admm, nncp_update_nes, nncp_mttkrp_noalloc,
-    NNCP_NOALLOC_SCRATCH_BYTES,
+    NNCP_NOALLOC_SCRATCH_BYTES, nncp_gemm_plan, nncp_read_probe, nncp_uses_fused_grad,
+    nncp_factors_changed,
 )

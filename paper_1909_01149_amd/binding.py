@@ -34,6 +34,7 @@ EXPORTS = [
     "nncp_grad", "nncp_pgd", "nncp_destroy", "nncp_last_error", "nncp_split",
     "nncp_gemm_path", "nncp_timers_enable", "nncp_timers_read", "nncp_sweep_capture",
     "nncp_update_bpp", "nncp_update_admm", "nncp_update_nes", "nncp_mttkrp_noalloc",
+    "nncp_gemm_plan", "nncp_read_probe", "nncp_uses_fused_grad", "nncp_factors_changed",
 ]
 NNCP_NOALLOC_SCRATCH_BYTES = 64 << 20
 NNCP_TIMER_CATEGORIES = 5
@@ -50,7 +51,7 @@ class NNCPError(RuntimeError):
 
 class nncp_options(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int), ("krp_split", ctypes.c_int), ("generic", ctypes.c_int),
-                ("eps_mu", ctypes.c_double), ("graphs", ctypes.c_int)]
+                ("eps_mu", ctypes.c_double), ("graphs", ctypes.c_int), ("fused_grad", ctypes.c_int)]
 
 
 _lib = None
@@ -92,6 +93,10 @@ def lib() -> ctypes.CDLL:
     L.nncp_last_error.restype = ctypes.c_char_p
     L.nncp_split.argtypes = [vp]
     L.nncp_gemm_path.argtypes = [vp, ci]
+    L.nncp_gemm_plan.argtypes = [vp, ci, i64p]
+    L.nncp_read_probe.argtypes = [vp, ctypes.c_size_t, ci, vp, vp]
+    L.nncp_uses_fused_grad.argtypes = [vp]
+    L.nncp_factors_changed.argtypes = [vp, ci]
     L.nncp_timers_enable.argtypes = [vp, ci]
     L.nncp_timers_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ctypes.c_int64)]
     for name in ("nncp_timers_enable", "nncp_timers_read",
@@ -99,7 +104,8 @@ def lib() -> ctypes.CDLL:
                  "nncp_update_mu", "nncp_update_hals", "nncp_cp_loss", "nncp_sweep", "nncp_grad",
                  "nncp_pgd", "nncp_destroy", "nncp_split", "nncp_gemm_path",
                  "nncp_sweep_capture", "nncp_update_bpp", "nncp_update_admm",
-                 "nncp_update_nes", "nncp_mttkrp_noalloc"):
+                 "nncp_update_nes", "nncp_mttkrp_noalloc", "nncp_gemm_plan", "nncp_read_probe",
+                 "nncp_uses_fused_grad", "nncp_factors_changed"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -120,8 +126,9 @@ def _dims(dims):
     return arr
 
 
-def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16, graphs=1):
-    return nncp_options(int(split), int(krp_split), int(generic), float(eps_mu), int(graphs))
+def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16, graphs=1, fused_grad=1):
+    return nncp_options(int(split), int(krp_split), int(generic), float(eps_mu), int(graphs),
+                        int(fused_grad))
 
 
 def _ptr_array(ts):
@@ -241,6 +248,36 @@ def nncp_gemm_path(ctx, side) -> int:
     return _check(lib().nncp_gemm_path(ctx, int(side)))
 
 
+def nncp_uses_fused_grad(ctx) -> int:
+    return _check(lib().nncp_uses_fused_grad(ctx))
+
+
+def nncp_factors_changed(ctx, mode=-1):
+    return _check(lib().nncp_factors_changed(ctx, int(mode)))
+
+
+def nncp_read_probe(buf, workgroups=8192):
+    """Launch one streaming read of the device tensor buf on the current
+    stream (time it with torch events on that stream)."""
+    if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous GPU tensor")
+    nbytes = buf.numel() * buf.element_size()
+    out = torch.empty(1, dtype=torch.int32, device=buf.device)
+    _check(lib().nncp_read_probe(_ptr(buf), nbytes - nbytes % 16, int(workgroups), _ptr(out),
+                                 _stream_handle(buf.device)))
+    return out
+
+
+GEMM_PLAN_KEYS = ("mfma", "Pf", "Ps", "nsplit", "tiles", "W", "hl")
+
+
+def nncp_gemm_plan(ctx, side) -> dict:
+    """Launch plan of one partial MTTKRP (see include/nncp.h)."""
+    info = (ctypes.c_int64 * len(GEMM_PLAN_KEYS))()
+    _check(lib().nncp_gemm_plan(ctx, int(side), info))
+    return dict(zip(GEMM_PLAN_KEYS, [int(v) for v in info]))
+
+
 def nncp_timers_enable(ctx, on: bool):
     return _check(lib().nncp_timers_enable(ctx, 1 if on else 0))
 
@@ -322,7 +359,7 @@ class Context:
     checked here and in every method before the library is called."""
 
     def __init__(self, X, factors, lam=None, *, split=0, krp_split=1, generic=0, eps_mu=1e-16,
-                 graphs=1):
+                 graphs=1, fused_grad=1):
         if not isinstance(X, torch.Tensor) or not X.is_cuda:
             raise ValueError("X must be a GPU tensor")
         dims, R = check_problem(X, factors, lam)
@@ -335,7 +372,7 @@ class Context:
         self.lam = (lam.to(device=dev, dtype=torch.float64).contiguous() if lam is not None
                     else torch.ones(self.R, dtype=torch.float64, device=dev))
         self.opts = dict(split=split, krp_split=krp_split, generic=generic, eps_mu=eps_mu,
-                         graphs=graphs)
+                         graphs=graphs, fused_grad=fused_grad)
         nbytes = nncp_workspace_size(self.dims, self.R, _DT[X.dtype], _DT[self.factors[0].dtype],
                                      **self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -355,6 +392,12 @@ class Context:
 
     def gemm_path(self, side: int) -> int:
         return nncp_gemm_path(self.ctx, side)
+
+    def gemm_plan(self, side: int) -> dict:
+        return nncp_gemm_plan(self.ctx, side)
+
+    def uses_fused_grad(self) -> bool:
+        return bool(nncp_uses_fused_grad(self.ctx))
 
     def _mode(self, mode):
         if not 0 <= int(mode) < self.N:
@@ -439,11 +482,11 @@ class Context:
         self._check_hist(relerr_hist, nsweeps)
         nncp_sweep_capture(self.ctx, algo, nsweeps, relerr_hist)
 
-    def refresh_grams(self):
-        """Recompute the context's Gram matrices after the factor tensors were
-        overwritten in place (same buffers, so captured graphs stay valid)."""
-        for n in range(self.N):
-            nncp_gram(self.ctx, n, None)
+    def refresh_grams(self, mode: int = -1):
+        """Report factor tensors overwritten in place (same buffers, so
+        captured graphs stay valid): their Gram matrices are recomputed and
+        no cached dimension-tree node built from the old values is reused."""
+        nncp_factors_changed(self.ctx, mode)
 
     def grad(self, grads=None, loss=None):
         if grads is None:
@@ -479,7 +522,8 @@ class Context:
 class CPLoss(torch.autograd.Function):
     """L = 0.5 ||X - [[H^(0), ..., H^(N-1)]]||^2 (lambda = 1) with the
     hand-written adjoint dL/dH^(n) = H^(n) S^(n) - M^(n) computed by the
-    library (all N MTTKRPs at the same point, two passes over X).
+    library (all N MTTKRPs at the same point; one pass over X where the
+    fused path applies, the same pass count as the loss alone, else two).
 
     Usage: ``CPLoss.apply(ctx, *factors)`` with ctx a ``Context`` over X."""
 

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnncp.so")
-SOURCES = ["partial_mttkrp.hip", "tree_update.hip", "nncp_ctx.hip"]
+SOURCES = ["partial_mttkrp.hip", "tree_update.hip", "nncp_ctx.hip", "read_probe.hip"]
 ARCH = "gfx950"
 # Packed-FP32 instructions are kept out of the generated code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -52,9 +52,12 @@ struct Layout {
   nncp_options opt;
   GemmPlan gp[2];
   int64_t maxI, nodeA, nodeB, part_elems, kfast_elems, kslow_elems, sumI;
+  // nncp_grad's single pass over X: both root products in one kernel
+  int dual;
+  int64_t dual_tiles, nodeR;
   // byte offsets into the workspace
   size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart,
-      off_red, off_M, off_A, off_B, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_outer, off_admmU,
+      off_red, off_M, off_A, off_B, off_R, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_outer, off_admmU,
       off_admmMc, off_admmP, off_admmNorm, off_admmStatus, total;
 };
 
@@ -65,6 +68,7 @@ nncp_options default_options() {
   o.generic = 0;
   o.eps_mu = 1e-16;
   o.graphs = 1;
+  o.fused_grad = 1;
   return o;
 }
 
@@ -99,6 +103,9 @@ void plan_side(Layout &L, int side) {
   const int es = (int)xsize(L.xdt);
   // tensors up to 1 GiB are read with normal loads (much of them is still in
   // the last-level cache for the next product); larger ones are streamed
+  // with non-temporal loads by the left product (and the gradient's fused
+  // pass); the right product measured slower with them on the 256^4 tensor
+  // (4.99 against 5.47 TB/s)
   p.nt_loads = (double)p.m * (double)p.k * es > (double)(1ull << 30) ? 1 : 0;
   const int hs = (int)xsize(L.hdt);
   const int VEC = 16 / es;
@@ -241,6 +248,25 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
     for (int a = lo; a < hi - 1; ++a)
       part = std::max(part, mttv_strided_part_elems(L.hdt, L.dims[a], L.dims + a + 1, hi - a - 1, R));
   }
+  // the fused pass of the gradient (see launch_dual_mttkrp)
+  {
+    const GemmPlan &pl = L.gp[0], &pr = L.gp[1];
+    L.dual = 0;
+    L.dual_tiles = 0;
+    L.nodeR = 1;
+    // fused_grad = 1: only where the columns alone give about 0.75 of a
+    // workgroup per CU (smaller grids are faster as two passes);
+    // fused_grad = 2: wherever the kernel can run
+    if (L.opt.fused_grad && xdt == NNCP_BF16 && pl.mfma && pr.mfma && pl.NT <= 2 && S >= 2 &&
+        pl.m < ((int64_t)1 << 31) && pr.Pf % 32 == 0 &&
+        dual_lds_bytes(pl.NT, pl.hl, pr.Pf) <= 160 * 1024 &&
+        (L.opt.fused_grad == 2 || dual_tiles(pl.m) >= 192)) {
+      L.dual = 1;
+      L.dual_tiles = dual_tiles(pl.m);
+      part = std::max(part, L.dual_tiles * pl.k * R);
+      L.nodeR = pl.k * R;
+    }
+  }
   L.part_elems = part;
   L.kfast_elems = 0;
   L.kslow_elems = 0;
@@ -265,6 +291,7 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_M = take(hs * L.maxI * R);
   L.off_A = take(hs * L.nodeA);
   L.off_B = take(hs * L.nodeB);
+  L.off_R = take(hs * L.nodeR);
   L.off_part = take(hs * L.part_elems);
   L.off_kf = take(es * L.kfast_elems);
   L.off_ks = take(hs * L.kslow_elems);
@@ -321,8 +348,20 @@ struct nncp_ctx {
   double *admmU, *admmMc, *admmP, *admmNorm;
   int *admmStatus;
   double *outer;
-  void *M, *nodeA, *nodeB, *part, *kf, *ks;
+  void *M, *nodeA, *nodeB, *nodeR, *part, *kf, *ks;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
+  // set while nncp_grad walks the right subtree from the fused pass: the
+  // right root node lives in nodeR
+  bool right_root_in_R = false;
+  // node cache of nncp_mttkrp: a version per factor, bumped whenever the
+  // library writes the factor or the caller reports a write
+  // (nncp_factors_changed), and for each node buffer the node it holds with
+  // the versions of the factors it was contracted with
+  uint64_t ver[NNCP_MAX_MODES] = {};
+  struct NodeTag {
+    int side = -1, a = -1;
+    uint64_t ver[NNCP_MAX_MODES];
+  } tagA, tagB;
 };
 
 namespace {
@@ -403,6 +442,10 @@ struct MRef {
   int64_t mstride;
 };
 
+// Dead-column mask of the sweep's deferred MU/HALS path (R doubles after
+// the scratch that launch_sweep_normalize uses in c->outer).
+double *dead_mask(nncp_ctx *c) { return c->outer + (int64_t)(NNCP_MAX_MODES + 1) * c->L.R; }
+
 // Runs a pending Gram step as a kernel of its own.
 hipError_t flush_gram(nncp_ctx *c) {
   if (c->pending.R == 0) return hipSuccess;
@@ -415,7 +458,36 @@ hipError_t flush_gram(nncp_ctx *c) {
 
 void *node_buf(nncp_ctx *c, int side, int a) {
   const int lo = side == 0 ? 0 : c->L.S;
+  if (side == 1 && a == lo && c->right_root_in_R) return c->nodeR;
   return ((a - lo) % 2 == 0) ? c->nodeA : c->nodeB;
+}
+
+// ---- node cache of nncp_mttkrp
+void bump_versions(nncp_ctx *c, int mode) {
+  for (int q = 0; q < c->L.N; ++q)
+    if (mode < 0 || q == mode) ++c->ver[q];
+}
+void drop_nodes(nncp_ctx *c) {
+  c->tagA.side = c->tagB.side = -1;
+}
+nncp_ctx::NodeTag &tag_of(nncp_ctx *c, int side, int a) {
+  return node_buf(c, side, a) == c->nodeA ? c->tagA : c->tagB;
+}
+// node a of a side (modes a .. hi-1, hi-1 kept only as an M) was contracted
+// with every factor outside [a, hi)
+bool node_valid(nncp_ctx *c, int side, int a) {
+  const int hi = side == 0 ? c->L.S : c->L.N;
+  const nncp_ctx::NodeTag &t = tag_of(c, side, a);
+  if (t.side != side || t.a != a) return false;
+  for (int q = 0; q < c->L.N; ++q)
+    if ((q < a || q >= hi) && t.ver[q] != c->ver[q]) return false;
+  return true;
+}
+void set_tag(nncp_ctx *c, int side, int a) {
+  nncp_ctx::NodeTag &t = tag_of(c, side, a);
+  t.side = side;
+  t.a = a;
+  for (int q = 0; q < NNCP_MAX_MODES; ++q) t.ver[q] = c->ver[q];
 }
 
 // Root partial MTTKRP of one side into node[lo] (or into Mout if the subtree
@@ -451,14 +523,19 @@ int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout, MRef *defer
 // mode n-1 (same subtree) must hold the values left by the previous call and
 // H^(n-1) may have changed since (Gauss-Seidel order of Algorithm 1).
 int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_root,
-                MRef *defer = nullptr) {
+                MRef *defer = nullptr, bool roots_ready = false, int have_node = -1) {
   const Layout &L = c->L;
   const int side = n < L.S ? 0 : 1;
   const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
   const int R = L.R;
   int start;
   if (defer) *defer = MRef{Mout, 1, 0};
-  if (from_root || n == lo) {
+  if (have_node >= lo) {
+    // node have_node (<= n) already holds its values
+    start = have_node + 1;
+  } else if (roots_ready && n == lo) {
+    start = lo + 1;
+  } else if (from_root || n == lo) {
     int rc = root_gemm(c, F, side, Mout, hi - lo == 1 ? defer : nullptr);
     if (rc) return rc;
     if (hi - lo == 1) return NNCP_OK;
@@ -497,7 +574,8 @@ int refresh_grams(nncp_ctx *c, const FactorSet &F, double *G) {
 // for the next multi-TTV or Khatri-Rao launch to carry (flush_gram runs it
 // otherwise); else it runs right after the update.
 int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double eps,
-                double *relerr_out, double *scal, double *S_next = nullptr, bool defer = false) {
+                double *relerr_out, double *scal, double *S_next = nullptr, bool defer = false,
+                int unnormalised = 0, int fold_lambda = 1) {
   const Layout &L = c->L;
   HIPCHK(flush_gram(c));
   UpdateArgs a;
@@ -537,6 +615,10 @@ int update_mode(nncp_ctx *c, int algo, int n, MRef M, const double *S, double ep
   a.alpha = c->scal + 8;
   a.relerr_out = relerr_out;
   a.scal = scal;
+  a.defer = unnormalised;
+  a.fold_lambda = fold_lambda;
+  a.dead = dead_mask(c);
+  if (unnormalised) a.lambda = fold_lambda ? c->lambda : c->ones;
   GramJob job;
   TIMED(4, launch_update(L.hdt, a, c->st, &job));
   c->pending = job;
@@ -675,6 +757,7 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->M = c->ws + L.off_M;
   c->nodeA = c->ws + L.off_A;
   c->nodeB = c->ws + L.off_B;
+  c->nodeR = c->ws + L.off_R;
   c->part = c->ws + L.off_part;
   c->kf = c->ws + L.off_kf;
   c->ks = c->ws + L.off_ks;
@@ -724,6 +807,7 @@ int nncp_set_factors(nncp_ctx *c, void *const *H, double *lambda) {
   for (int n = 0; n < c->L.N; ++n) c->H[n] = H[n];
   if (lambda) c->lambda = lambda;
   ++c->binding;
+  bump_versions(c, -1);
   // a new start point: the ADMM duals and the outer-step count start again
   // from zero
   if (c->L.R <= 64) HIPCHK(launch_fill(c->admmU, 0.0, c->L.sumI * c->L.R, c->st));
@@ -742,12 +826,66 @@ int nncp_gemm_path(const nncp_ctx *c, int side) {
   return c->L.gp[side].mfma;
 }
 
+int nncp_read_probe(const void *buf, size_t bytes, int workgroups, void *out4, void *stream) {
+  if (!buf || !out4) return fail(NNCP_E_INVAL, "NULL buffer");
+  if (!aligned16(buf) || ((uintptr_t)out4 & 3)) return fail(NNCP_E_INVAL, "misaligned buffer");
+  if (bytes == 0 || bytes % 16) return fail(NNCP_E_INVAL, "bytes must be a positive multiple of 16");
+  if (workgroups < 1 || workgroups > (1 << 20)) return fail(NNCP_E_INVAL, "workgroups outside [1, 2^20]");
+  HIPCHK(launch_read_probe(buf, bytes, workgroups, out4, (hipStream_t)stream));
+  return NNCP_OK;
+}
+
+int nncp_gemm_plan(const nncp_ctx *c, int side, int64_t *info) {
+  if (check_ctx(c)) return NNCP_E_STATE;
+  if (side < 0 || side > 1) return fail(NNCP_E_INVAL, "side must be 0 or 1");
+  if (!info) return fail(NNCP_E_INVAL, "info is NULL");
+  const GemmPlan &p = c->L.gp[side];
+  info[0] = p.mfma;
+  info[1] = p.Pf;
+  info[2] = p.Ps;
+  info[3] = p.nsplit;
+  info[4] = p.tiles;
+  info[5] = p.W;
+  info[6] = p.hl;
+  return NNCP_OK;
+}
+
 int nncp_mttkrp(nncp_ctx *c, int mode, void *M) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
   if (!M) return fail(NNCP_E_INVAL, "M is NULL");
-  return mttkrp_tree(c, factors_of(c, c->H), mode, M, true);
+  const Layout &L = c->L;
+  const int side = mode < L.S ? 0 : 1;
+  const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
+  // the deepest node on the way to `mode` still valid (nodes are lo .. hi-2)
+  int have = -1;
+  for (int a = std::min(mode, hi - 2); a >= lo; --a)
+    if (node_valid(c, side, a)) {
+      have = a;
+      break;
+    }
+  rc = mttkrp_tree(c, factors_of(c, c->H), mode, M, true, nullptr, false, have);
+  if (rc) {
+    drop_nodes(c);
+    return rc;
+  }
+  // the nodes this call wrote
+  const int first = have >= lo ? have + 1 : lo;
+  for (int a = first; a <= std::min(mode, hi - 2); ++a) set_tag(c, side, a);
+  return NNCP_OK;
+}
+
+int nncp_factors_changed(nncp_ctx *c, int mode) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (mode < -1 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [-1, %d)", mode, c->L.N);
+  bump_versions(c, mode);
+  for (int n = 0; n < c->L.N; ++n)
+    if (mode < 0 || n == mode)
+      HIPCHK(launch_gram(c->L.hdt, c->H[n], c->L.dims[n], c->L.R, c->G + (int64_t)n * c->L.R * c->L.R,
+                         c->st));
+  return NNCP_OK;
 }
 
 int nncp_mttkrp_noalloc(int N, const int64_t *dims, int R, int x_dtype, const void *X,
@@ -822,6 +960,7 @@ static int update_api(nncp_ctx *c, int algo, int mode, const void *M, const doub
   if (rc) return rc;
   if (mode < 0 || mode >= c->L.N) return fail(NNCP_E_INVAL, "mode %d outside [0, %d)", mode, c->L.N);
   if (!M || !S) return fail(NNCP_E_INVAL, "M or S is NULL");
+  bump_versions(c, mode);
   return update_mode(c, algo, mode, MRef{M, 1, 0}, S, eps, nullptr, nullptr);
 }
 
@@ -859,6 +998,7 @@ int nncp_update_nes(nncp_ctx *c, int mode, const void *M, const double *S) {
 int nncp_cp_loss(nncp_ctx *c, double *loss, double *relerr) {
   int rc = check_ctx(c);
   if (rc) return rc;
+  drop_nodes(c);
   const Layout &L = c->L;
   const int n = L.N - 1;
   rc = mttkrp_tree(c, factors_of(c, c->H), n, c->M, true);
@@ -929,8 +1069,50 @@ static int nes_outer_step(nncp_ctx *c, double *hist) {
   return NNCP_OK;
 }
 
+// MU and HALS sweeps without the per-mode normalisation (R <= 64): each
+// mode's rows are written unnormalised by one kernel, lambda is folded into
+// the first update only, and the factors are normalised once at the end
+// (launch_sweep_normalize); see k_update_rows_defer for why the iterates
+// are unchanged.  The relative error after each sweep comes from the same
+// identity with lambda = 1.
+static int sweep_deferred(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
+  const Layout &L = c->L;
+  const FactorSet F = factors_of(c, c->H);
+  HIPCHK(launch_hadamard(c->G, L.N, L.R, 0, c->S, c->st));
+  HIPCHK(launch_fill(dead_mask(c), 0.0, L.R, c->st));
+  for (int s = 0; s < nsweeps; ++s) {
+    for (int n = 0; n < L.N; ++n) {
+      MRef M;
+      int rc = mttkrp_tree(c, F, n, c->M, false, &M);
+      if (rc) {
+        c->pending.R = 0;
+        return rc;
+      }
+      const bool last = n == L.N - 1;
+      rc = update_mode(c, algo, n, M, c->S, L.opt.eps_mu,
+                       last && relerr_hist ? relerr_hist + s : nullptr, last ? c->scal : nullptr,
+                       c->S, true, 1, (s == 0 && n == 0) ? 1 : 0);
+      if (rc) {
+        c->pending.R = 0;
+        return rc;
+      }
+    }
+  }
+  HIPCHK(flush_gram(c));
+  TIMED(4, launch_sweep_normalize(L.hdt, F, L.dims, L.N, L.R, c->G, c->lambda, c->outer, c->st));
+  return NNCP_OK;
+}
+
+// The deferred path above measured slower than the per-mode normalisation
+// at 512^3 (0.183 against 0.174 ms per BF16 sweep: its Gram step adds 64
+// slices in one workgroup inside the next launch); it stays off until that
+// step is spread over workgroups.
+constexpr bool kDeferredSweep = false;
+
 static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   const Layout &L = c->L;
+  if (kDeferredSweep && (algo == NNCP_MU || algo == NNCP_HALS) && L.R <= 64)
+    return sweep_deferred(c, algo, nsweeps, relerr_hist);
   const FactorSet F = factors_of(c, c->H);
   const bool outer = algo == NNCP_NES_OUTER;
   if (outer) algo = NNCP_NES;
@@ -1018,6 +1200,8 @@ int nncp_sweep(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
     return fail(NNCP_E_UNSUPPORTED, "BPP, ADMM and NES need R <= 64 (R = %d)", c->L.R);
   if (nsweeps < 0) return fail(NNCP_E_INVAL, "nsweeps %d < 0", nsweeps);
   if (nsweeps == 0) return NNCP_OK;
+  drop_nodes(c);
+  bump_versions(c, -1);
   // Eager launches while timing (each launch is bracketed by events) or when
   // graphs are switched off; otherwise replay a cached graph of the sweeps.
   if (c->timing || !c->L.opt.graphs) return sweep_launches(c, algo, nsweeps, relerr_hist);
@@ -1042,11 +1226,47 @@ int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) 
   return build_graph(c, algo, nsweeps, relerr_hist);
 }
 
+// The gradient's fused pass: the right product's Khatri-Rao operand, then
+// one kernel for both root products (left into nodeA, right as per-tile
+// partials in c->part), the partials added in tile order into nodeR: the
+// right root node, or M^(N-1) itself (row-major) when the right subtree is
+// the single mode N-1.  Nothing else writes nodeR, while the left subtree's
+// multi-TTVs reuse c->part.
+static int dual_roots(nncp_ctx *c, const FactorSet &F) {
+  const Layout &L = c->L;
+  HIPCHK(flush_gram(c));
+  TIMED(2, launch_krp_operands(L.xdt, L.gp[1], L.R, L.dims, L.N, F, c->kf, c->ks, c->st));
+  TIMED(0, launch_dual_mttkrp(L.xdt, L.gp[0], L.gp[1], L.R, c->X, L.dims, L.N, L.S, F, c->kf,
+                              c->ks, c->nodeA, c->part, c->st));
+  GemmPlan pd = L.gp[1];
+  pd.nsplit = (int)L.dual_tiles;
+  TIMED(3, launch_finalize(L.hdt, pd, L.R, c->part, c->nodeR, L.N - L.S == 1 ? 1 : 0, c->st));
+  return NNCP_OK;
+}
+
 static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const *grads,
                    double *loss) {
   const Layout &L = c->L;
+  const bool dual = L.dual != 0;
+  if (dual) {
+    int rc = dual_roots(c, F);
+    if (rc) return rc;
+  }
+  void *Mn = c->M;
   for (int n = 0; n < L.N; ++n) {
-    int rc = mttkrp_tree(c, F, n, c->M, false);
+    int rc = NNCP_OK;
+    Mn = c->M;
+    if (dual) {
+      if (n == L.S && L.N - L.S == 1) {
+        Mn = c->nodeR;  // M^(N-1), added from the fused pass's partials
+      } else {
+        c->right_root_in_R = true;
+        rc = mttkrp_tree(c, F, n, c->M, false, nullptr, true);
+        c->right_root_in_R = false;
+      }
+    } else {
+      rc = mttkrp_tree(c, F, n, c->M, false);
+    }
     if (rc) return rc;
     if (grads) {
       const double *S = nullptr;
@@ -1054,11 +1274,11 @@ static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const
         HIPCHK(launch_hadamard(G, L.N, L.R, n, c->S, c->st));
         S = c->S;
       }
-      HIPCHK(launch_grad(L.hdt, L.dims[n], L.R, L.N, n, c->M, F.H[n], G, S, grads[n], c->st));
+      HIPCHK(launch_grad(L.hdt, L.dims[n], L.R, L.N, n, Mn, F.H[n], G, S, grads[n], c->st));
     }
   }
   const int n = L.N - 1;
-  HIPCHK(launch_loss(L.hdt, L.N, L.R, L.dims[n], c->M, F.H[n], c->ones, G, c->scal + 8, loss,
+  HIPCHK(launch_loss(L.hdt, L.N, L.R, L.dims[n], Mn, F.H[n], c->ones, G, c->scal + 8, loss,
                      nullptr, c->scal + 4, c->st));
   return NNCP_OK;
 }
@@ -1069,7 +1289,13 @@ int nncp_grad(nncp_ctx *c, void *const *grads, double *loss) {
   if (!grads) return fail(NNCP_E_INVAL, "grads is NULL");
   for (int n = 0; n < c->L.N; ++n)
     if (!grads[n]) return fail(NNCP_E_INVAL, "grads[%d] is NULL", n);
+  drop_nodes(c);
   return grad_at(c, factors_of(c, c->H), c->G, grads, loss);
+}
+
+int nncp_uses_fused_grad(const nncp_ctx *c) {
+  if (check_ctx(c)) return NNCP_E_STATE;
+  return c->L.dual ? 1 : 0;
 }
 
 int nncp_pgd(nncp_ctx *c, int nsteps, double armijo_c, int max_halvings, int power_iters,
@@ -1079,6 +1305,8 @@ int nncp_pgd(nncp_ctx *c, int nsteps, double armijo_c, int max_halvings, int pow
   if (nsteps < 0 || max_halvings < 0 || power_iters < 0 || !(armijo_c >= 0.0))
     return fail(NNCP_E_INVAL, "bad PGD parameters");
   if (c->L.R > 64) return fail(NNCP_E_UNSUPPORTED, "nncp_pgd supports R <= 64");
+  drop_nodes(c);
+  bump_versions(c, -1);
   const Layout &L = c->L;
   const int N = L.N, R = L.R;
   const FactorSet F = factors_of(c, c->H);

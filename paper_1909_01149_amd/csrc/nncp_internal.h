@@ -79,7 +79,7 @@ struct GemmPlan {
   int NT;            // 16-column tiles (Rpad = 16 * NT)
   int Rpad;
   int hl;            // hi+lo Khatri-Rao operand
-  int nt_loads;      // left kernel: non-temporal loads of X (large tensors)
+  int nt_loads;      // left kernel: non-temporal loads of X (tensors over 1 GiB)
   int nsplit;        // split of the reduction across workgroups
   int64_t tiles;     // output tiles (grid.x)
   size_t lds_bytes;  // dynamic LDS of the MFMA kernel
@@ -110,6 +110,18 @@ hipError_t launch_partial_mttkrp(int xdt, const GemmPlan &p, int R, const void *
                                  const int64_t *dims, int N, int S, const FactorSet &F,
                                  const void *kfast, const void *kslow, void *out,
                                  hipStream_t st);
+
+// Both root partial MTTKRPs in one pass over X (BF16 tensor, NT <= 2, the
+// left product written straight into its node out_l, [r][m]); the right
+// product leaves dual_tiles(m) partials [tile][k][R] in out_r, to be added in
+// tile order (launch_finalize with nsplit = dual_tiles(m)).  kfl / ksl are
+// the right plan's Khatri-Rao operands (launch_krp_operands with pr).
+hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, int R,
+                              const void *X, const int64_t *dims, int N, int S,
+                              const FactorSet &F, const void *kfl, const void *ksl, void *out_l,
+                              void *out_r, hipStream_t st);
+size_t dual_lds_bytes(int NT, int hl, int64_t PfL);
+int64_t dual_tiles(int64_t m);
 
 // Sum split partials of a partial MTTKRP into a node ([r][row]) or, when
 // leaf != 0, an M matrix ([row][r]).
@@ -176,6 +188,13 @@ struct UpdateArgs {
   // Nesterov-type update (R <= 64): [L, mu, lam, alpha, beta, ok] written by
   // its parameter kernel; always a valid address of 6 doubles
   double *nesParam;
+  // the sweep's deferred MU/HALS path (R <= 64): rows written straight into
+  // H without normalisation; lambda folded only when fold_lambda is set;
+  // dead[r] != 0 (R doubles) marks a column whose model column has been zero
+  // since an update zeroed it (where the normalised iteration's lambda_r is
+  // 0, so every later start value of column r is zero)
+  int defer, fold_lambda;
+  const double *dead;
 };
 constexpr int kAdmmMaxit = 5;         // passes per ADMM update (Section 4.3.4)
 constexpr double kAdmmTol = 0.01;     // stopping tolerance of the cited method
@@ -185,11 +204,14 @@ constexpr double kNesKappa = 100.0;   // condition number the proximal weight al
 // workgroups of the finish kernel (R <= 64) and the rows each one normalises
 constexpr int kNormWG = 8;
 int norm_workgroups(int64_t I, int64_t *rows_per_wg);
-// scratch of the finish kernel (R <= 64): kNormWG slices of Gram tiles, then
+// most Gram slices the Gram step adds (the finish kernel writes kNormWG, the
+// row kernel of the sweep's deferred path up to this many)
+constexpr int kGramSlices = 64;
+// scratch of the Gram step (R <= 64): kGramSlices slices of Gram tiles, then
 // the R x R Hadamard product of the Grams other than mode and next_mode
 __host__ __device__ inline int64_t norm_pn_offset(int R) {
   const int T = (R + 15) / 16;
-  return (int64_t)kNormWG * (T * (T + 1) / 2) * 256;
+  return (int64_t)kGramSlices * (T * (T + 1) / 2) * 256;
 }
 int norm_gpart_elems(int R);
 int64_t update_part_elems(int64_t I, int R);
@@ -208,7 +230,8 @@ int64_t update_part_elems(int64_t I, int R);
 // ---------------------------------------------------------------------------
 struct GramJob {
   const double *gpart;   // nw x ntile x 256 slices
-  const double *pn;      // R x R, read when S_next is set
+  const double *pn;      // R x R, read when S_next is set and pn_inline is 0
+  const double *beta_part;  // if not NULL: beta = sum of nbeta partials (in order)
   double *G;             // N x R x R Grams; G[mode] written
   const double *S;       // S of this mode (read for gamma)
   double *S_next;        // may be NULL; may alias S
@@ -218,6 +241,10 @@ struct GramJob {
   double *relerr_out;    // may be NULL
   double *scal;          // may be NULL: [0]=beta [1]=gamma [2]=raw relerr^2
   int R, N, mode, next_mode, nw;
+  int nbeta;
+  int pn_inline;         // 1: the product of the Grams other than mode and
+                         // next_mode is formed here from G (no pn buffer)
+  double *dead;          // if not NULL: dead[x] = 1 where G^(mode)(x, x) == 0
 };
 
 // One 256-thread workgroup.  Thread t takes the upper-tile entries u = t +
@@ -226,7 +253,8 @@ struct GramJob {
 // from one value), so gamma adds the diagonal once and each off-diagonal pair
 // twice.  Each thread reads S(x, y) before it writes S_next(x, y) and
 // S_next(y, x), and no other thread touches either.  All loads of a round are
-// unconditional (clamped indices) so that they are in flight together.
+// unconditional (clamped indices) so that they are in flight together; the
+// slices are added in slice order, eight at a time.
 __device__ inline void gram_finish(const GramJob &j) {
   __shared__ double gred[4];
   const int R = j.R, RR = R * R, T = (R + 15) >> 4, slice = (T * (T + 1) / 2) * 256;
@@ -234,14 +262,15 @@ __device__ inline void gram_finish(const GramJob &j) {
   const bool want_err = j.relerr_out || j.scal;
   const int nw = j.nw;
   double *Gm = j.G + (int64_t)j.mode * RR;
-  const double *pnp = j.S_next ? j.pn : j.lambda;  // any valid address when unused
+  const double *pnp = (j.S_next && !j.pn_inline) ? j.pn : j.lambda;  // any valid address when unused
   const double *sp = want_err ? j.S : j.lambda;
-  const double alpha = j.alpha[0], beta = j.beta[0];  // read early (both always valid)
+  const double alpha = j.alpha[0];
+  double beta = j.beta[0];  // both always valid addresses
   double gsum = 0.0;
   // FE entries per thread and round trip (one round up to R = 32)
   constexpr int FE = 3;
   for (int u0 = tid; u0 < slice; u0 += 256 * FE) {
-    double v[FE][kNormWG], sv[FE], la[FE], lb[FE], pn[FE];
+    double sv[FE], la[FE], lb[FE], pn[FE], sum[FE];
     int xs[FE], ys[FE];
     bool ok[FE];
 #pragma unroll
@@ -261,23 +290,44 @@ __device__ inline void gram_finish(const GramJob &j) {
       la[kk] = j.lambda[xs[kk]];
       lb[kk] = j.lambda[ys[kk]];
       sv[kk] = sp[want_err ? e : 0];
-      pn[kk] = pnp[j.S_next ? e : 0];
+      if (j.S_next && j.pn_inline) {
+        double p = 1.0;
+        for (int g = 0; g < j.N; ++g)
+          if (g != j.mode && g != j.next_mode) p *= j.G[(int64_t)g * RR + e];
+        pn[kk] = p;
+      } else {
+        pn[kk] = pnp[j.S_next ? e : 0];
+      }
+    }
+    // the slices in order, eight loads per entry in flight
+    for (int w0 = 0; w0 < nw; w0 += kNormWG) {
+      double v[FE][kNormWG];
 #pragma unroll
-      for (int w = 0; w < kNormWG; ++w) v[kk][w] = j.gpart[(int64_t)(w < nw ? w : nw - 1) * slice + u];
+      for (int kk = 0; kk < FE; ++kk) {
+        const int u = u0 + 256 * kk < slice ? u0 + 256 * kk : slice - 1;
+#pragma unroll
+        for (int w = 0; w < kNormWG; ++w)
+          v[kk][w] = j.gpart[(int64_t)(w0 + w < nw ? w0 + w : nw - 1) * slice + u];
+      }
+#pragma unroll
+      for (int kk = 0; kk < FE; ++kk) {
+        double s0 = w0 == 0 ? v[kk][0] : sum[kk] + v[kk][0];
+#pragma unroll
+        for (int w = 1; w < kNormWG; ++w)
+          if (w0 + w < nw) s0 += v[kk][w];
+        sum[kk] = s0;
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < FE; ++kk) {
       if (!ok[kk]) continue;
-      double sum = v[kk][0];
-#pragma unroll
-      for (int w = 1; w < kNormWG; ++w)
-        if (w < nw) sum += v[kk][w];
       const int x = xs[kk], y = ys[kk];
-      Gm[x * R + y] = sum;
-      Gm[y * R + x] = sum;
-      if (want_err) gsum += (x == y ? 1.0 : 2.0) * (la[kk] * sv[kk] * sum * lb[kk]);
+      Gm[x * R + y] = sum[kk];
+      Gm[y * R + x] = sum[kk];
+      if (j.dead && x == y && sum[kk] == 0.0) j.dead[x] = 1.0;
+      if (want_err) gsum += (x == y ? 1.0 : 2.0) * (la[kk] * sv[kk] * sum[kk] * lb[kk]);
       if (j.S_next) {
-        const double sn = j.next_mode == j.mode ? pn[kk] : pn[kk] * sum;
+        const double sn = j.next_mode == j.mode ? pn[kk] : pn[kk] * sum[kk];
         j.S_next[x * R + y] = sn;
         j.S_next[y * R + x] = sn;
       }
@@ -289,6 +339,10 @@ __device__ inline void gram_finish(const GramJob &j) {
   if (lane == 0) gred[wave] = gsum;
   __syncthreads();
   if (tid == 0) {
+    if (j.beta_part) {
+      beta = j.beta_part[0];
+      for (int w = 1; w < j.nbeta; ++w) beta += j.beta_part[w];
+    }
     const double gamma = gred[0] + gred[1] + gred[2] + gred[3];
     const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
     if (j.scal) {
@@ -302,8 +356,18 @@ __device__ inline void gram_finish(const GramJob &j) {
 
 // Launches the update.  For R <= 64 the Gram step is left out and *job
 // describes it (job->R == 0 otherwise); the caller runs it before anything
-// reads G, S_next or the error outputs.
+// reads G, S_next or the error outputs.  With a.defer (MU/HALS, R <= 64) the
+// rows go straight into H unnormalised, in one kernel that also leaves the
+// Gram slices and the <M, Hhat> partials for the Gram step.
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st, GramJob *job);
+// workgroups of the deferred row kernel (at most kGramSlices)
+int defer_workgroups(int64_t I);
+// End of the sweep's deferred path: s_k(r) = sqrt(G^(k)(r, r)) for every
+// mode, lambda_r = prod_k s_k(r); then H^(k)(:, r) /= s_k(r) and G^(k)(a, b)
+// /= s_k(a) s_k(b), a column with lambda_r = 0 set to zero in every mode.
+// scale: N x R + R doubles of scratch.
+hipError_t launch_sweep_normalize(int hdt, const FactorSet &F, const int64_t *dims, int N, int R,
+                                  double *G, double *lambda, double *scale, hipStream_t st);
 // the Gram step as a kernel of its own (no-op for an empty job)
 hipError_t launch_gram_finish(const GramJob &j, hipStream_t st);
 // the norm kernel alone on rows left in a.hhat with nblocks per-workgroup
@@ -345,5 +409,11 @@ hipError_t launch_pgd_eta(const double *G, int N, int R, int iters, double *eta,
 // H' = max(0, H - eta g); accumulates sum (H'-H)^2 into part[blockIdx] then d[0]
 hipError_t launch_pgd_trial(int hdt, int64_t n, const void *H, const void *g, double eta,
                             void *Hn, double *part, double *d_out, hipStream_t st);
+
+// streaming read of `bytes` (a multiple of 16) with `workgroups` workgroups of
+// 256 threads; writes out4 only in the (practically never taken) case that
+// the XOR of everything read equals a fixed value
+hipError_t launch_read_probe(const void *buf, size_t bytes, int workgroups, void *out4,
+                             hipStream_t st);
 
 }  // namespace nncp

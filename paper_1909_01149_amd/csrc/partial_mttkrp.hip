@@ -101,6 +101,11 @@ template <typename VT> __device__ __forceinline__ VT gload_c(const void *p) {
   return *(gvt *)p;
 }
 
+template <bool NTL, typename VT> __device__ __forceinline__ VT xload(const void *p) {
+  if constexpr (NTL) return gload<VT>(p);
+  else return gload_c<VT>(p);
+}
+
 template <typename CT> __device__ __forceinline__ void czero(CT &c) {
   c[0] = 0; c[1] = 0; c[2] = 0; c[3] = 0;
 }
@@ -205,7 +210,7 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
 // out: [nsplit][k][R] partial sums (factor type).
 // ---------------------------------------------------------------------------
 
-template <typename XT, int MT, int NT, bool HL, bool SLOW, int U>
+template <typename XT, int MT, int NT, bool HL, bool SLOW, int U, bool ILV>
 __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
     const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
     const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int64_t steps_total, int nsplit,
@@ -295,6 +300,52 @@ __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
     }
   };
 
+  if constexpr (ILV) {
+    // The workgroup's steps in batches of U, dealt to the waves in turn
+    // (wave w takes batches w, w + kRightWaves, ...): at any time the waves
+    // read neighbouring pieces of the same 16 MT rows (kRightWaves x U x 64
+    // bytes of each row together, as the left kernel's waves do), instead
+    // of kRightWaves distant ranges.  Current/next buffers; the batch after
+    // the last re-reads the last one.  A block of the Khatri-Rao operand cut
+    // by the end of a batch is flushed with its slow factor there; the
+    // steps after the last full batch go to the wave next in turn.
+    const int64_t nb = (s_hi - s_lo) / U;
+    u32x4 cur[U][MT], nxt[U][MT];
+    auto load = [&](u32x4 (&dst)[U][MT], int64_t b) {
+      const int64_t t0 = s_lo + (b < nb ? b : nb - 1) * U;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) dst[u][mt] = gload_c<u32x4>(xp[mt] + (t0 + u) * KSTEP);
+    };
+    int64_t b = wave;
+    if (b < nb) load(cur, b);
+    for (; b < nb; b += kRightWaves) {
+      load(nxt, b + kRightWaves);
+      const int64_t t0 = s_lo + b * U;
+      pf = (int)(t0 % spb) * KSTEP;
+      bI = t0 / spb;
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(cur[u]);
+      if (SLOW && pf != 0) flush();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) cur[u][mt] = nxt[u][mt];
+    }
+    if (wave == (int)(nb % kRightWaves) && s_lo + nb * U < s_hi) {
+      const int64_t t0 = s_lo + nb * U;
+      pf = (int)(t0 % spb) * KSTEP;
+      bI = t0 / spb;
+      for (int64_t tt = t0; tt < s_hi; ++tt) {
+        u32x4 va[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) va[mt] = gload_c<u32x4>(xp[mt] + tt * KSTEP);
+        step(va);
+      }
+      if (SLOW && pf != 0) flush();
+    }
+  } else {
   // batches of U steps, the next batch's loads issued before the current
   // batch is consumed.  16-bit and FP64 tensors: current/next buffers with a
   // copy (the last batch re-reads itself instead of running past the wave's
@@ -364,6 +415,7 @@ __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
   }
   // a fast block cut by the end of the wave's range
   if (SLOW && pf != 0) flush();
+  }
   if (!SLOW) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
@@ -633,6 +685,280 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
   }
 }
 
+// Cross-lane exchange through LDS inside one wave: the wave's LDS accesses
+// are performed in order, so a wavefront-scope fence with a scheduling
+// barrier is all that orders one lane's write before another lane's read.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Both partial MTTKRPs of the root in one pass over X (the gradient, where
+// every mode's MTTKRP is taken at the same factors):
+//   left   T_L[i, r] = sum_j Xr[j, i] K_R(j, r)    (reduce over rows)
+//   right  T_R[j, r] = sum_i Xr[j, i] K_L(i, r)    (reduce over columns)
+// BF16 tensors, R <= 32.  A workgroup is kDualWaves waves on 128 consecutive
+// columns each and walks every row in steps of 32; lane (rho, g) loads rows
+// 8g .. 8g+7 of the step at columns 8 rho .. 8 rho+7 of its wave, eight
+// 16-byte loads, as the left kernel does.
+//  * T_L: the left kernel's in-lane transpose into A operands; the B operand
+//    is K_R itself, the slow factor already folded in: rows of K_R are staged
+//    in LDS a window of kDualWin rows at a time, each entry formed in FP64
+//    from the factors and split hi + lo, between two barriers when the rows
+//    cross into the next window.  No per-block accumulators are needed.
+//  * T_R: each lane also writes its eight 16-byte row pieces into a
+//    wave-private LDS tile (16-byte chunks XOR-swizzled by row) and reads the
+//    A operands (16 rows x 32 columns) back from it; the B operands are the
+//    fast part of K_L (staged once); the product of each 32-column chunk is
+//    scaled by the slow part of K_L at its columns (fixed for the wave, held
+//    in registers) before it is added.  The waves' 32 x R results of a step
+//    are added in wave order through LDS (two slot sets used in turn, one
+//    barrier per step) and written as the workgroup's partial
+//    out_r[tile][j][r]; the tiles' partials are added in tile order
+//    afterwards by k_finalize.
+// ---------------------------------------------------------------------------
+constexpr int kDualWaves = 8;
+constexpr int kDualWin = 128;
+
+struct DualArgs {
+  KrpArgs kr;          // the factors; K_R(j, r) = prod over modes kr_lo..kr_hi-1
+  int kr_lo, kr_hi;
+  int64_t m, k;
+  int PfL;             // fast length of K_L (a multiple of 32), staged whole
+  int R;
+};
+
+template <typename XT, int NT, bool HL, bool NTL>
+__global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
+    const XT *__restrict__ X, DualArgs a, const XT *__restrict__ kfl,
+    const float *__restrict__ ksl, float *__restrict__ out_l, float *__restrict__ out_r) {
+  typedef f32x4 CT;
+  constexpr int WV = kDualWaves, QV = 8, KL = 8, KSTEP = 32, RP = 16 * NT;
+  constexpr int SVEC = 8;  // elements per 16-byte chunk
+  extern __shared__ __align__(16) unsigned char smem[];
+  // LDS: K_R window [HL+1][RP][kDualWin] | K_L fast part [HL+1][RP][ldl] |
+  //      X tiles [WV][32][128] | T_R slots [2][WV][64 * 4 * 2 * NT] floats
+  const int ldl = ((a.PfL / SVEC) % 16 == 0) ? a.PfL : a.PfL + SVEC;
+  const int swl = ((a.PfL / SVEC) % 16 == 0) ? 15 : 0;
+  XT *skr = reinterpret_cast<XT *>(smem);
+  XT *skl = skr + (HL ? 2 : 1) * RP * kDualWin;
+  XT *sxt = skl + (HL ? 2 : 1) * RP * ldl;
+  constexpr int SLOT = 64 * 4 * 2 * NT;  // floats per wave and step
+  float *str = reinterpret_cast<float *>(sxt + WV * 32 * 128);
+  const int m = (int)a.m;  // m < 2^31 (checked by the planner)
+  const int64_t k = a.k;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rho = lane & 15, g = lane >> 4;
+  const int64_t c0w = ((int64_t)blockIdx.x * WV + wave) * 128;  // the wave's first column
+  const int64_t il = c0w + QV * rho;
+  const bool valid = il < m;
+  const XT *xp = X + (valid ? il : 0) + (int64_t)(g * KL) * m;
+
+  // K_L fast part, staged once (the 16-byte chunks of row r XOR-swizzled with
+  // r & swl, as in the other kernels)
+  {
+    const int nv = a.PfL / SVEC;
+    const int total = RP * nv * (HL ? 2 : 1);
+    for (int e = tid; e < total; e += 64 * WV) {
+      const int h = e / (RP * nv);
+      const int rem = e - h * RP * nv;
+      const int r = rem / nv, v = rem - r * nv;
+      *reinterpret_cast<u32x4 *>(skl + h * RP * ldl + kidx<XT>(r, v * SVEC, ldl, swl)) =
+          *reinterpret_cast<const u32x4 *>(kfl + ((int64_t)(h * RP + r)) * a.PfL + v * SVEC);
+    }
+  }
+  // the slow factor of K_L at the wave's four 32-column chunks, and the fast
+  // offset of each chunk (a chunk never crosses a fast block: PfL % 32 == 0)
+  float ks[4][NT];
+  int pfl[4];
+  bool cok[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t col = c0w + 32 * c + 8 * g;  // this lane's 8 columns as an A operand
+    cok[c] = col < m;
+    const int64_t cc = c0w + 32 * c < m ? c0w + 32 * c : 0;
+    pfl[c] = (int)(cc % a.PfL);
+    const int64_t sidx = cc / a.PfL;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) ks[c][nt] = ksl[sidx * RP + 16 * nt + rho];
+  }
+  // K_R window: rows wbase .. wbase + kDualWin of K_R, hi (+ lo), formed in FP64
+  auto stage_kr = [&](int64_t wbase) {
+    const int total = RP * kDualWin;
+    for (int e = tid; e < total; e += 64 * WV) {
+      const int r = e / kDualWin, p = e - r * kDualWin;
+      const int64_t j = wbase + p;
+      const double v = (r < a.R && j < k) ? krp_entry<float>(a.kr, a.kr_lo, a.kr_hi, j, r) : 0.0;
+      const XT hi = from_d<XT>(v);
+      skr[kidx<XT>(r, p, kDualWin, 15)] = hi;
+      if (HL) skr[RP * kDualWin + kidx<XT>(r, p, kDualWin, 15)] = from_d<XT>(v - to_d<XT>(hi));
+    }
+  };
+
+  CT acc[QV][NT], cr[2][NT];
+#pragma unroll
+  for (int q = 0; q < QV; ++q)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) czero(acc[q][nt]);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) czero(cr[h][nt]);
+
+  XT *xt = sxt + wave * 32 * 128;
+  const int64_t steps = k / KSTEP;
+  constexpr int NB = 2;
+  u32x4 buf[NB][KL];
+  auto load_step = [&](u32x4 *dst, int64_t t) {
+    const int64_t tt = t < steps ? t : steps - 1;
+#pragma unroll
+    for (int u = 0; u < KL; ++u) dst[u] = xload<NTL, u32x4>(xp + (tt * KSTEP + u) * (int64_t)m);
+  };
+  load_step(buf[0], 0);
+  int64_t wcur = -1;
+  for (int64_t t0 = 0; t0 < steps; t0 += NB) {
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+      const int64_t t = t0 + jb;
+      load_step(buf[(jb + 1) % NB], t + 1);
+      if (t >= steps) break;
+      const u32x4 *rw = buf[jb];
+      const int64_t j0 = t * KSTEP;
+      const int64_t wb = j0 / kDualWin * kDualWin;
+      if (wb != wcur) {
+        __syncthreads();
+        stage_kr(wb);
+        __syncthreads();
+        wcur = wb;
+      }
+      // ---- T_L: as the left kernel, B = K_R rows j0 - wb + 8g ..
+      {
+        u32x4 vb[NT], vbl[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const XT *bp = skr + kidx<XT>(16 * nt + rho, (int)(j0 - wb) + g * KL, kDualWin, 15);
+          vb[nt] = *reinterpret_cast<const u32x4 *>(bp);
+          if (HL) vbl[nt] = *reinterpret_cast<const u32x4 *>(bp + RP * kDualWin);
+        }
+#pragma unroll
+        for (int q = 0; q < QV; ++q) {
+          const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
+          u32x4 av;
+          av.x = __builtin_amdgcn_perm(rw[1][q >> 1], rw[0][q >> 1], sel);
+          av.y = __builtin_amdgcn_perm(rw[3][q >> 1], rw[2][q >> 1], sel);
+          av.z = __builtin_amdgcn_perm(rw[5][q >> 1], rw[4][q >> 1], sel);
+          av.w = __builtin_amdgcn_perm(rw[7][q >> 1], rw[6][q >> 1], sel);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            mma16(acc[q][nt], av, vb[nt], (XT *)nullptr);
+            if (HL) mma16(acc[q][nt], av, vbl[nt], (XT *)nullptr);
+          }
+        }
+      }
+      // ---- T_R: the step's 32 rows through the wave's LDS tile
+      wave_sync_lds();
+#pragma unroll
+      for (int u = 0; u < KL; ++u) {
+        const int row = 8 * g + u;
+        *reinterpret_cast<u32x4 *>(xt + row * 128 + ((rho ^ (row & 15)) * SVEC)) = rw[u];
+      }
+      wave_sync_lds();
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        u32x4 ar[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = 16 * h + rho;
+          ar[h] = *reinterpret_cast<const u32x4 *>(xt + row * 128 + (((4 * c + g) ^ (row & 15)) * SVEC));
+          if (!cok[c]) ar[h] = u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const XT *bp = skl + kidx<XT>(16 * nt + rho, pfl[c] + g * KL, ldl, swl);
+          const u32x4 bh = *reinterpret_cast<const u32x4 *>(bp);
+          u32x4 bl;
+          if (HL) bl = *reinterpret_cast<const u32x4 *>(bp + RP * ldl);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            CT tmp;
+            czero(tmp);
+            mma16(tmp, ar[h], bh, (XT *)nullptr);
+            if (HL) mma16(tmp, ar[h], bl, (XT *)nullptr);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cr[h][nt][v] += tmp[v] * ks[c][nt];
+          }
+        }
+      }
+      // ---- the waves' T_R results of this step, added in wave order
+      float *slot = str + ((int)(t & 1) * WV + wave) * SLOT;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          *reinterpret_cast<f32x4 *>(slot + lane * (8 * NT) + (h * NT + nt) * 4) = cr[h][nt];
+          czero(cr[h][nt]);
+        }
+      __syncthreads();
+      // output (row jj of the step, column r): lane (r % 16) + 16 ((jj % 16) / 4),
+      // entry (jj / 16, r / 16, jj % 4) of its fragments
+      for (int e = tid; e < 32 * RP; e += 64 * WV) {
+        const int jj = e / RP, r = e - jj * RP;
+        const int sl = (r & 15) + 16 * ((jj & 15) >> 2);
+        const int off = sl * (8 * NT) + ((jj >> 4) * NT + (r >> 4)) * 4 + (jj & 3);
+        const float *sb = str + (int)(t & 1) * WV * SLOT;
+        float s = sb[off];
+#pragma unroll
+        for (int w = 1; w < WV; ++w) s += sb[w * SLOT + off];
+        const int64_t j = j0 + jj;
+        if (r < a.R && j < k) out_r[((int64_t)blockIdx.x * k + j) * a.R + r] = s;
+      }
+    }
+  }
+
+  // ---- T_L epilogue (as the left kernel): 16 result columns at a time
+  // through LDS so that every store writes whole 16-byte pieces
+  constexpr int CW = 16 * QV, VE = 4, LDW = CW + VE, LPR = CW / VE, RPI = 64 / LPR;
+  float *eb = reinterpret_cast<float *>(smem) + wave * 16 * LDW;
+  const bool vec_ok = (m % VE) == 0;
+  const int64_t i0 = c0w;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float *dst = eb + rho * LDW + QV * (4 * g + v);
+#pragma unroll
+      for (int q0 = 0; q0 < QV; q0 += VE) {
+        f32x4 tv;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) tv[e] = acc[q0 + e][nt][v];
+        *reinterpret_cast<f32x4 *>(dst + q0) = tv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += RPI) {
+      const int rr = r0 + lane / LPR, cc = (lane % LPR) * VE;
+      const int r = 16 * nt + rr;
+      const int64_t col = i0 + cc;
+      if (r < a.R && col < m) {
+        const float *src = eb + rr * LDW + cc;
+        float *gd = out_l + (int64_t)r * m + col;
+        if (vec_ok && col + VE <= m) {
+          *reinterpret_cast<f32x4 *>(gd) = *reinterpret_cast<const f32x4 *>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VE; ++e)
+            if (col + e < m) gd[e] = src[e];
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // portable vector-ALU partial MTTKRPs (any shape, any R; used when the
 // matrix-core preconditions are not met, and as a forced path)
@@ -799,8 +1125,11 @@ static void run_right(const GemmPlan &p, int R, const void *X, const void *kf, c
   typedef typename XTraits<XT>::AT AT;
   constexpr int KSTEP = 4 * XTraits<XT>::VEC;
   dim3 grid((unsigned)p.tiles, p.nsplit), block(64 * kRightWaves);
-  hipLaunchKernelGGL((k_gemm_right_mfma<XT, MT, NT, HL, SLOW, 4>), grid, block, p.lds_bytes, st,
-                     (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf,
+  // the waves take contiguous ranges (batches dealt in turn measured 1.5%
+  // faster at 512^3 BF16 but 3% slower on the 256^4 tensor)
+  constexpr bool ILV = false;
+  hipLaunchKernelGGL((k_gemm_right_mfma<XT, MT, NT, HL, SLOW, 4, ILV>), grid, block, p.lds_bytes,
+                     st, (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf,
                      (p.m / KSTEP), p.nsplit, R, (AT *)out);
 }
 
@@ -921,6 +1250,48 @@ hipError_t launch_partial_mttkrp(int xdt, const GemmPlan &p, int R, const void *
     case NNCP_F64: return dispatch_generic<double, double>(p, R, X, dims, N, S, F, out, st);
   }
   return hipErrorInvalidValue;
+}
+
+size_t dual_lds_bytes(int NT, int hl, int64_t PfL) {
+  const int RP = 16 * NT;
+  const int64_t ldl = ((PfL / 8) % 16 == 0) ? PfL : PfL + 8;
+  const size_t main = (size_t)(hl ? 2 : 1) * RP * kDualWin * 2 + (size_t)(hl ? 2 : 1) * RP * ldl * 2 +
+                      (size_t)kDualWaves * 32 * 128 * 2 + (size_t)2 * kDualWaves * 64 * 8 * NT * 4;
+  const size_t epi = (size_t)kDualWaves * 16 * (16 * 8 + 4) * 4;
+  return main > epi ? main : epi;
+}
+
+int64_t dual_tiles(int64_t m) { return (m + 128 * kDualWaves - 1) / (128 * kDualWaves); }
+
+hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, int R,
+                              const void *X, const int64_t *dims, int N, int S,
+                              const FactorSet &F, const void *kfl, const void *ksl, void *out_l,
+                              void *out_r, hipStream_t st) {
+  if (xdt != NNCP_BF16 || pl.NT > 2) return hipErrorInvalidValue;
+  DualArgs a;
+  a.kr = make_krp_args(pl, R, dims, F, N);
+  a.kr_lo = S;
+  a.kr_hi = N;
+  a.m = pl.m;
+  a.k = pl.k;
+  a.PfL = (int)pr.Pf;
+  a.R = R;
+  const size_t lds = dual_lds_bytes(pl.NT, pl.hl, pr.Pf);
+  dim3 grid((unsigned)dual_tiles(pl.m)), block(64 * kDualWaves);
+#define NNCP_DUAL(NTV, HLV, NTLV)                                                                 \
+  hipLaunchKernelGGL((k_gemm_dual_mfma<bf16_t, NTV, HLV, NTLV>), grid, block, lds, st,          \
+                     (const bf16_t *)X, a, (const bf16_t *)kfl, (const float *)ksl,              \
+                     (float *)out_l, (float *)out_r)
+  const bool ntl = pl.nt_loads != 0;
+  if (pl.NT == 1) {
+    if (pl.hl) { if (ntl) NNCP_DUAL(1, true, true); else NNCP_DUAL(1, true, false); }
+    else { if (ntl) NNCP_DUAL(1, false, true); else NNCP_DUAL(1, false, false); }
+  } else {
+    if (pl.hl) { if (ntl) NNCP_DUAL(2, true, true); else NNCP_DUAL(2, true, false); }
+    else { if (ntl) NNCP_DUAL(2, false, true); else NNCP_DUAL(2, false, false); }
+  }
+#undef NNCP_DUAL
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(int hdt, const GemmPlan &p, int R, const void *part, void *out,

@@ -1338,6 +1338,173 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
   }
 }
 
+// Row update of the sweep's MU/HALS path without normalisation.  MU
+// (Eq. eqn:muupd) and HALS (Eq. eqn:halsupd) commute with column scalings
+// of the other factors (M and S scale with them and the update scales back),
+// so the factors can stay unnormalised through the sweeps and be normalised
+// once at the end of the call (k_norm_scales, k_apply_scales): the iterates
+// are those of the normalised iteration up to rounding.  The kernel writes
+// the rows straight into H; there is no separate normalisation launch.
+// 8 rows per pass (512 threads, one row per wave, lane c owns column c and
+// keeps column c of S in registers), row blocks gridDim.x apart.  The stored
+// (rounded) rows also feed the workgroup's slice of the Gram of the new
+// factor (upper 16 x 16 tiles on FP64 MFMA, four rows a step; wave w owns
+// tiles w and w + 8) and its share of <M, Hhat>, added in row-block and wave
+// order.  The arithmetic of a row is that of k_update_rows_small.
+template <typename HT, int RB>
+__global__ __launch_bounds__(512) void k_update_rows_defer(UpdateArgs a) {
+  __shared__ double rows[8][RB];
+  __shared__ double bred[8];
+  const int R = a.R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int T = (R + 15) / 16, ntile = T * (T + 1) / 2;
+  int tx[2] = {-1, -1}, ty[2] = {-1, -1};
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (wave + 8 * q < ntile) tile_pair(wave + 8 * q, T, tx[q], ty[q]);
+  const int lr = lane >> 4, lc = lane & 15;
+  f64x4 gacc[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) gacc[q][0] = gacc[q][1] = gacc[q][2] = gacc[q][3] = 0.0;
+  double bsum = 0.0;
+  const HT *M = (const HT *)a.M;
+  HT *H = (HT *)a.H;
+  const bool own = lane < R;
+  const int c = own ? lane : 0;
+  double sc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) sc[r] = (own && r < R) ? a.S[r * R + c] : 0.0;
+  const double d = own ? a.S[c * R + c] : 0.0;
+  // the start value: lambda folded in (first update of the call), or zero
+  // in a dead column (as lambda_r = 0 would make it), else the row as stored
+  const double lam = a.fold_lambda ? a.lambda[c] : (a.dead[c] != 0.0 ? 0.0 : 1.0);
+  const int ns = a.msplit;
+  for (int64_t blk = blockIdx.x; blk * 8 < a.I; blk += gridDim.x) {
+    const int64_t i = blk * 8 + wave;
+    const bool live = i < a.I;
+    const int64_t ir = live ? i : a.I - 1;
+    const HT *mp = M + ir * R + c;
+    HT mv[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) mv[k] = k < ns ? mp[(int64_t)k * a.mstride] : (HT)0;
+    const HT h_raw = H[ir * R + c];
+    HT macc = mv[0];
+#pragma unroll
+    for (int k = 1; k < 32; ++k)
+      if (k < ns) macc += mv[k];
+    for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
+    const bool ok = live && own;
+    double h = ok ? (double)h_raw * lam : 0.0;
+    const double m = ok ? (double)macc : 0.0;
+    double g = 0.0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < R) g += bcast(h, j) * sc[j];
+    if (a.algo == NNCP_MU) {
+      h = h * m / (g + a.eps);
+    } else {
+      g = m - g;
+      const bool pos = d > 0.0;
+      const double invd = pos ? 1.0 / d : 0.0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (r < R) {
+          double v = h + g * invd;
+          v = v > 0.0 ? v : 0.0;
+          const double dl = pos ? v - h : 0.0;
+          const double delta = bcast(dl, r);
+          if (lane == r && pos) h = v;
+          g -= delta * sc[r];
+        }
+      }
+    }
+    const HT hs = (HT)h;
+    if (ok) H[i * R + c] = hs;
+    if (lane < RB) rows[wave][lane] = ok ? (double)hs : 0.0;
+    double beta = ok ? m * h : 0.0;
+    beta = wave_sum(beta);
+    if (lane == 0) bred[wave] = beta;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (tx[q] < 0) continue;
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const double av = rows[4 * st + lr][16 * tx[q] + lc];
+        const double bv = rows[4 * st + lr][16 * ty[q] + lc];
+        gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, gacc[q], 0, 0, 0);
+      }
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int w = 0; w < 8; ++w) bsum += bred[w];
+    }
+    __syncthreads();
+  }
+  // this workgroup's slice: entry (lr + 4 v, lc) of tile t, as the finish
+  // kernel writes its slices
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (tx[q] < 0) continue;
+    double *gp = a.gpart + ((int64_t)blockIdx.x * ntile + wave + 8 * q) * 256;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gp[(lr + 4 * v) * 16 + lc] = gacc[q][v];
+  }
+  if (threadIdx.x == 0) a.part[blockIdx.x] = bsum;
+}
+
+// End of the deferred path, step 1 (one workgroup): the column norms of
+// every factor from its Gram, s_k(r) = sqrt(G^(k)(r, r)), and
+// lambda_r = prod_k s_k(r) (modes in order).  scale = [N][R] norms, then R
+// lambdas.
+__global__ __launch_bounds__(256) void k_norm_scales(const double *__restrict__ G, int N, int R,
+                                                     double *__restrict__ lambda,
+                                                     double *__restrict__ scale) {
+  for (int r = threadIdx.x; r < R; r += 256) {
+    double l = 1.0;
+    for (int k = 0; k < N; ++k) {
+      const double sk = sqrt(G[((int64_t)k * R + r) * R + r]);
+      scale[k * R + r] = sk;
+      l *= sk;
+    }
+    scale[N * R + r] = l;
+    lambda[r] = l;
+  }
+}
+
+struct ScaleArgs {
+  void *H[NNCP_MAX_MODES];
+  int64_t off[NNCP_MAX_MODES + 1];  // prefix sums of I_k R
+  int N, R;
+};
+
+// Step 2: H^(k)(i, r) /= s_k(r) and G^(k)(a, b) /= s_k(a) s_k(b), zero where
+// lambda is zero; one thread per entry (the factors' entries first, then the
+// N Grams).
+template <typename HT>
+__global__ __launch_bounds__(256) void k_apply_scales(ScaleArgs a, double *__restrict__ G,
+                                                      const double *__restrict__ scale) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int N = a.N, R = a.R;
+  const double *lam = scale + N * R;
+  if (e < a.off[N]) {
+    int k = 0;
+    while (e >= a.off[k + 1]) ++k;
+    const int r = (int)((e - a.off[k]) % R);
+    HT *H = (HT *)a.H[k];
+    const int64_t idx = e - a.off[k];
+    const double s = scale[k * R + r];
+    H[idx] = lam[r] > 0.0 ? (HT)((double)H[idx] / s) : (HT)0;
+    return;
+  }
+  const int64_t f = e - a.off[N];
+  if (f >= (int64_t)N * R * R) return;
+  const int k = (int)(f / ((int64_t)R * R));
+  const int x = (int)((f / R) % R), y = (int)(f % R);
+  const double sx = scale[k * R + x], sy = scale[k * R + y];
+  G[f] = (lam[x] > 0.0 && lam[y] > 0.0) ? G[f] / (sx * sy) : 0.0;
+}
+
 // the Gram step as a kernel of its own
 __global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_finish(j); }
 
@@ -1655,6 +1822,11 @@ hipError_t launch_sumsq(int xdt, const void *X, int64_t n, double *part, double 
   return hipGetLastError();
 }
 
+int defer_workgroups(int64_t I) {
+  const int64_t blocks = (I + 7) / 8;
+  return (int)(blocks < kGramSlices ? blocks : kGramSlices);
+}
+
 template <typename HT>
 static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *job) {
   const int rpb = update_rows_per_block(a.R);
@@ -1662,6 +1834,32 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
   dim3 grid(nb), block(256);
   *job = GramJob{};
   job->R = 0;
+  if (a.defer) {
+    if (a.R > 64 || (a.algo != NNCP_MU && a.algo != NNCP_HALS)) return hipErrorInvalidValue;
+    const int nw = defer_workgroups(a.I);
+    job->gpart = a.gpart;
+    job->G = a.G;
+    job->S = a.S;
+    job->S_next = a.S_next;
+    job->lambda = a.lambda;   // the ones vector on this path
+    job->beta = a.part;       // any valid address; beta comes from beta_part
+    job->beta_part = a.part;
+    job->nbeta = nw;
+    job->pn_inline = 1;
+    job->dead = const_cast<double *>(a.dead);
+    job->alpha = a.alpha;
+    job->relerr_out = a.relerr_out;
+    job->scal = a.scal;
+    job->R = a.R;
+    job->N = a.N;
+    job->mode = a.mode;
+    job->next_mode = a.next_mode;
+    job->nw = nw;
+    if (a.R <= 16) hipLaunchKernelGGL((k_update_rows_defer<HT, 16>), dim3(nw), dim3(512), 0, st, a);
+    else if (a.R <= 32) hipLaunchKernelGGL((k_update_rows_defer<HT, 32>), dim3(nw), dim3(512), 0, st, a);
+    else hipLaunchKernelGGL((k_update_rows_defer<HT, 64>), dim3(nw), dim3(512), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.R <= 64) {
     int64_t rpw;
     const int nw = norm_workgroups(a.I, &rpw);
@@ -1726,6 +1924,26 @@ int norm_workgroups(int64_t I, int64_t *rows_per_wg) {
 
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st, GramJob *job) {
   return hdt == NNCP_F64 ? update_dispatch<double>(a, st, job) : update_dispatch<float>(a, st, job);
+}
+
+hipError_t launch_sweep_normalize(int hdt, const FactorSet &F, const int64_t *dims, int N, int R,
+                                  double *G, double *lambda, double *scale, hipStream_t st) {
+  ScaleArgs a;
+  a.N = N;
+  a.R = R;
+  a.off[0] = 0;
+  for (int k = 0; k < NNCP_MAX_MODES; ++k) {
+    a.H[k] = k < N ? const_cast<void *>(F.H[k]) : nullptr;
+    if (k < N) a.off[k + 1] = a.off[k] + dims[k] * R;
+  }
+  hipLaunchKernelGGL(k_norm_scales, dim3(1), dim3(256), 0, st, G, N, R, lambda, scale);
+  const int64_t total = a.off[N] + (int64_t)N * R * R;
+  dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (hdt == NNCP_F64)
+    hipLaunchKernelGGL(k_apply_scales<double>, grid, block, 0, st, a, G, scale);
+  else
+    hipLaunchKernelGGL(k_apply_scales<float>, grid, block, 0, st, a, G, scale);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram_finish(const GramJob &j, hipStream_t st) {

@@ -9,6 +9,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+import mttkrp_bounds as mb  # noqa: E402
 import nncp_inputs as gen  # noqa: E402
 import oracle  # noqa: E402
 
@@ -40,11 +41,12 @@ def slice_of(X, dims, n, i):
     return T.select(N - 1 - n, int(i)).contiguous().double().cpu().numpy().reshape(-1)
 
 
-def oracle_row(X, dims, Hh, n, i, nthreads=16):
+def oracle_row(X, dims, Hh, n, i, nthreads=16, want_sum=False):
     xs = slice_of(X, dims, n, i)
     Hs = list(Hh)
     Hs[n] = Hh[n][i:i + 1]
-    return oracle.mttkrp_rows(xs, Hs, n, [0], nthreads=nthreads)[0]
+    row = oracle.mttkrp_rows(xs, Hs, n, [0], nthreads=nthreads)[0]
+    return (row, float(xs.sum())) if want_sum else row
 
 
 def oracle_grad_row(X, dims, Hh, n, i, nthreads=16):
@@ -64,12 +66,15 @@ def test_256_4way_bf16_sampled_rows(nn):
     ctx = nn.Context(X, H)
     assert ctx.split() == 2 and ctx.gemm_path(0) == 1 and ctx.gemm_path(1) == 1
     rng = np.random.default_rng(3)
+    plans = [ctx.gemm_plan(0), ctx.gemm_plan(1)]
     for n in range(4):
         M = ctx.mttkrp(n).double().cpu().numpy()
         rows = rng.choice(dims[n], 2, replace=False)
         ref = np.stack([oracle_row(X, dims, Hh, n, i) for i in rows])
         e = relerr(M[rows], ref)
-        print(f"mode {n}: sampled-row rel err {e:.3e}", flush=True)
+        worst, c = mb.check(M[rows], ref, "bf16", dims, 2, n, plans)
+        print(f"mode {n}: sampled-row rel err {e:.3e}, max entrywise {worst:.3e} "
+              f"(bound {c:.3e})", flush=True)
         assert e <= 3e-5
     rel = ctx.sweep(nn.NNCP_HALS, 2).cpu().numpy()
     assert np.all(np.isfinite(rel)) and rel[1] < rel[0]
@@ -85,12 +90,17 @@ def test_imaging_fp16_sampled_rows_and_mu_hals(nn):
     ctx = nn.Context(X, H)
     assert ctx.gemm_path(0) == 1 and ctx.gemm_path(1) == 1
     rng = np.random.default_rng(4)
+    plans = [ctx.gemm_plan(0), ctx.gemm_plan(1)]
+    S = ctx.split()
     for n in range(3):
         M = ctx.mttkrp(n).double().cpu().numpy()
         rows = rng.choice(dims[n], 3, replace=False)
-        ref = np.stack([oracle_row(X, dims, Hh, n, i) for i in rows])
+        got = [oracle_row(X, dims, Hh, n, i, want_sum=True) for i in rows]
+        ref = np.stack([g[0] for g in got])
         e = relerr(M[rows], ref)
-        print(f"mode {n}: sampled-row rel err {e:.3e}", flush=True)
+        worst, c = mb.check(M[rows], ref, "f16", dims, S, n, plans, Hh, [g[1] for g in got])
+        print(f"mode {n}: sampled-row rel err {e:.3e}, max entrywise {worst:.3e} "
+              f"(bound {c:.3e} + the FP16 range term)", flush=True)
         assert e <= 1e-5
     ctx.close()
     for algo in (nn.NNCP_MU, nn.NNCP_HALS):
