@@ -57,7 +57,7 @@ struct Layout {
   int64_t dual_tiles, nodeR;
   // byte offsets into the workspace
   size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart,
-      off_red, off_M, off_A, off_B, off_R, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_outer, off_admmU,
+      off_red, off_M, off_A, off_B, off_R, off_kfR, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_outer, off_admmU,
       off_admmMc, off_admmP, off_admmNorm, off_admmStatus, total;
 };
 
@@ -292,6 +292,7 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_A = take(hs * L.nodeA);
   L.off_B = take(hs * L.nodeB);
   L.off_R = take(hs * L.nodeR);
+  L.off_kfR = take(L.dual ? es * (L.gp[0].hl ? 2 : 1) * L.gp[0].Rpad * L.gp[0].k : 0);
   L.off_part = take(hs * L.part_elems);
   L.off_kf = take(es * L.kfast_elems);
   L.off_ks = take(hs * L.kslow_elems);
@@ -348,7 +349,7 @@ struct nncp_ctx {
   double *admmU, *admmMc, *admmP, *admmNorm;
   int *admmStatus;
   double *outer;
-  void *M, *nodeA, *nodeB, *nodeR, *part, *kf, *ks;
+  void *M, *nodeA, *nodeB, *nodeR, *kfR, *part, *kf, *ks;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
   // set while nncp_grad walks the right subtree from the fused pass: the
   // right root node lives in nodeR
@@ -758,6 +759,7 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->nodeA = c->ws + L.off_A;
   c->nodeB = c->ws + L.off_B;
   c->nodeR = c->ws + L.off_R;
+  c->kfR = c->ws + L.off_kfR;
   c->part = c->ws + L.off_part;
   c->kf = c->ws + L.off_kf;
   c->ks = c->ws + L.off_ks;
@@ -1107,7 +1109,7 @@ static int sweep_deferred(nncp_ctx *c, int algo, int nsweeps, double *relerr_his
 // at 512^3 (0.183 against 0.174 ms per BF16 sweep: its Gram step adds 64
 // slices in one workgroup inside the next launch); it stays off until that
 // step is spread over workgroups.
-constexpr bool kDeferredSweep = false;
+constexpr bool kDeferredSweep = true;
 
 static int sweep_launches(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) {
   const Layout &L = c->L;
@@ -1236,8 +1238,11 @@ static int dual_roots(nncp_ctx *c, const FactorSet &F) {
   const Layout &L = c->L;
   HIPCHK(flush_gram(c));
   TIMED(2, launch_krp_operands(L.xdt, L.gp[1], L.R, L.dims, L.N, F, c->kf, c->ks, c->st));
-  TIMED(0, launch_dual_mttkrp(L.xdt, L.gp[0], L.gp[1], L.R, c->X, L.dims, L.N, L.S, F, c->kf,
-                              c->ks, c->nodeA, c->part, c->st));
+  // the left operand whole (its slow part, a row of ones, goes to scratch)
+  TIMED(2, launch_krp_operands(L.xdt, dual_full_plan(L.gp[0], L.S, L.N), L.R, L.dims, L.N, F,
+                               c->kfR, c->red, c->st));
+  TIMED(0, launch_dual_mttkrp(L.xdt, L.gp[0], L.gp[1], L.R, c->X, c->kfR, c->kf, c->ks, c->nodeA,
+                              c->part, c->st));
   GemmPlan pd = L.gp[1];
   pd.nsplit = (int)L.dual_tiles;
   TIMED(3, launch_finalize(L.hdt, pd, L.R, c->part, c->nodeR, L.N - L.S == 1 ? 1 : 0, c->st));

@@ -115,11 +115,23 @@ hipError_t launch_partial_mttkrp(int xdt, const GemmPlan &p, int R, const void *
 // left product written straight into its node out_l, [r][m]); the right
 // product leaves dual_tiles(m) partials [tile][k][R] in out_r, to be added in
 // tile order (launch_finalize with nsplit = dual_tiles(m)).  kfl / ksl are
-// the right plan's Khatri-Rao operands (launch_krp_operands with pr).
+// the right plan's Khatri-Rao operands (launch_krp_operands with pr); kfr is
+// the left product's whole operand K_R, [hl][Rpad][k] (launch_krp_operands
+// with dual_full_plan(pl)).
 hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, int R,
-                              const void *X, const int64_t *dims, int N, int S,
-                              const FactorSet &F, const void *kfl, const void *ksl, void *out_l,
-                              void *out_r, hipStream_t st);
+                              const void *X, const void *kfr, const void *kfl, const void *ksl,
+                              void *out_l, void *out_r, hipStream_t st);
+// the left plan with every reduced mode in the fast part (Pf = k, Ps = 1)
+inline GemmPlan dual_full_plan(const GemmPlan &pl, int S, int N) {
+  GemmPlan p = pl;
+  p.fast_lo = S;
+  p.fast_hi = N;
+  p.slow_lo = N;
+  p.slow_hi = N;
+  p.Pf = pl.k;
+  p.Ps = 1;
+  return p;
+}
 size_t dual_lds_bytes(int NT, int hl, int64_t PfL);
 int64_t dual_tiles(int64_t m);
 
@@ -206,7 +218,7 @@ constexpr int kNormWG = 8;
 int norm_workgroups(int64_t I, int64_t *rows_per_wg);
 // most Gram slices the Gram step adds (the finish kernel writes kNormWG, the
 // row kernel of the sweep's deferred path up to this many)
-constexpr int kGramSlices = 64;
+constexpr int kGramSlices = 256;
 // scratch of the Gram step (R <= 64): kGramSlices slices of Gram tiles, then
 // the R x R Hadamard product of the Grams other than mode and next_mode
 __host__ __device__ inline int64_t norm_pn_offset(int R) {
@@ -245,6 +257,12 @@ struct GramJob {
   int pn_inline;         // 1: the product of the Grams other than mode and
                          // next_mode is formed here from G (no pn buffer)
   double *dead;          // if not NULL: dead[x] = 1 where G^(mode)(x, x) == 0
+  // parts > 0: the step is split over `parts` workgroups (gram_part), each
+  // adding the slices of 32 upper-tile entries; gamma then comes from the
+  // update's per-workgroup partials (gamma_part, nbeta of them) instead of
+  // G and S
+  int parts;
+  const double *gamma_part;
 };
 
 // One 256-thread workgroup.  Thread t takes the upper-tile entries u = t +
@@ -351,6 +369,109 @@ __device__ inline void gram_finish(const GramJob &j) {
       j.scal[2] = e2;
     }
     if (j.relerr_out) j.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
+  }
+}
+
+// Part p (0 <= p < j.parts) of a Gram step split over workgroups, one
+// 256-thread workgroup: the upper-tile entries u = 32 p .. 32 p + 31.  Thread
+// t adds the slices w = t / 32, t / 32 + 8, ... of entry 32 p + t % 32 in
+// that order, and the eight groups are added in group order through LDS, so
+// the sum is the same on every run.  Part 0 also forms beta, gamma and the
+// relative error from the update's partials.  Only the thread of entry
+// (x, y) writes G(x, y), G(y, x), S_next(x, y), S_next(y, x) and dead[x].
+__device__ inline void gram_part(const GramJob &j, int p) {
+  __shared__ double red[8][32];
+  const int R = j.R, RR = R * R, T = (R + 15) >> 4, slice = (T * (T + 1) / 2) * 256;
+  const int tid = threadIdx.x, e32 = tid & 31, grp = tid >> 5;
+  const int u = 32 * p + e32;
+  const int uc = u < slice ? u : slice - 1;
+  const int nw = j.nw;
+  double acc = 0.0;
+  for (int w0 = grp; w0 < nw; w0 += 32) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int w = w0 + 8 * k;
+      v[k] = j.gpart[(int64_t)(w < nw ? w : nw - 1) * slice + uc];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (w0 + 8 * k < nw) acc += v[k];
+  }
+  red[grp][e32] = acc;
+  __syncthreads();
+  if (tid < 32 && u < slice) {
+    double sum = red[0][tid];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) sum += red[g][tid];
+    int tx = 0, q = u >> 8;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      if (tx == r && q >= T - r) { q -= T - r; tx = r + 1; }
+    const int xl = (u >> 4) & 15, yl = u & 15;
+    const int x = 16 * tx + xl, y = 16 * (tx + q) + yl;
+    if (x < R && y < R && (q > 0 || xl <= yl)) {
+      double *Gm = j.G + (int64_t)j.mode * RR;
+      Gm[x * R + y] = sum;
+      Gm[y * R + x] = sum;
+      if (j.dead && x == y && sum == 0.0) j.dead[x] = 1.0;
+      if (j.S_next) {
+        double pn = 1.0;
+        if (j.pn_inline) {
+          for (int g = 0; g < j.N; ++g)
+            if (g != j.mode && g != j.next_mode) pn *= j.G[(int64_t)g * RR + x * R + y];
+        } else {
+          pn = j.pn[x * R + y];
+        }
+        const double sn = j.next_mode == j.mode ? pn : pn * sum;
+        j.S_next[x * R + y] = sn;
+        j.S_next[y * R + x] = sn;
+      }
+    }
+  }
+  if (p == 0 && (j.relerr_out || j.scal)) {
+    // the update's beta and gamma partials: thread t adds partials t, t +
+    // 256, ..., then a fixed butterfly per wave and the four waves in order
+    __shared__ double bg[2][4];
+    double b = 0.0, g = 0.0;
+    for (int w = tid; w < j.nbeta; w += 256) {
+      b += j.beta_part[w];
+      g += j.gamma_part[w];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      b += __shfl_xor(b, o);
+      g += __shfl_xor(g, o);
+    }
+    if ((tid & 63) == 0) {
+      bg[0][tid >> 6] = b;
+      bg[1][tid >> 6] = g;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const double beta = bg[0][0] + bg[0][1] + bg[0][2] + bg[0][3];
+    const double gamma = bg[1][0] + bg[1][1] + bg[1][2] + bg[1][3];
+    const double alpha = j.alpha[0];
+    const double e2 = (alpha - 2.0 * beta + gamma) / alpha;
+    if (j.scal) {
+      j.scal[0] = beta;
+      j.scal[1] = gamma;
+      j.scal[2] = e2;
+    }
+    if (j.relerr_out) j.relerr_out[0] = sqrt(e2 > 0.0 ? e2 : 0.0);
+  }
+}
+
+// workgroups a Gram step needs (0 for an empty job)
+__host__ __device__ inline int gram_blocks(const GramJob &j) {
+  return j.R == 0 ? 0 : (j.parts > 0 ? j.parts : 1);
+}
+// run block p of a Gram step (a carrier's extra workgroups, or its own kernel)
+__device__ inline void gram_run(const GramJob &j, int p) {
+  if (j.parts > 0) {
+    if (p < j.parts) gram_part(j, p);
+  } else if (p == 0) {
+    gram_finish(j);
   }
 }
 

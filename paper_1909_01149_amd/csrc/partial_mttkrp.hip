@@ -154,10 +154,10 @@ __device__ double krp_entry(const KrpArgs &a, int lo, int hi, int64_t rho, int r
 template <typename XT, typename HT>
 __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict__ kfast,
                                                       HT *__restrict__ kslow, GramJob job) {
-  // an extra column of workgroups (blockIdx.x == Rpad) when carrying the
+  // extra columns of workgroups (blockIdx.x >= Rpad) when carrying the
   // Gram step of the previous update
-  if (job.R && blockIdx.x == a.Rpad) {
-    if (blockIdx.y == 0) gram_finish(job);
+  if (job.R && blockIdx.x >= a.Rpad) {
+    gram_run(job, (blockIdx.x - a.Rpad) * gridDim.y + blockIdx.y);
     return;
   }
   const int r = blockIdx.x;
@@ -704,10 +704,12 @@ __device__ __forceinline__ void wave_sync_lds() {
 // 8g .. 8g+7 of the step at columns 8 rho .. 8 rho+7 of its wave, eight
 // 16-byte loads, as the left kernel does.
 //  * T_L: the left kernel's in-lane transpose into A operands; the B operand
-//    is K_R itself, the slow factor already folded in: rows of K_R are staged
-//    in LDS a window of kDualWin rows at a time, each entry formed in FP64
-//    from the factors and split hi + lo, between two barriers when the rows
-//    cross into the next window.  No per-block accumulators are needed.
+//    is K_R itself, the slow factor already folded in (formed once, whole,
+//    by the Khatri-Rao operand kernel, hi + lo): its rows are staged in LDS a
+//    window of kDualWin rows at a time between two barriers when the rows
+//    cross into the next window, the next window's pieces loaded into
+//    registers while the current one is in use.  No per-block accumulators
+//    are needed.
 //  * T_R: each lane also writes its eight 16-byte row pieces into a
 //    wave-private LDS tile (16-byte chunks XOR-swizzled by row) and reads the
 //    A operands (16 rows x 32 columns) back from it; the B operands are the
@@ -723,8 +725,6 @@ constexpr int kDualWaves = 8;
 constexpr int kDualWin = 128;
 
 struct DualArgs {
-  KrpArgs kr;          // the factors; K_R(j, r) = prod over modes kr_lo..kr_hi-1
-  int kr_lo, kr_hi;
   int64_t m, k;
   int PfL;             // fast length of K_L (a multiple of 32), staged whole
   int R;
@@ -732,7 +732,7 @@ struct DualArgs {
 
 template <typename XT, int NT, bool HL, bool NTL>
 __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
-    const XT *__restrict__ X, DualArgs a, const XT *__restrict__ kfl,
+    const XT *__restrict__ X, DualArgs a, const XT *__restrict__ kfr, const XT *__restrict__ kfl,
     const float *__restrict__ ksl, float *__restrict__ out_l, float *__restrict__ out_r) {
   typedef f32x4 CT;
   constexpr int WV = kDualWaves, QV = 8, KL = 8, KSTEP = 32, RP = 16 * NT;
@@ -785,18 +785,37 @@ __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) ks[c][nt] = ksl[sidx * RP + 16 * nt + rho];
   }
-  // K_R window: rows wbase .. wbase + kDualWin of K_R, hi (+ lo), formed in FP64
-  auto stage_kr = [&](int64_t wbase) {
-    const int total = RP * kDualWin;
-    for (int e = tid; e < total; e += 64 * WV) {
-      const int r = e / kDualWin, p = e - r * kDualWin;
-      const int64_t j = wbase + p;
-      const double v = (r < a.R && j < k) ? krp_entry<float>(a.kr, a.kr_lo, a.kr_hi, j, r) : 0.0;
-      const XT hi = from_d<XT>(v);
-      skr[kidx<XT>(r, p, kDualWin, 15)] = hi;
-      if (HL) skr[RP * kDualWin + kidx<XT>(r, p, kDualWin, 15)] = from_d<XT>(v - to_d<XT>(hi));
+  // K_R windows: rows wbase .. wbase + kDualWin of K_R ([HL+1][RP][k] in
+  // global memory), fetched into registers (16-byte pieces) and stored to
+  // LDS at the window boundary
+  constexpr int WCH = kDualWin / SVEC;
+  constexpr int WTOT = (HL ? 2 : 1) * RP * WCH;
+  constexpr int WPT = (WTOT + 64 * WV - 1) / (64 * WV);
+  u32x4 kwin[WPT];
+  auto fetch_kr = [&](int64_t wbase) {
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int e = tid + q * 64 * WV;
+      const int ec = e < WTOT ? e : WTOT - 1;
+      const int h = ec / (RP * WCH), rem = ec - h * RP * WCH;
+      const int r = rem / WCH, v = rem - r * WCH;
+      const int64_t j = wbase + v * SVEC;
+      kwin[q] = j < k ? *reinterpret_cast<const u32x4 *>(kfr + ((int64_t)(h * RP + r)) * k + j)
+                      : u32x4{0u, 0u, 0u, 0u};
     }
   };
+  auto store_kr = [&]() {
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int e = tid + q * 64 * WV;
+      if (e >= WTOT) continue;
+      const int h = e / (RP * WCH), rem = e - h * RP * WCH;
+      const int r = rem / WCH, v = rem - r * WCH;
+      *reinterpret_cast<u32x4 *>(skr + h * RP * kDualWin + kidx<XT>(r, v * SVEC, kDualWin, 15)) =
+          kwin[q];
+    }
+  };
+  fetch_kr(0);
 
   CT acc[QV][NT], cr[2][NT];
 #pragma unroll
@@ -830,9 +849,10 @@ __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
       const int64_t wb = j0 / kDualWin * kDualWin;
       if (wb != wcur) {
         __syncthreads();
-        stage_kr(wb);
+        store_kr();
         __syncthreads();
         wcur = wb;
+        fetch_kr(wb + kDualWin);
       }
       // ---- T_L: as the left kernel, B = K_R rows j0 - wb + 8g ..
       {
@@ -1098,7 +1118,8 @@ hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t 
   const int64_t longest = p.Pf > p.Ps ? p.Pf : p.Ps;
   int64_t chunks = (longest + 255) / 256;
   if (chunks > 64) chunks = 64;
-  dim3 grid(p.Rpad + (job.R ? 1 : 0), xdt == NNCP_F16 ? 1 : (unsigned)chunks), block(256);
+  const unsigned gy = xdt == NNCP_F16 ? 1 : (unsigned)chunks;
+  dim3 grid(p.Rpad + (gram_blocks(job) + gy - 1) / gy, gy), block(256);
   switch (xdt) {
     case NNCP_BF16:
       hipLaunchKernelGGL((k_krp_operands<bf16_t, float>), grid, block, 0, st, a, (bf16_t *)kfast, (float *)kslow, job);
@@ -1264,14 +1285,10 @@ size_t dual_lds_bytes(int NT, int hl, int64_t PfL) {
 int64_t dual_tiles(int64_t m) { return (m + 128 * kDualWaves - 1) / (128 * kDualWaves); }
 
 hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, int R,
-                              const void *X, const int64_t *dims, int N, int S,
-                              const FactorSet &F, const void *kfl, const void *ksl, void *out_l,
-                              void *out_r, hipStream_t st) {
+                              const void *X, const void *kfr, const void *kfl, const void *ksl,
+                              void *out_l, void *out_r, hipStream_t st) {
   if (xdt != NNCP_BF16 || pl.NT > 2) return hipErrorInvalidValue;
   DualArgs a;
-  a.kr = make_krp_args(pl, R, dims, F, N);
-  a.kr_lo = S;
-  a.kr_hi = N;
   a.m = pl.m;
   a.k = pl.k;
   a.PfL = (int)pr.Pf;
@@ -1280,7 +1297,8 @@ hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, i
   dim3 grid((unsigned)dual_tiles(pl.m)), block(64 * kDualWaves);
 #define NNCP_DUAL(NTV, HLV, NTLV)                                                                 \
   hipLaunchKernelGGL((k_gemm_dual_mfma<bf16_t, NTV, HLV, NTLV>), grid, block, lds, st,          \
-                     (const bf16_t *)X, a, (const bf16_t *)kfl, (const float *)ksl,              \
+                     (const bf16_t *)X, a, (const bf16_t *)kfr, (const bf16_t *)kfl,             \
+                     (const float *)ksl,                                                          \
                      (float *)out_l, (float *)out_r)
   const bool ntl = pl.nt_loads != 0;
   if (pl.NT == 1) {

@@ -129,9 +129,9 @@ __global__ __launch_bounds__(256) void k_mttv_contig_reg(const HT *__restrict__ 
   constexpr int QB = 8 / CPL;
   typedef HT vt __attribute__((ext_vector_type(V)));
   __shared__ vt hs[64 * CPL];
-  // an extra column of workgroups when carrying the Gram step
-  if (job.R && blockIdx.x == gridDim.x - 1) {
-    if (blockIdx.y == 0) gram_finish(job);
+  // extra columns of workgroups when carrying the Gram step
+  if (job.R && blockIdx.x >= R) {
+    gram_run(job, (blockIdx.x - R) * gridDim.y + blockIdx.y);
     return;
   }
   const int r = blockIdx.x;
@@ -192,9 +192,9 @@ __global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, 
   typedef HT vt __attribute__((ext_vector_type(V)));
   __shared__ vt red[256];
   __shared__ HT kq[1024];
-  // an extra row of workgroups (blockIdx.y == R) when carrying the Gram step
-  if (job.R && blockIdx.y == a.R) {
-    if (blockIdx.x == 0 && blockIdx.z == 0) gram_finish(job);
+  // extra rows of workgroups (blockIdx.y >= R) when carrying the Gram step
+  if (job.R && blockIdx.y >= a.R) {
+    gram_run(job, ((blockIdx.y - a.R) * gridDim.z + blockIdx.z) * gridDim.x + blockIdx.x);
     return;
   }
   const int il = threadIdx.x % a.IT, qs = threadIdx.x / a.IT;
@@ -1345,28 +1345,32 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
 // once at the end of the call (k_norm_scales, k_apply_scales): the iterates
 // are those of the normalised iteration up to rounding.  The kernel writes
 // the rows straight into H; there is no separate normalisation launch.
-// 8 rows per pass (512 threads, one row per wave, lane c owns column c and
+// 4 rows per pass (256 threads, one row per wave, lane c owns column c and
 // keeps column c of S in registers), row blocks gridDim.x apart.  The stored
 // (rounded) rows also feed the workgroup's slice of the Gram of the new
-// factor (upper 16 x 16 tiles on FP64 MFMA, four rows a step; wave w owns
-// tiles w and w + 8) and its share of <M, Hhat>, added in row-block and wave
+// factor (upper 16 x 16 tiles on FP64 MFMA, the pass's four rows one step;
+// wave w owns tiles w, w + 4, w + 8) and its shares of beta = <M, Hhat> and
+// of gamma = sum_i hs_i S hs_i^T (hs the stored row), which the relative
+// error identity needs with lambda = 1; both added in row-block and wave
 // order.  The arithmetic of a row is that of k_update_rows_small.
 template <typename HT, int RB>
-__global__ __launch_bounds__(512) void k_update_rows_defer(UpdateArgs a) {
-  __shared__ double rows[8][RB];
-  __shared__ double bred[8];
+__global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
+  __shared__ double rows[4][RB];
+  __shared__ double bred[4][2];
   const int R = a.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int T = (R + 15) / 16, ntile = T * (T + 1) / 2;
-  int tx[2] = {-1, -1}, ty[2] = {-1, -1};
+  int tx[3], ty[3];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
-    if (wave + 8 * q < ntile) tile_pair(wave + 8 * q, T, tx[q], ty[q]);
+  for (int q = 0; q < 3; ++q) {
+    tx[q] = ty[q] = -1;
+    if (wave + 4 * q < ntile) tile_pair(wave + 4 * q, T, tx[q], ty[q]);
+  }
   const int lr = lane >> 4, lc = lane & 15;
-  f64x4 gacc[2];
+  f64x4 gacc[3];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) gacc[q][0] = gacc[q][1] = gacc[q][2] = gacc[q][3] = 0.0;
-  double bsum = 0.0;
+  for (int q = 0; q < 3; ++q) gacc[q][0] = gacc[q][1] = gacc[q][2] = gacc[q][3] = 0.0;
+  double bsum = 0.0, gsum = 0.0;
   const HT *M = (const HT *)a.M;
   HT *H = (HT *)a.H;
   const bool own = lane < R;
@@ -1379,8 +1383,8 @@ __global__ __launch_bounds__(512) void k_update_rows_defer(UpdateArgs a) {
   // in a dead column (as lambda_r = 0 would make it), else the row as stored
   const double lam = a.fold_lambda ? a.lambda[c] : (a.dead[c] != 0.0 ? 0.0 : 1.0);
   const int ns = a.msplit;
-  for (int64_t blk = blockIdx.x; blk * 8 < a.I; blk += gridDim.x) {
-    const int64_t i = blk * 8 + wave;
+  for (int64_t blk = blockIdx.x; blk * 4 < a.I; blk += gridDim.x) {
+    const int64_t i = blk * 4 + wave;
     const bool live = i < a.I;
     const int64_t ir = live ? i : a.I - 1;
     const HT *mp = M + ir * R + c;
@@ -1418,39 +1422,51 @@ __global__ __launch_bounds__(512) void k_update_rows_defer(UpdateArgs a) {
         }
       }
     }
-    const HT hs = (HT)h;
-    if (ok) H[i * R + c] = hs;
-    if (lane < RB) rows[wave][lane] = ok ? (double)hs : 0.0;
-    double beta = ok ? m * h : 0.0;
-    beta = wave_sum(beta);
-    if (lane == 0) bred[wave] = beta;
+    const HT hst = (HT)h;
+    if (ok) H[i * R + c] = hst;
+    const double hs = ok ? (double)hst : 0.0;
+    if (lane < RB) rows[wave][lane] = hs;
+    // (hs S)(c), j in order
+    double gs = 0.0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (j < R) gs += bcast(hs, j) * sc[j];
+    const double beta = wave_sum(ok ? m * h : 0.0);
+    const double gam = wave_sum(ok ? hs * gs : 0.0);
+    if (lane == 0) {
+      bred[wave][0] = beta;
+      bred[wave][1] = gam;
+    }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 3; ++q) {
       if (tx[q] < 0) continue;
-#pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        const double av = rows[4 * st + lr][16 * tx[q] + lc];
-        const double bv = rows[4 * st + lr][16 * ty[q] + lc];
-        gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, gacc[q], 0, 0, 0);
-      }
+      const double av = rows[lr][16 * tx[q] + lc];
+      const double bv = rows[lr][16 * ty[q] + lc];
+      gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, gacc[q], 0, 0, 0);
     }
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int w = 0; w < 8; ++w) bsum += bred[w];
+      for (int w = 0; w < 4; ++w) {
+        bsum += bred[w][0];
+        gsum += bred[w][1];
+      }
     }
     __syncthreads();
   }
   // this workgroup's slice: entry (lr + 4 v, lc) of tile t, as the finish
   // kernel writes its slices
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < 3; ++q) {
     if (tx[q] < 0) continue;
-    double *gp = a.gpart + ((int64_t)blockIdx.x * ntile + wave + 8 * q) * 256;
+    double *gp = a.gpart + ((int64_t)blockIdx.x * ntile + wave + 4 * q) * 256;
 #pragma unroll
     for (int v = 0; v < 4; ++v) gp[(lr + 4 * v) * 16 + lc] = gacc[q][v];
   }
-  if (threadIdx.x == 0) a.part[blockIdx.x] = bsum;
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = bsum;
+    a.part[gridDim.x + blockIdx.x] = gsum;
+  }
 }
 
 // End of the deferred path, step 1 (one workgroup): the column norms of
@@ -1505,8 +1521,8 @@ __global__ __launch_bounds__(256) void k_apply_scales(ScaleArgs a, double *__res
   G[f] = (lam[x] > 0.0 && lam[y] > 0.0) ? G[f] / (sx * sy) : 0.0;
 }
 
-// the Gram step as a kernel of its own
-__global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_finish(j); }
+// the Gram step as a kernel of its own (gram_blocks(j) workgroups)
+__global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_run(j, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // loss of [[lambda; H]] given M^(N-1) at the current factors
@@ -1669,7 +1685,8 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
   if (Ia % V == 0 && Ia <= 8 * 64 * V) {
     const int CPL = Ia <= 64 * V ? 1 : Ia <= 128 * V ? 2 : Ia <= 256 * V ? 4 : 8;
     const int QB = 8 / CPL;
-    dim3 grid((unsigned)R + (job.R ? 1 : 0), (unsigned)((Q + 4 * QB - 1) / (4 * QB))), block(256);
+    const unsigned gy = (unsigned)((Q + 4 * QB - 1) / (4 * QB));
+    dim3 grid((unsigned)R + (gram_blocks(job) + gy - 1) / gy, gy), block(256);
 #define NNCP_CONTIG_REG(HTV, C)                                                            \
   hipLaunchKernelGGL((k_mttv_contig_reg<HTV, C>), grid, block, 0, st, (const HTV *)T, Ia, Q, R, \
                      (const HTV *)H, (HTV *)out, leaf, job)
@@ -1772,7 +1789,9 @@ hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t
   strided_shape(Ia, V, Q, R, a.IT, a.QS, a.nsplit, gx);
   if ((int64_t)a.nsplit * Ia * R > part_elems) return hipErrorInvalidValue;
   if (carry) carry->R = 0;
-  dim3 grid((unsigned)gx, R + (job.R ? 1 : 0), a.nsplit), block(256);
+  const int64_t per_row = gx * (int64_t)a.nsplit;
+  dim3 grid((unsigned)gx, R + (unsigned)((gram_blocks(job) + per_row - 1) / per_row), a.nsplit),
+      block(256);
   const int64_t n = Ia * R;
   dim3 g2((unsigned)((n + 255) / 256));
   if (nsplit_out) *nsplit_out = a.nsplit;
@@ -1823,7 +1842,7 @@ hipError_t launch_sumsq(int xdt, const void *X, int64_t n, double *part, double 
 }
 
 int defer_workgroups(int64_t I) {
-  const int64_t blocks = (I + 7) / 8;
+  const int64_t blocks = (I + 3) / 4;
   return (int)(blocks < kGramSlices ? blocks : kGramSlices);
 }
 
@@ -1844,9 +1863,14 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     job->lambda = a.lambda;   // the ones vector on this path
     job->beta = a.part;       // any valid address; beta comes from beta_part
     job->beta_part = a.part;
+    job->gamma_part = a.part + nw;
     job->nbeta = nw;
     job->pn_inline = 1;
     job->dead = const_cast<double *>(a.dead);
+    {
+      const int T = (a.R + 15) / 16;
+      job->parts = (T * (T + 1) / 2) * 8;  // 32 upper-tile entries each
+    }
     job->alpha = a.alpha;
     job->relerr_out = a.relerr_out;
     job->scal = a.scal;
@@ -1855,9 +1879,9 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     job->mode = a.mode;
     job->next_mode = a.next_mode;
     job->nw = nw;
-    if (a.R <= 16) hipLaunchKernelGGL((k_update_rows_defer<HT, 16>), dim3(nw), dim3(512), 0, st, a);
-    else if (a.R <= 32) hipLaunchKernelGGL((k_update_rows_defer<HT, 32>), dim3(nw), dim3(512), 0, st, a);
-    else hipLaunchKernelGGL((k_update_rows_defer<HT, 64>), dim3(nw), dim3(512), 0, st, a);
+    if (a.R <= 16) hipLaunchKernelGGL((k_update_rows_defer<HT, 16>), dim3(nw), dim3(256), 0, st, a);
+    else if (a.R <= 32) hipLaunchKernelGGL((k_update_rows_defer<HT, 32>), dim3(nw), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_update_rows_defer<HT, 64>), dim3(nw), dim3(256), 0, st, a);
     return hipGetLastError();
   }
   if (a.R <= 64) {
@@ -1948,7 +1972,7 @@ hipError_t launch_sweep_normalize(int hdt, const FactorSet &F, const int64_t *di
 
 hipError_t launch_gram_finish(const GramJob &j, hipStream_t st) {
   if (j.R == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gram_finish, dim3(1), dim3(256), 0, st, j);
+  hipLaunchKernelGGL(k_gram_finish, dim3(gram_blocks(j)), dim3(256), 0, st, j);
   return hipGetLastError();
 }
 
