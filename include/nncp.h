@@ -115,6 +115,11 @@ typedef struct nncp_options {
                        (at least 192 workgroups of 1024 columns), 2 = wherever
                        it applies, whatever the grid, 0 = one pass per root
                        product [1].                                            */
+  int krp_kernel;   /* 1 = build every matrix-core product's Khatri-Rao operand
+                       with its own kernel; 0 = where the operand is a single
+                       fast mode times at most one slow mode (R a multiple of
+                       16, not FP16), the product kernel reads the factors and
+                       forms the operand itself, one launch fewer [0].        */
 } nncp_options;
 
 typedef struct nncp_ctx nncp_ctx;
@@ -394,7 +399,7 @@ int nncp_gemm_path(const nncp_ctx *ctx, int side);
 
 /*
  * Launch plan of one partial MTTKRP (side as for nncp_gemm_path), for
- * inspection and for bounding its rounding error.  info is a host array of 7
+ * inspection and for bounding its rounding error.  info is a host array of 8
  * entries:
  *   [0] 1 = matrix cores, 0 = vector ALU
  *   [1] Pf      length of the fast part of the reduced index (the Khatri-Rao
@@ -406,6 +411,8 @@ int nncp_gemm_path(const nncp_ctx *ctx, int side);
  *   [5] W       left side: fast indices staged in LDS at a time
  *   [6] hl      1 = the Khatri-Rao operand is a hi + lo pair of the tensor's
  *               16-bit type
+ *   [7] direct  1 = the product kernel forms the operand from the factors
+ *               (options.krp_kernel), 0 = a kernel of its own forms it first
  */
 int nncp_gemm_plan(const nncp_ctx *ctx, int side, int64_t *info);
 

@@ -51,7 +51,8 @@ class NNCPError(RuntimeError):
 
 class nncp_options(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int), ("krp_split", ctypes.c_int), ("generic", ctypes.c_int),
-                ("eps_mu", ctypes.c_double), ("graphs", ctypes.c_int), ("fused_grad", ctypes.c_int)]
+                ("eps_mu", ctypes.c_double), ("graphs", ctypes.c_int), ("fused_grad", ctypes.c_int),
+                ("krp_kernel", ctypes.c_int)]
 
 
 _lib = None
@@ -126,9 +127,9 @@ def _dims(dims):
     return arr
 
 
-def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16, graphs=1, fused_grad=1):
+def _opts(split=0, krp_split=1, generic=0, eps_mu=1e-16, graphs=1, fused_grad=1, krp_kernel=0):
     return nncp_options(int(split), int(krp_split), int(generic), float(eps_mu), int(graphs),
-                        int(fused_grad))
+                        int(fused_grad), int(krp_kernel))
 
 
 def _ptr_array(ts):
@@ -268,7 +269,7 @@ def nncp_read_probe(buf, workgroups=8192):
     return out
 
 
-GEMM_PLAN_KEYS = ("mfma", "Pf", "Ps", "nsplit", "tiles", "W", "hl")
+GEMM_PLAN_KEYS = ("mfma", "Pf", "Ps", "nsplit", "tiles", "W", "hl", "direct")
 
 
 def nncp_gemm_plan(ctx, side) -> dict:
@@ -359,7 +360,7 @@ class Context:
     checked here and in every method before the library is called."""
 
     def __init__(self, X, factors, lam=None, *, split=0, krp_split=1, generic=0, eps_mu=1e-16,
-                 graphs=1, fused_grad=1):
+                 graphs=1, fused_grad=1, krp_kernel=0):
         if not isinstance(X, torch.Tensor) or not X.is_cuda:
             raise ValueError("X must be a GPU tensor")
         dims, R = check_problem(X, factors, lam)
@@ -372,7 +373,7 @@ class Context:
         self.lam = (lam.to(device=dev, dtype=torch.float64).contiguous() if lam is not None
                     else torch.ones(self.R, dtype=torch.float64, device=dev))
         self.opts = dict(split=split, krp_split=krp_split, generic=generic, eps_mu=eps_mu,
-                         graphs=graphs, fused_grad=fused_grad)
+                         graphs=graphs, fused_grad=fused_grad, krp_kernel=krp_kernel)
         nbytes = nncp_workspace_size(self.dims, self.R, _DT[X.dtype], _DT[self.factors[0].dtype],
                                      **self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)

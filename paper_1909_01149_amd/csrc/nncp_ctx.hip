@@ -69,6 +69,7 @@ nncp_options default_options() {
   o.eps_mu = 1e-16;
   o.graphs = 1;
   o.fused_grad = 1;
+  o.krp_kernel = 0;
   return o;
 }
 
@@ -150,6 +151,11 @@ void plan_side(Layout &L, int side) {
     p.W = W;
     p.Ps = red / Pf;
     p.fast_lo = lo; p.fast_hi = fhi; p.slow_lo = fhi; p.slow_hi = hi;
+    // the operand straight from the factors: one fast mode, at most one slow
+    // mode, R a multiple of 16, no FP16 column scaling, and (left product)
+    // one LDS window
+    p.direct = L.xdt != NNCP_F16 && fhi - lo == 1 && hi - fhi <= 1 && R == p.Rpad &&
+                       (side == 1 || W == Pf) && !L.opt.krp_kernel ? 1 : 0;
     const size_t stage = stage_bytes(p.Rpad, W, es, p.hl);
     if (side == 1) {
       const size_t redb = (size_t)(kRightWaves - 1) * MT * p.NT * 4 * 64 * hs;
@@ -182,6 +188,7 @@ void plan_side(Layout &L, int side) {
   } else {
     p.Pf = red; p.Ps = 1; p.W = red;
     p.fast_lo = lo; p.fast_hi = hi; p.slow_lo = hi; p.slow_hi = hi;
+    p.direct = 0;
     p.lds_bytes = 0;
     if (side == 1) {
       p.tiles = p.k;
@@ -499,17 +506,18 @@ int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout, MRef *defer
   const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
   const bool leaf = hi - lo == 1;
   // the Gram step of the previous update rides along with the Khatri-Rao
-  // operand kernel; the vector-ALU GEMM path runs it on its own first
-  if (p.mfma)
+  // operand kernel, or with the product itself when that reads the factors
+  // directly; the vector-ALU GEMM path runs it on its own first
+  if (p.mfma && !p.direct)
     TIMED(2, launch_krp_operands(L.xdt, p, L.R, L.dims, L.N, F, c->kf, c->ks, c->st, &c->pending));
-  else
+  else if (!p.mfma || c->pending.parts == 0)
     HIPCHK(flush_gram(c));
   void *node = leaf ? Mout : node_buf(c, side, lo);
-  const bool direct = p.nsplit == 1 && ((side == 0 && !leaf) || (side == 1 && leaf));
+  const bool to_node = p.nsplit == 1 && ((side == 0 && !leaf) || (side == 1 && leaf));
   TIMED(side, launch_partial_mttkrp(L.xdt, p, L.R, c->X, L.dims, L.N, L.S, F, c->kf, c->ks,
-                                    direct ? node : c->part, c->st));
+                                    to_node ? node : c->part, c->st, &c->pending));
   if (defer) *defer = MRef{Mout, 1, 0};
-  if (!direct) {
+  if (!to_node) {
     // right partials of a single-mode subtree are already row-major copies of M
     if (defer && leaf && side == 1) {
       *defer = MRef{c->part, p.nsplit, p.k * L.R};
@@ -849,6 +857,7 @@ int nncp_gemm_plan(const nncp_ctx *c, int side, int64_t *info) {
   info[4] = p.tiles;
   info[5] = p.W;
   info[6] = p.hl;
+  info[7] = p.direct;
   return NNCP_OK;
 }
 
@@ -1241,11 +1250,15 @@ static int dual_roots(nncp_ctx *c, const FactorSet &F) {
   // the left operand whole (its slow part, a row of ones, goes to scratch)
   TIMED(2, launch_krp_operands(L.xdt, dual_full_plan(L.gp[0], L.S, L.N), L.R, L.dims, L.N, F,
                                c->kfR, c->red, c->st));
+  // the right partials in the layout of their destination: [R][k] for the
+  // right root node, [k][R] for M^(N-1), so that the sum reads and writes
+  // whole lines
+  const int leaf = L.N - L.S == 1 ? 1 : 0;
   TIMED(0, launch_dual_mttkrp(L.xdt, L.gp[0], L.gp[1], L.R, c->X, c->kfR, c->kf, c->ks, c->nodeA,
-                              c->part, c->st));
+                              c->part, leaf ? 0 : 1, c->st));
   GemmPlan pd = L.gp[1];
   pd.nsplit = (int)L.dual_tiles;
-  TIMED(3, launch_finalize(L.hdt, pd, L.R, c->part, c->nodeR, L.N - L.S == 1 ? 1 : 0, c->st));
+  TIMED(3, launch_finalize(L.hdt, pd, L.R, c->part, c->nodeR, leaf, c->st, leaf ? 0 : 1));
   return NNCP_OK;
 }
 

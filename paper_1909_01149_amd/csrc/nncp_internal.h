@@ -84,6 +84,8 @@ struct GemmPlan {
   int64_t tiles;     // output tiles (grid.x)
   size_t lds_bytes;  // dynamic LDS of the MFMA kernel
   int fast_lo, fast_hi, slow_lo, slow_hi;  // mode ranges [lo, hi) of the reduced modes
+  int direct;        // MFMA kernel reads the factors as its operand (one fast
+                     // mode, at most one slow mode, not FP16): no operand kernel
 };
 
 // Factor-set view passed to kernels (device pointers, row-major I_n x R).
@@ -105,22 +107,29 @@ hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t 
                                GramJob *carry = nullptr);
 
 // Partial MTTKRP.  `out` receives [nsplit][...] partials (see the kernels) or,
-// when nsplit == 1 and direct != 0, the node itself ([r][row] layout).
+// when nsplit == 1, the node itself ([r][row] layout) for the left product.
+// The matrix-core kernels take their operand from kfast / kslow
+// (launch_krp_operands) or, when p.direct, from the factors F.  A non-empty
+// *carry, which must be a split Gram step (parts > 0), is run by extra
+// workgroups of a matrix-core launch and emptied; the vector-ALU path cannot
+// carry one (hipErrorInvalidValue).
 hipError_t launch_partial_mttkrp(int xdt, const GemmPlan &p, int R, const void *X,
                                  const int64_t *dims, int N, int S, const FactorSet &F,
                                  const void *kfast, const void *kslow, void *out,
-                                 hipStream_t st);
+                                 hipStream_t st, GramJob *carry = nullptr);
 
 // Both root partial MTTKRPs in one pass over X (BF16 tensor, NT <= 2, the
 // left product written straight into its node out_l, [r][m]); the right
-// product leaves dual_tiles(m) partials [tile][k][R] in out_r, to be added in
-// tile order (launch_finalize with nsplit = dual_tiles(m)).  kfl / ksl are
+// product leaves dual_tiles(m) partials in out_r, [tile][R][k] when
+// r_major != 0 (the node layout: added by launch_finalize with part_rmajor
+// 1) else [tile][k][R] (the layout of M), to be added in tile order
+// (launch_finalize with nsplit = dual_tiles(m)).  kfl / ksl are
 // the right plan's Khatri-Rao operands (launch_krp_operands with pr); kfr is
 // the left product's whole operand K_R, [hl][Rpad][k] (launch_krp_operands
 // with dual_full_plan(pl)).
 hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, int R,
                               const void *X, const void *kfr, const void *kfl, const void *ksl,
-                              void *out_l, void *out_r, hipStream_t st);
+                              void *out_l, void *out_r, int r_major, hipStream_t st);
 // the left plan with every reduced mode in the fast part (Pf = k, Ps = 1)
 inline GemmPlan dual_full_plan(const GemmPlan &pl, int S, int N) {
   GemmPlan p = pl;
@@ -136,9 +145,11 @@ size_t dual_lds_bytes(int NT, int hl, int64_t PfL);
 int64_t dual_tiles(int64_t m);
 
 // Sum split partials of a partial MTTKRP into a node ([r][row]) or, when
-// leaf != 0, an M matrix ([row][r]).
+// leaf != 0, an M matrix ([row][r]).  The partials are [split][R][rows] for
+// the left product and [split][rows][R] for the right one, unless
+// part_rmajor (0 or 1) says otherwise.
 hipError_t launch_finalize(int hdt, const GemmPlan &p, int R, const void *part, void *out,
-                           int leaf, hipStream_t st);
+                           int leaf, hipStream_t st, int part_rmajor = -1);
 
 // Multi-TTV, contiguous reduction over the node's first mode:
 //   out(q, r) = sum_{i<Ia} T[r][i + Ia q] * H(i, r)
@@ -228,6 +239,15 @@ __host__ __device__ inline int64_t norm_pn_offset(int R) {
 int norm_gpart_elems(int R);
 int64_t update_part_elems(int64_t I, int R);
 
+// Cross-lane exchange through LDS inside one wave: the wave's LDS accesses
+// are performed in order, so a wavefront-scope fence with a scheduling
+// barrier is all that orders one lane's write before another lane's read.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // The Gram step of an update with R <= 64.  The update's last kernel leaves
 // the Gram of the new factor as nw slices of upper 16 x 16 tiles (one slice
@@ -236,7 +256,7 @@ int64_t update_part_elems(int64_t I, int R);
 // next_mode.  This step adds the slices in slice order into G^(mode) (both
 // halves), forms gamma = lambda^T (S .* G^(mode)) lambda and the relative
 // error when asked, and the next mode's S = pn .* G^(mode).  It runs as one
-// 256-thread workgroup, either a kernel of its own or an extra workgroup of
+// workgroup (its first 256 threads), either a kernel of its own or an extra workgroup of
 // the next kernel on the stream ("carrier"), which must not touch G, S or the
 // error outputs.  R == 0 marks an empty job.
 // ---------------------------------------------------------------------------
@@ -265,7 +285,7 @@ struct GramJob {
   const double *gamma_part;
 };
 
-// One 256-thread workgroup.  Thread t takes the upper-tile entries u = t +
+// One workgroup (its first 256 threads).  Thread t takes the upper-tile entries u = t +
 // 256 k (consecutive threads read consecutive slice entries) and writes both
 // (x, y) and (y, x): G, S and pn are exactly symmetric (each pair is written
 // from one value), so gamma adds the diagonal once and each off-diagonal pair
@@ -278,6 +298,11 @@ __device__ inline void gram_finish(const GramJob &j) {
   const int R = j.R, RR = R * R, T = (R + 15) >> 4, slice = (T * (T + 1) / 2) * 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool want_err = j.relerr_out || j.scal;
+  // threads past the first 256 (a carrier of 512) only meet the barrier
+  if (tid >= 256) {
+    if (want_err) __syncthreads();
+    return;
+  }
   const int nw = j.nw;
   double *Gm = j.G + (int64_t)j.mode * RR;
   const double *pnp = (j.S_next && !j.pn_inline) ? j.pn : j.lambda;  // any valid address when unused
@@ -373,7 +398,7 @@ __device__ inline void gram_finish(const GramJob &j) {
 }
 
 // Part p (0 <= p < j.parts) of a Gram step split over workgroups, one
-// 256-thread workgroup: the upper-tile entries u = 32 p .. 32 p + 31.  Thread
+// workgroup of at least 256 threads (the first 256 work): the upper-tile entries u = 32 p .. 32 p + 31.  Thread
 // t adds the slices w = t / 32, t / 32 + 8, ... of entry 32 p + t % 32 in
 // that order, and the eight groups are added in group order through LDS, so
 // the sum is the same on every run.  Part 0 also forms beta, gamma and the
@@ -383,6 +408,12 @@ __device__ inline void gram_part(const GramJob &j, int p) {
   __shared__ double red[8][32];
   const int R = j.R, RR = R * R, T = (R + 15) >> 4, slice = (T * (T + 1) / 2) * 256;
   const int tid = threadIdx.x, e32 = tid & 31, grp = tid >> 5;
+  // threads past the first 256 (a carrier of 512) only meet the barriers
+  if (tid >= 256) {
+    __syncthreads();
+    if (p == 0 && (j.relerr_out || j.scal)) __syncthreads();
+    return;
+  }
   const int u = 32 * p + e32;
   const int uc = u < slice ? u : slice - 1;
   const int nw = j.nw;

@@ -201,6 +201,124 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// The Khatri-Rao operand as the matrix-core kernels read it.  Either the
+// precomputed Kfast [hl][Rpad][Pf] and Kslow [Ps][Rpad] of k_krp_operands
+// (hf == NULL, ldks = Rpad), or, when the fast part is a single mode and the
+// slow part at most one (no FP16 scaling), the factors themselves: hf is the
+// fast mode's factor [Pf][R], split into hi (+ lo) while it is staged with
+// the same roundings as k_krp_operands, and kslow the slow mode's factor
+// [Ps][R] (ldks = R) or NULL for no slow mode (a scale of one).  The direct
+// form (R a multiple of 16, so R == Rpad) saves the operand kernel's launch.
+// ---------------------------------------------------------------------------
+template <typename XT> struct KOp {
+  const XT *kfast;
+  const typename XTraits<XT>::AT *kslow;
+  const typename XTraits<XT>::AT *hf;
+  int ldks;
+};
+
+template <typename XT> struct Chunk16 { XT v[16 / sizeof(XT)]; };
+
+// Stage fast indices wbase .. wbase + W of Kfast into LDS rows of ldk
+// elements (the hi rows 0 .. RP - 1, then the lo rows), 16-byte chunks
+// XOR-swizzled with swz; nthr threads of the workgroup take part.
+template <typename XT, bool HL>
+__device__ __forceinline__ void stage_copy(const XT *kfast, XT *sk, int RP, int64_t Pf,
+                                           int64_t wbase, int W, int ldk, int swz, int nthr) {
+  constexpr int SV = 16 / (int)sizeof(XT);
+  const int nv = W / SV;
+  const int total = RP * nv * (HL ? 2 : 1);
+  for (int e = threadIdx.x; e < total; e += nthr) {
+    const int h = e / (RP * nv);
+    const int rem = e - h * RP * nv;
+    const int r = rem / nv, v = rem - r * nv;
+    *reinterpret_cast<u32x4 *>(sk + h * RP * ldk + kidx<XT>(r, v * SV, ldk, swz)) =
+        *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + wbase + v * SV);
+  }
+}
+
+template <typename XT, bool HL>
+__device__ __forceinline__ void stage_kfast(const KOp<XT> &ko, XT *sk, int RP, int R, int64_t Pf,
+                                            int64_t wbase, int W, int ldk, int swz, int nthr) {
+  typedef typename XTraits<XT>::AT AT;
+  constexpr int SV = 16 / (int)sizeof(XT);
+  const int nv = W / SV;
+  if (ko.hf == nullptr) {
+    stage_copy<XT, HL>(ko.kfast, sk, RP, Pf, wbase, W, ldk, swz, nthr);
+  } else if (R % (8 / (int)sizeof(AT) > 0 ? 8 / (int)sizeof(AT) : 1) == 0) {
+    // thread e: columns r0 .. r0 + RV - 1 (r0 = RV (e % (RP / RV))) at fast
+    // indices v SV .. v SV + SV - 1 (v = e / (RP / RV)): SV 16-byte loads of
+    // factor rows (consecutive threads read consecutive pieces of a row),
+    // RV 16-byte LDS chunks per half
+    constexpr int RV = 8 / (int)sizeof(AT) > 0 ? 8 / (int)sizeof(AT) : 1;
+    const int nrv = RP / RV;
+    for (int e = threadIdx.x; e < nrv * nv; e += nthr) {
+      const int r0 = RV * (e % nrv), v = e / nrv;
+      AT x[SV][RV];
+#pragma unroll
+      for (int q = 0; q < SV; ++q) {
+        typedef AT avec __attribute__((ext_vector_type(RV)));
+        avec t;
+        if (r0 < R) {
+          t = *reinterpret_cast<const avec *>(ko.hf + (wbase + v * SV + q) * R + r0);
+        } else {
+#pragma unroll
+          for (int u = 0; u < RV; ++u) t[u] = (AT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < RV; ++u) x[q][u] = t[u];
+      }
+#pragma unroll
+      for (int u = 0; u < RV; ++u) {
+        Chunk16<XT> hi, lo;
+#pragma unroll
+        for (int q = 0; q < SV; ++q) {
+          const double xv = (double)x[q][u];
+          hi.v[q] = from_d<XT>(xv);
+          if (HL) lo.v[q] = from_d<XT>(xv - to_d<XT>(hi.v[q]));
+        }
+        XT *d = sk + kidx<XT>(r0 + u, v * SV, ldk, swz);
+        *reinterpret_cast<u32x4 *>(d) = __builtin_bit_cast(u32x4, hi);
+        if (HL) *reinterpret_cast<u32x4 *>(d + RP * ldk) = __builtin_bit_cast(u32x4, lo);
+      }
+    }
+  } else {
+    // thread e: column r = e % RP at fast indices v SV .. v SV + SV - 1 of
+    // the window (consecutive threads read consecutive entries of a row)
+    for (int e = threadIdx.x; e < RP * nv; e += nthr) {
+      const int r = e % RP, v = e / RP;
+      const int rc = r < R ? r : R - 1;
+      Chunk16<XT> hi, lo;
+#pragma unroll
+      for (int q = 0; q < SV; ++q) {
+        const double x = (double)ko.hf[(wbase + v * SV + q) * R + rc];
+        const double xv = r < R ? x : 0.0;
+        hi.v[q] = from_d<XT>(xv);
+        if (HL) lo.v[q] = from_d<XT>(xv - to_d<XT>(hi.v[q]));
+      }
+      *reinterpret_cast<u32x4 *>(sk + kidx<XT>(r, v * SV, ldk, swz)) = __builtin_bit_cast(u32x4, hi);
+      if (HL)
+        *reinterpret_cast<u32x4 *>(sk + RP * ldk + kidx<XT>(r, v * SV, ldk, swz)) =
+            __builtin_bit_cast(u32x4, lo);
+    }
+  }
+}
+
+// Kslow(b, r) where there is a slow part (r < Rpad: the direct form is used
+// only when R == Rpad)
+template <typename XT>
+__device__ __forceinline__ typename XTraits<XT>::AT kslow_at(const KOp<XT> &ko, int64_t b, int r) {
+  return ko.kslow[b * ko.ldks + r];
+}
+// the column scale of a product without slow modes: one, or the FP16 column
+// scaling of the precomputed operand
+template <typename XT>
+__device__ __forceinline__ typename XTraits<XT>::AT kscale0(const KOp<XT> &ko, int r) {
+  typedef typename XTraits<XT>::AT AT;
+  return ko.kslow ? ko.kslow[r] : (AT)1;
+}
+
+// ---------------------------------------------------------------------------
 // right partial MTTKRP on the matrix cores (reduction over the contiguous index)
 //
 // Workgroup = kRightWaves waves on the same 16*MT rows of Xr; the
@@ -212,9 +330,18 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
 
 template <typename XT, int MT, int NT, bool HL, bool SLOW, int U, bool ILV>
 __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
-    const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
-    const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int64_t steps_total, int nsplit,
-    int R, typename XTraits<XT>::AT *__restrict__ out) {
+    const XT *__restrict__ X, int64_t m, int64_t k, KOp<XT> ko, int Pf, int64_t steps_total,
+    int nsplit, int R, typename XTraits<XT>::AT *__restrict__ out, int ntx, GramJob job) {
+  // workgroups past the product's ntx x nsplit (extra columns when nsplit is
+  // 1, else extra rows: dispatched after every product workgroup) carry the
+  // split Gram step of the previous update
+  if (job.R) {
+    const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (lin >= ntx * nsplit) {
+      if (lin - ntx * nsplit < job.parts) gram_part(job, lin - ntx * nsplit);
+      return;
+    }
+  }
   typedef typename XTraits<XT>::AT AT;
   typedef typename CFrag<AT>::T CT;
   constexpr int VEC = XTraits<XT>::VEC;
@@ -226,17 +353,7 @@ __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
   const int ldk = swz ? Pf : Pf + VEC;
 
   // stage Kfast (hi, then lo) into LDS
-  {
-    const int nv = Pf / VEC;
-    const int total = RP * nv * (HL ? 2 : 1);
-    for (int e = threadIdx.x; e < total; e += 64 * kRightWaves) {
-      const int h = e / (RP * nv);
-      const int rem = e - h * RP * nv;
-      const int r = rem / nv, v = rem - r * nv;
-      *reinterpret_cast<u32x4 *>(sk + h * RP * ldk + kidx<XT>(r, v * VEC, ldk, swz)) =
-          *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + v * VEC);
-    }
-  }
+  stage_kfast<XT, HL>(ko, sk, RP, R, Pf, 0, Pf, ldk, swz, 64 * kRightWaves);
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -269,7 +386,7 @@ __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
   auto flush = [&]() {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const AT s = kslow[bI * RP + 16 * nt + row];
+      const AT s = kslow_at(ko, bI, 16 * nt + row);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
@@ -419,7 +536,7 @@ __global__ __launch_bounds__(64 * kRightWaves) void k_gemm_right_mfma(
   if (!SLOW) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const AT s = kslow[16 * nt + row];
+      const AT s = kscale0(ko, 16 * nt + row);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -483,9 +600,19 @@ __device__ __forceinline__ uint32_t dw(const u32x2 &v, int i) { return v[i]; }
 
 template <typename XT, int QV, int NT, bool HL, bool SLOW, bool NTL>
 __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_gemm_left_mfma(
-    const XT *__restrict__ X, int64_t m, int64_t k, const XT *__restrict__ kfast,
-    const typename XTraits<XT>::AT *__restrict__ kslow, int Pf, int W, int64_t steps_total,
-    int nsplit, int R, typename XTraits<XT>::AT *__restrict__ out) {
+    const XT *__restrict__ X, int64_t m, int64_t k, KOp<XT> ko, int Pf, int W,
+    int64_t steps_total, int nsplit, int R, typename XTraits<XT>::AT *__restrict__ out, int ntx,
+    GramJob job) {
+  // workgroups past the product's ntx x nsplit (extra columns when nsplit is
+  // 1, else extra rows: dispatched after every product workgroup) carry the
+  // split Gram step of the previous update
+  if (job.R) {
+    const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (lin >= ntx * nsplit) {
+      if (lin - ntx * nsplit < job.parts) gram_part(job, lin - ntx * nsplit);
+      return;
+    }
+  }
   typedef typename XTraits<XT>::AT AT;
   typedef typename CFrag<AT>::T CT;
   constexpr int WV = left_waves(sizeof(XT), QV, NT, SLOW);
@@ -502,17 +629,8 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
   // cross into the next window (once per workgroup when W == Pf)
   const int swz = ((W / SVEC) % 16 == 0) ? 15 : 0;
   const int ldk = swz ? W : W + SVEC;
-  auto stage = [&](int wbase) {
-    const int nv = W / SVEC;
-    const int total = RP * nv * (HL ? 2 : 1);
-    for (int e = threadIdx.x; e < total; e += 64 * WV) {
-      const int h = e / (RP * nv);
-      const int rem = e - h * RP * nv;
-      const int r = rem / nv, v = rem - r * nv;
-      *reinterpret_cast<u32x4 *>(sk + h * RP * ldk + kidx<XT>(r, v * SVEC, ldk, swz)) =
-          *reinterpret_cast<const u32x4 *>(kfast + ((int64_t)(h * RP + r)) * Pf + wbase + v * SVEC);
-    }
-  };
+  // precomputed operand windows, staged inside the loop
+  auto stage = [&](int wbase) { stage_copy<XT, HL>(ko.kfast, sk, RP, Pf, wbase, W, ldk, swz, 64 * WV); };
   int cur_w = -1;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -550,9 +668,18 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
         else dst[b * KL + u] = gload_c<LT>(xp + (tt * KSTEP + u) * m);
     }
   };
+  if (s_lo < s_hi) load_batch(buf[0], s_lo);
+  if (ko.hf) {
+    // the operand formed from the factors (one window, W == Pf), staged
+    // while the first batch is in flight and before the next ones are
+    // issued (fewer registers live than inside the loop)
+    stage_kfast<XT, HL>(ko, sk, RP, R, Pf, 0, W, ldk, swz, 64 * WV);
+    __syncthreads();
+    cur_w = 0;
+  }
   if (s_lo < s_hi) {
 #pragma unroll
-    for (int j = 0; j < NB - 1; ++j) load_batch(buf[j], s_lo + j * SB);
+    for (int j = 1; j < NB - 1; ++j) load_batch(buf[j], s_lo + j * SB);
   }
   // position in the fast block, window index and block index, advanced with
   // the steps (one division at the start)
@@ -615,7 +742,7 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
         if (SLOW && (wrap || t + 1 == s_hi)) {
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
-            const AT sc = kslow[bI * RP + 16 * nt + rho];
+            const AT sc = kslow_at(ko, bI, 16 * nt + rho);
 #pragma unroll
             for (int q = 0; q < QV; ++q) {
 #pragma unroll
@@ -646,7 +773,7 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
   const bool vec_ok = (m % VE) == 0;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
-    const AT s = SLOW ? (AT)1 : kslow[16 * nt + rho];
+    const AT s = SLOW ? (AT)1 : kscale0(ko, 16 * nt + rho);
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -685,15 +812,6 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
   }
 }
 
-// Cross-lane exchange through LDS inside one wave: the wave's LDS accesses
-// are performed in order, so a wavefront-scope fence with a scheduling
-// barrier is all that orders one lane's write before another lane's read.
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---------------------------------------------------------------------------
 // Both partial MTTKRPs of the root in one pass over X (the gradient, where
 // every mode's MTTKRP is taken at the same factors):
@@ -728,6 +846,7 @@ struct DualArgs {
   int64_t m, k;
   int PfL;             // fast length of K_L (a multiple of 32), staged whole
   int R;
+  int rmaj;            // right partials [tile][R][k] (else [tile][k][R])
 };
 
 template <typename XT, int NT, bool HL, bool NTL>
@@ -912,28 +1031,45 @@ __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
           }
         }
       }
-      // ---- the waves' T_R results of this step, added in wave order
+      // ---- the waves' T_R results of this step, added in wave order.  Lane
+      // l's fragment (h, nt) holds rows jj = 16 h + 4 (l / 16) + v (v < 4) of
+      // the step at column r = 16 nt + l % 16; its 16-byte piece goes to
+      // chunk (h NT + nt) ^ (l / 16) of the lane's slot row, so that the
+      // readers below, which take the four rows of one column from the
+      // lanes l % 16 = r % 16, spread over the banks.
       float *slot = str + ((int)(t & 1) * WV + wave) * SLOT;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          *reinterpret_cast<f32x4 *>(slot + lane * (8 * NT) + (h * NT + nt) * 4) = cr[h][nt];
+          const int ch = (h * NT + nt) ^ (g & (2 * NT - 1));
+          *reinterpret_cast<f32x4 *>(slot + lane * (8 * NT) + ch * 4) = cr[h][nt];
           czero(cr[h][nt]);
         }
       __syncthreads();
-      // output (row jj of the step, column r): lane (r % 16) + 16 ((jj % 16) / 4),
-      // entry (jj / 16, r / 16, jj % 4) of its fragments
-      for (int e = tid; e < 32 * RP; e += 64 * WV) {
-        const int jj = e / RP, r = e - jj * RP;
-        const int sl = (r & 15) + 16 * ((jj & 15) >> 2);
-        const int off = sl * (8 * NT) + ((jj >> 4) * NT + (r >> 4)) * 4 + (jj & 3);
-        const float *sb = str + (int)(t & 1) * WV * SLOT;
-        float s = sb[off];
+      // thread (r, q): rows 4 q .. 4 q + 3 of the step at column r, one
+      // 16-byte piece per wave
+      if (tid < 8 * RP) {
+        const int q = tid & 7, r = tid >> 3;
+        const int sl = (r & 15) + 16 * (q & 3);
+        const int ch = ((q >> 2) * NT + (r >> 4)) ^ ((q & 3) & (2 * NT - 1));
+        const float *sb = str + (int)(t & 1) * WV * SLOT + sl * (8 * NT) + ch * 4;
+        f32x4 s = *reinterpret_cast<const f32x4 *>(sb);
+#pragma unroll 2
+        for (int w = 1; w < WV; ++w) {
+          const f32x4 v = *reinterpret_cast<const f32x4 *>(sb + w * SLOT);
+          s[0] += v[0]; s[1] += v[1]; s[2] += v[2]; s[3] += v[3];
+        }
+        if (r < a.R) {
+          const int64_t j = j0 + 4 * q;  // k is a multiple of 32
+          if (a.rmaj) {
+            *reinterpret_cast<f32x4 *>(out_r + ((int64_t)blockIdx.x * a.R + r) * k + j) = s;
+          } else {
+            float *o = out_r + ((int64_t)blockIdx.x * k + j) * a.R + r;
 #pragma unroll
-        for (int w = 1; w < WV; ++w) s += sb[w * SLOT + off];
-        const int64_t j = j0 + jj;
-        if (r < a.R && j < k) out_r[((int64_t)blockIdx.x * k + j) * a.R + r] = s;
+            for (int v = 0; v < 4; ++v) o[(int64_t)v * a.R] = s[v];
+          }
+        }
       }
     }
   }
@@ -1140,34 +1276,64 @@ hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t 
   return hipGetLastError();
 }
 
+// The operand of plan p: the factors themselves when p.direct, else the
+// precomputed kf / ks.
+template <typename XT>
+static KOp<XT> make_kop(const GemmPlan &p, int R, const FactorSet &F, const void *kf,
+                        const void *ks) {
+  typedef typename XTraits<XT>::AT AT;
+  KOp<XT> ko;
+  if (p.direct) {
+    ko.kfast = nullptr;
+    ko.hf = (const AT *)F.H[p.fast_lo];
+    ko.kslow = p.slow_hi > p.slow_lo ? (const AT *)F.H[p.slow_lo] : nullptr;
+    ko.ldks = R;
+  } else {
+    ko.kfast = (const XT *)kf;
+    ko.hf = nullptr;
+    ko.kslow = (const AT *)ks;
+    ko.ldks = p.Rpad;
+  }
+  return ko;
+}
+
+// grid of a product that carries a split Gram step: its workgroups come
+// after the product's in dispatch order (extra columns when nsplit is 1,
+// else extra rows), so that they never hold a CU a product workgroup waits for
+static dim3 carry_grid(const GemmPlan &p, const GramJob &job) {
+  const int gb = job.R ? job.parts : 0;
+  if (p.nsplit == 1) return dim3((unsigned)(p.tiles + gb), 1);
+  return dim3((unsigned)p.tiles, (unsigned)(p.nsplit + (gb + p.tiles - 1) / p.tiles));
+}
+
 template <typename XT, int MT, int NT, bool HL, bool SLOW>
-static void run_right(const GemmPlan &p, int R, const void *X, const void *kf, const void *ks,
-                      void *out, hipStream_t st) {
+static void run_right(const GemmPlan &p, int R, const void *X, const KOp<XT> &ko, void *out,
+                      const GramJob &job, hipStream_t st) {
   typedef typename XTraits<XT>::AT AT;
   constexpr int KSTEP = 4 * XTraits<XT>::VEC;
-  dim3 grid((unsigned)p.tiles, p.nsplit), block(64 * kRightWaves);
+  dim3 grid = carry_grid(p, job), block(64 * kRightWaves);
   // the waves take contiguous ranges (batches dealt in turn measured 1.5%
   // faster at 512^3 BF16 but 3% slower on the 256^4 tensor)
   constexpr bool ILV = false;
   hipLaunchKernelGGL((k_gemm_right_mfma<XT, MT, NT, HL, SLOW, 4, ILV>), grid, block, p.lds_bytes,
-                     st, (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf,
-                     (p.m / KSTEP), p.nsplit, R, (AT *)out);
+                     st, (const XT *)X, p.m, p.k, ko, (int)p.Pf, (p.m / KSTEP), p.nsplit, R,
+                     (AT *)out, (int)p.tiles, job);
 }
 
 template <typename XT, int QV, int NT, bool HL, bool SLOW>
-static void run_left(const GemmPlan &p, int R, const void *X, const void *kf, const void *ks,
-                     void *out, hipStream_t st) {
+static void run_left(const GemmPlan &p, int R, const void *X, const KOp<XT> &ko, void *out,
+                     const GramJob &job, hipStream_t st) {
   typedef typename XTraits<XT>::AT AT;
   constexpr int KSTEP = 4 * XTraits<XT>::KL;
-  dim3 grid((unsigned)p.tiles, p.nsplit), block(64 * left_waves(sizeof(XT), QV, NT, SLOW));
+  dim3 grid = carry_grid(p, job), block(64 * left_waves(sizeof(XT), QV, NT, SLOW));
   if (p.nt_loads)
     hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW, true>), grid, block, p.lds_bytes, st,
-                       (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf, (int)p.W,
-                       (p.k / KSTEP), p.nsplit, R, (AT *)out);
+                       (const XT *)X, p.m, p.k, ko, (int)p.Pf, (int)p.W, (p.k / KSTEP), p.nsplit,
+                       R, (AT *)out, (int)p.tiles, job);
   else
     hipLaunchKernelGGL((k_gemm_left_mfma<XT, QV, NT, HL, SLOW, false>), grid, block, p.lds_bytes, st,
-                       (const XT *)X, p.m, p.k, (const XT *)kf, (const AT *)ks, (int)p.Pf, (int)p.W,
-                       (p.k / KSTEP), p.nsplit, R, (AT *)out);
+                       (const XT *)X, p.m, p.k, ko, (int)p.Pf, (int)p.W, (p.k / KSTEP), p.nsplit,
+                       R, (AT *)out, (int)p.tiles, job);
 }
 
 // NT dispatch (1..4) with the template flags fixed
@@ -1188,43 +1354,45 @@ static void run_left(const GemmPlan &p, int R, const void *X, const void *kf, co
   }
 
 template <typename XT>
-static hipError_t dispatch_mfma(const GemmPlan &p, int R, const void *X, const void *kf,
-                                const void *ks, void *out, hipStream_t st) {
+static hipError_t dispatch_mfma(const GemmPlan &p, int R, const void *X, const FactorSet &F,
+                                const void *kf, const void *ks, void *out, const GramJob &job,
+                                hipStream_t st) {
   constexpr bool IS16 = sizeof(XT) == 2;
+  const KOp<XT> ko = make_kop<XT>(p, R, F, kf, ks);
   const bool slow = p.Ps > 1;
   if (p.side == 1) {
     constexpr int MT = sizeof(XT) == 8 ? 1 : 2;
     if (IS16 && p.hl) {
-      if (slow) { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, IS16, true>(p, R, X, kf, ks, out, st))) }
-      else { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, IS16, false>(p, R, X, kf, ks, out, st))) }
+      if (slow) { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, IS16, true>(p, R, X, ko, out, job, st))) }
+      else { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, IS16, false>(p, R, X, ko, out, job, st))) }
     } else {
-      if (slow) { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, false, true>(p, R, X, kf, ks, out, st))) }
-      else { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+      if (slow) { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, false, true>(p, R, X, ko, out, job, st))) }
+      else { NNCP_NT_SWITCH(p.NT, (run_right<XT, MT, NTC, false, false>(p, R, X, ko, out, job, st))) }
     }
   } else {
     // columns per lane: 8 (16 B) for 16-bit types up to 32 columns of R, else 4
     if constexpr (IS16) {
       if (p.NT <= 2) {
         if (p.hl) {
-          if (slow) { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, IS16, true>(p, R, X, kf, ks, out, st))) }
-          else { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, IS16, false>(p, R, X, kf, ks, out, st))) }
+          if (slow) { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, IS16, true>(p, R, X, ko, out, job, st))) }
+          else { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, IS16, false>(p, R, X, ko, out, job, st))) }
         } else {
-          if (slow) { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, false, true>(p, R, X, kf, ks, out, st))) }
-          else { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+          if (slow) { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, false, true>(p, R, X, ko, out, job, st))) }
+          else { NNCP_NT_SWITCH12(p.NT, (run_left<XT, 8, NTC, false, false>(p, R, X, ko, out, job, st))) }
         }
       } else {
         if (p.hl) {
-          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, IS16, true>(p, R, X, kf, ks, out, st))) }
-          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, IS16, false>(p, R, X, kf, ks, out, st))) }
+          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, IS16, true>(p, R, X, ko, out, job, st))) }
+          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, IS16, false>(p, R, X, ko, out, job, st))) }
         } else {
-          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, false, true>(p, R, X, kf, ks, out, st))) }
-          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+          if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, false, true>(p, R, X, ko, out, job, st))) }
+          else { NNCP_NT_SWITCH(p.NT, (run_left<XT, 4, NTC, false, false>(p, R, X, ko, out, job, st))) }
         }
       }
     } else {
       constexpr int QV = 16 / sizeof(XT);
-      if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, QV, NTC, false, true>(p, R, X, kf, ks, out, st))) }
-      else { NNCP_NT_SWITCH(p.NT, (run_left<XT, QV, NTC, false, false>(p, R, X, kf, ks, out, st))) }
+      if (slow) { NNCP_NT_SWITCH(p.NT, (run_left<XT, QV, NTC, false, true>(p, R, X, ko, out, job, st))) }
+      else { NNCP_NT_SWITCH(p.NT, (run_left<XT, QV, NTC, false, false>(p, R, X, ko, out, job, st))) }
     }
   }
   return hipGetLastError();
@@ -1254,16 +1422,22 @@ static hipError_t dispatch_generic(const GemmPlan &p, int R, const void *X, cons
 hipError_t launch_partial_mttkrp(int xdt, const GemmPlan &p, int R, const void *X,
                                  const int64_t *dims, int N, int S, const FactorSet &F,
                                  const void *kfast, const void *kslow, void *out,
-                                 hipStream_t st) {
+                                 hipStream_t st, GramJob *carry) {
   if (p.mfma) {
+    const GramJob job = carry ? *carry : GramJob{};
+    // only a split Gram step rides along (its workgroups are light)
+    if (job.R && job.parts == 0) return hipErrorInvalidValue;
+    if (carry) carry->R = 0;
+    if (p.direct && xdt == NNCP_F16) return hipErrorInvalidValue;  // needs the column scaling
     switch (xdt) {
-      case NNCP_BF16: return dispatch_mfma<bf16_t>(p, R, X, kfast, kslow, out, st);
-      case NNCP_F16: return dispatch_mfma<f16_t>(p, R, X, kfast, kslow, out, st);
-      case NNCP_F32: return dispatch_mfma<float>(p, R, X, kfast, kslow, out, st);
-      case NNCP_F64: return dispatch_mfma<double>(p, R, X, kfast, kslow, out, st);
+      case NNCP_BF16: return dispatch_mfma<bf16_t>(p, R, X, F, kfast, kslow, out, job, st);
+      case NNCP_F16: return dispatch_mfma<f16_t>(p, R, X, F, kfast, kslow, out, job, st);
+      case NNCP_F32: return dispatch_mfma<float>(p, R, X, F, kfast, kslow, out, job, st);
+      case NNCP_F64: return dispatch_mfma<double>(p, R, X, F, kfast, kslow, out, job, st);
     }
     return hipErrorInvalidValue;
   }
+  if (carry && carry->R) return hipErrorInvalidValue;  // the caller runs it first
   switch (xdt) {
     case NNCP_BF16: return dispatch_generic<bf16_t, float>(p, R, X, dims, N, S, F, out, st);
     case NNCP_F16: return dispatch_generic<f16_t, float>(p, R, X, dims, N, S, F, out, st);
@@ -1286,13 +1460,14 @@ int64_t dual_tiles(int64_t m) { return (m + 128 * kDualWaves - 1) / (128 * kDual
 
 hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, int R,
                               const void *X, const void *kfr, const void *kfl, const void *ksl,
-                              void *out_l, void *out_r, hipStream_t st) {
-  if (xdt != NNCP_BF16 || pl.NT > 2) return hipErrorInvalidValue;
+                              void *out_l, void *out_r, int r_major, hipStream_t st) {
+  if (xdt != NNCP_BF16 || pl.NT > 2 || pl.k % 32 != 0) return hipErrorInvalidValue;
   DualArgs a;
   a.m = pl.m;
   a.k = pl.k;
   a.PfL = (int)pr.Pf;
   a.R = R;
+  a.rmaj = r_major ? 1 : 0;
   const size_t lds = dual_lds_bytes(pl.NT, pl.hl, pr.Pf);
   dim3 grid((unsigned)dual_tiles(pl.m)), block(64 * kDualWaves);
 #define NNCP_DUAL(NTV, HLV, NTLV)                                                                 \
@@ -1313,9 +1488,9 @@ hipError_t launch_dual_mttkrp(int xdt, const GemmPlan &pl, const GemmPlan &pr, i
 }
 
 hipError_t launch_finalize(int hdt, const GemmPlan &p, int R, const void *part, void *out,
-                           int leaf, hipStream_t st) {
+                           int leaf, hipStream_t st, int part_rmajor) {
   const int64_t rows = p.side == 1 ? p.k : p.m;
-  const int rmajor = p.side == 0;
+  const int rmajor = part_rmajor >= 0 ? part_rmajor : p.side == 0;
   const int64_t n = rows * R;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (hdt == NNCP_F64)

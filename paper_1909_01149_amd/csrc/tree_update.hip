@@ -1592,60 +1592,77 @@ __global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
 // ---------------------------------------------------------------------------
 // projected gradient helpers
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pgd_eta(const double *__restrict__ G, int N, int R,
+// Step size of the projected gradient: 1 / max_n lambda_max(S^(n)), each
+// lambda_max by `iters` power steps from the normalised all-ones vector and a
+// final Rayleigh quotient.  One wave per mode (modes n, n + 8, ... for wave
+// n of eight): lane i < R keeps row i of S^(n) = prod_{k != n} G^(k) in
+// registers (the Grams' rows read mode by mode, all loads of a mode in
+// flight together).  The iterate v and w = S v go through the wave's LDS
+// rows; every lane forms the norm of w and the Rayleigh quotient itself from
+// them (the same sums in j order, so every lane holds the same value).
+template <int RB>
+__global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, int N, int R,
                                                  int iters, double *__restrict__ eta) {
-  extern __shared__ double sh[];
-  double *S = sh;              // R*R
-  double *v = sh + R * R;      // R
-  double *w = v + R;           // R
-  __shared__ double red[256];
+  __shared__ double vs[8][RB];
+  __shared__ double ws[8][RB];
+  __shared__ double lm[8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool own = lane < R;
+  const int i = own ? lane : 0;
   double lmax = 0.0;
-  for (int n = 0; n < N; ++n) {
-    for (int e = threadIdx.x; e < R * R; e += 256) {
-      double s = 1.0;
-      for (int k = 0; k < N; ++k)
-        if (k != n) s *= G[(int64_t)k * R * R + e];
-      S[e] = s;
+  for (int n = wave; n < N; n += 8) {
+    double srow[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) srow[j] = 1.0;
+    for (int k = 0; k < N; ++k) {
+      if (k == n) continue;
+      const double *gr = G + (int64_t)k * R * R + (int64_t)i * R;
+      double g[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) g[j] = j < R ? gr[j] : 1.0;
+#pragma unroll
+      for (int j = 0; j < RB; ++j) srow[j] *= g[j];
     }
-    for (int i = threadIdx.x; i < R; i += 256) v[i] = 1.0 / sqrt((double)R);
-    __syncthreads();
-    bool zero = false;
-    for (int t = 0; t < iters && !zero; ++t) {
-      double part = 0.0;
-      for (int i = threadIdx.x; i < R; i += 256) {
-        double s = 0.0;
-        for (int j = 0; j < R; ++j) s += S[i * R + j] * v[j];
-        w[i] = s;
-        part += s * s;
-      }
-      red[threadIdx.x] = part;
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-      }
-      const double nrm = sqrt(red[0]);
-      __syncthreads();
-      if (!(nrm > 0.0)) { zero = true; break; }
-      for (int i = threadIdx.x; i < R; i += 256) v[i] = w[i] / nrm;
-      __syncthreads();
+    auto matvec = [&]() {
+      double w = 0.0;
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < R) w += srow[j] * vs[wave][j];
+      return own ? w : 0.0;
+    };
+    auto dot = [&](const double *x, const double *y) {
+      double d = 0.0;
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < R) d += x[j] * y[j];
+      return d;
+    };
+    if (lane < RB) vs[wave][lane] = own ? 1.0 / sqrt((double)R) : 0.0;
+    wave_sync_lds();
+    for (int t = 0; t < iters; ++t) {
+      const double w = matvec();
+      if (lane < RB) ws[wave][lane] = w;
+      wave_sync_lds();
+      const double nrm = sqrt(dot(ws[wave], ws[wave]));
+      if (!(nrm > 0.0)) break;
+      if (own) vs[wave][lane] = w / nrm;
+      wave_sync_lds();
     }
-    double part = 0.0;
-    for (int i = threadIdx.x; i < R; i += 256) {
-      double s = 0.0;
-      for (int j = 0; j < R; ++j) s += S[i * R + j] * v[j];
-      part += v[i] * s;
-    }
-    red[threadIdx.x] = part;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (red[0] > lmax) lmax = red[0];
-    __syncthreads();
+    const double w = matvec();
+    wave_sync_lds();
+    if (lane < RB) ws[wave][lane] = w;
+    wave_sync_lds();
+    const double rq = dot(vs[wave], ws[wave]);
+    if (rq > lmax) lmax = rq;
+    wave_sync_lds();
   }
-  if (threadIdx.x == 0) eta[0] = lmax > 0.0 ? 1.0 / lmax : 1.0;
+  if (lane == 0) lm[wave] = lmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double l = lm[0];
+    for (int w = 1; w < 8; ++w) l = lm[w] > l ? lm[w] : l;
+    eta[0] = l > 0.0 ? 1.0 / l : 1.0;
+  }
 }
 
 template <typename HT>
@@ -2190,8 +2207,9 @@ hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M
 
 hipError_t launch_pgd_eta(const double *G, int N, int R, int iters, double *eta, hipStream_t st) {
   if (R > 64) return hipErrorInvalidValue;
-  const size_t sh = sizeof(double) * (R * R + 2 * R);
-  hipLaunchKernelGGL(k_pgd_eta, dim3(1), dim3(256), sh, st, G, N, R, iters, eta);
+  if (R <= 16) hipLaunchKernelGGL((k_pgd_eta<16>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);
+  else if (R <= 32) hipLaunchKernelGGL((k_pgd_eta<32>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);
+  else hipLaunchKernelGGL((k_pgd_eta<64>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);
   return hipGetLastError();
 }
 

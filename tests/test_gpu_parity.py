@@ -300,6 +300,23 @@ def test_pgd_fp64_matches_oracle(nn):
     ctx.close()
 
 
+def test_pgd_fp64_five_modes_rank40_matches_oracle(nn):
+    """The step size's power iterations at R = 40 (the 64-row variant, lanes
+    40..63 idle) over five modes (one wave each)."""
+    banner("pgd 5 modes R 40")
+    dims = [10, 9, 8, 7, 6]
+    X64, H64 = gen.small_lowrank(dims, 6, 40, 21, noise=0.05)
+    X, H, Xo, Ho = prepare(X64, H64, "f64")
+    ctx = nn.Context(X, H)
+    lh, eh = ctx.pgd(5)
+    Hr, lho, eho = oracle.pgd(Xo, Ho, 5)
+    np.testing.assert_allclose(eh, eho, rtol=1e-10)
+    np.testing.assert_allclose(lh, lho, rtol=1e-8)
+    for a, b in zip(ctx.factors, Hr):
+        assert relerr(a.cpu().numpy(), b) <= 1e-8
+    ctx.close()
+
+
 def test_sweep_is_deterministic(nn):
     banner("determinism")
     dims = [64, 64, 64]
