@@ -445,6 +445,12 @@ def main():
                             "and NES with the outer step "
                             "(timed and untimed passes)")
             return
+        if len(sys.argv) > 3 and sys.argv[3] == "grad":
+            summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
+                            f"{pa} -- python3 bench.py --configs c5", "kernels_64x5_grad.txt",
+                            "64x64x64x64x64 R=32 gradient workload (FP32 and BF16 tensors: "
+                            "timed gradients and 100 PGD steps each)")
+            return
         if len(sys.argv) > 3 and sys.argv[3] == "anchor":
             summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
                             f"{pa} -- python3 bench.py --anchor-only", "kernels_256x4_hals.txt",

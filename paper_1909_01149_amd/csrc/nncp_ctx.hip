@@ -1274,16 +1274,21 @@ static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const
   for (int n = 0; n < L.N; ++n) {
     int rc = NNCP_OK;
     Mn = c->M;
+    // before the last mode, split partials of M^(n) are left for the
+    // gradient kernel to add (the loss needs M^(N-1) itself)
+    MRef mr{c->M, 1, 0};
+    MRef *dp = grads && n < L.N - 1 ? &mr : nullptr;
     if (dual) {
       if (n == L.S && L.N - L.S == 1) {
         Mn = c->nodeR;  // M^(N-1), added from the fused pass's partials
+        mr = MRef{Mn, 1, 0};
       } else {
         c->right_root_in_R = true;
-        rc = mttkrp_tree(c, F, n, c->M, false, nullptr, true);
+        rc = mttkrp_tree(c, F, n, c->M, false, dp, true);
         c->right_root_in_R = false;
       }
     } else {
-      rc = mttkrp_tree(c, F, n, c->M, false);
+      rc = mttkrp_tree(c, F, n, c->M, false, dp);
     }
     if (rc) return rc;
     if (grads) {
@@ -1292,7 +1297,8 @@ static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const
         HIPCHK(launch_hadamard(G, L.N, L.R, n, c->S, c->st));
         S = c->S;
       }
-      HIPCHK(launch_grad(L.hdt, L.dims[n], L.R, L.N, n, Mn, F.H[n], G, S, grads[n], c->st));
+      HIPCHK(launch_grad(L.hdt, L.dims[n], L.R, L.N, n, mr.p, mr.msplit, mr.mstride, F.H[n], G, S,
+                         grads[n], c->st));
     }
   }
   const int n = L.N - 1;

@@ -551,9 +551,11 @@ hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const v
                        const double *lambda, const double *G, const double *alpha, double *loss,
                        double *relerr, double *scal, hipStream_t st);
 
-// grad = H S - M (lambda = 1), S from the Grams (R <= 64) or the given S
-hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M, const void *H,
-                       const double *G, const double *S, void *grad, hipStream_t st);
+// grad = H S - M (lambda = 1), S from the Grams (R <= 64) or the given S;
+// M is msplit partial copies mstride apart, added in order (1: M itself)
+hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M, int msplit,
+                       int64_t mstride, const void *H, const double *G, const double *S,
+                       void *grad, hipStream_t st);
 
 // eta0 = 1 / max_n lmax(S^(n)) by power iteration; writes eta[0] (R <= 64)
 hipError_t launch_pgd_eta(const double *G, int N, int R, int iters, double *eta, hipStream_t st);

@@ -668,18 +668,17 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
         else dst[b * KL + u] = gload_c<LT>(xp + (tt * KSTEP + u) * m);
     }
   };
-  if (s_lo < s_hi) load_batch(buf[0], s_lo);
+  if (s_lo < s_hi) {
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) load_batch(buf[j], s_lo + j * SB);
+  }
   if (ko.hf) {
     // the operand formed from the factors (one window, W == Pf), staged
-    // while the first batch is in flight and before the next ones are
-    // issued (fewer registers live than inside the loop)
+    // while the first batches are in flight (outside the loop, where fewer
+    // registers are live)
     stage_kfast<XT, HL>(ko, sk, RP, R, Pf, 0, W, ldk, swz, 64 * WV);
     __syncthreads();
     cur_w = 0;
-  }
-  if (s_lo < s_hi) {
-#pragma unroll
-    for (int j = 1; j < NB - 1; ++j) load_batch(buf[j], s_lo + j * SB);
   }
   // position in the fast block, window index and block index, advanced with
   // the steps (one division at the start)

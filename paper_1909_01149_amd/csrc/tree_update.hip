@@ -172,6 +172,58 @@ __global__ __launch_bounds__(256) void k_mttv_contig_reg(const HT *__restrict__ 
   }
 }
 
+// Same reduction for Ia = GL V with GL < 64 a power of two: GL lanes per
+// output, so that a wave's load takes 64 / GL whole consecutive rows of T
+// (1 KB) instead of one row on GL of its 64 lanes; eight such loads per
+// lane are issued first.  The pieces of an output are added by a butterfly
+// over its GL lanes, which is the wave-wide butterfly of the kernel above
+// with the stages that only add the idle lanes' zeros left out.
+template <typename HT, int GL>
+__global__ __launch_bounds__(256) void k_mttv_contig_pack(const HT *__restrict__ T, int64_t Ia,
+                                                          int64_t Q, int R,
+                                                          const HT *__restrict__ H,
+                                                          HT *__restrict__ out, int leaf,
+                                                          GramJob job) {
+  constexpr int V = 16 / (int)sizeof(HT);
+  constexpr int OPL = 64 / GL;  // outputs per load of a wave
+  constexpr int NL = 8;         // loads per lane
+  typedef HT vt __attribute__((ext_vector_type(V)));
+  __shared__ vt hs[GL];
+  // extra columns of workgroups when carrying the Gram step
+  if (job.R && blockIdx.x >= R) {
+    gram_run(job, (blockIdx.x - R) * gridDim.y + blockIdx.y);
+    return;
+  }
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / GL, sub = lane % GL;
+  const int64_t qw = ((int64_t)blockIdx.y * 4 + wave) * (OPL * NL);
+  const HT *Tr = T + (int64_t)r * Ia * Q;
+  vt x[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int64_t q = qw + u * OPL + grp;
+    x[u] = reinterpret_cast<const vt *>(Tr + Ia * (q < Q ? q : Q - 1))[sub];
+  }
+  HT *hsf = reinterpret_cast<HT *>(hs);
+  for (int64_t i = threadIdx.x; i < Ia; i += 256) hsf[i] = H[i * R + r];
+  __syncthreads();
+  const vt hv = hs[sub];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    HT acc = 0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc += x[u][e] * hv[e];
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const int64_t q = qw + u * OPL + grp;
+    if (sub == 0 && q < Q) {
+      if (leaf) out[q * R + r] = acc;
+      else out[(int64_t)r * Q + q] = acc;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // multi-TTV, strided reduction keeping the first mode:
 //   part[z][i][r] = sum_{q in split z} T[r][i + Ia q] K(q, r),
@@ -1565,7 +1617,8 @@ __global__ __launch_bounds__(1024) void k_loss(int N, int R, int64_t In, const H
 // ---------------------------------------------------------------------------
 template <typename HT>
 __global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
-                                              const HT *__restrict__ M, const HT *__restrict__ H,
+                                              const HT *__restrict__ M, int msplit,
+                                              int64_t mstride, const HT *__restrict__ H,
                                               const double *__restrict__ G,
                                               const double *__restrict__ Sg, HT *__restrict__ grad) {
   // S in LDS for R <= 64, else read from the global Hadamard product Sg
@@ -1584,9 +1637,11 @@ __global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
   if (e >= I * R) return;
   const int64_t i = e / R;
   const int r = (int)(e % R);
+  // the split partials of M in split order (one load each, issued together)
+  const HT m = ordered_split_sum_wide(M + e, msplit, mstride);
   double s = 0.0;
   for (int c = 0; c < R; ++c) s += (double)H[i * R + c] * (lds ? sS[c * R + r] : Sg[c * R + r]);
-  grad[e] = (HT)(s - (double)M[e]);
+  grad[e] = (HT)(s - (double)m);
 }
 
 // ---------------------------------------------------------------------------
@@ -1597,14 +1652,14 @@ __global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
 // final Rayleigh quotient.  One wave per mode (modes n, n + 8, ... for wave
 // n of eight): lane i < R keeps row i of S^(n) = prod_{k != n} G^(k) in
 // registers (the Grams' rows read mode by mode, all loads of a mode in
-// flight together).  The iterate v and w = S v go through the wave's LDS
-// rows; every lane forms the norm of w and the Rayleigh quotient itself from
-// them (the same sums in j order, so every lane holds the same value).
+// flight together).  w = S v is one product per lane (j in order); for
+// R <= 32 every lane then takes all of w through v_readlane and forms the
+// norm and the next v itself (the same values in every lane), for R > 32 v
+// goes through the wave's LDS row and the norm is a wave reduction.
 template <int RB>
 __global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, int N, int R,
                                                  int iters, double *__restrict__ eta) {
   __shared__ double vs[8][RB];
-  __shared__ double ws[8][RB];
   __shared__ double lm[8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool own = lane < R;
@@ -1617,44 +1672,65 @@ __global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, i
     for (int k = 0; k < N; ++k) {
       if (k == n) continue;
       const double *gr = G + (int64_t)k * R * R + (int64_t)i * R;
-      double g[RB];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) g[j] = j < R ? gr[j] : 1.0;
-#pragma unroll
-      for (int j = 0; j < RB; ++j) srow[j] *= g[j];
+      for (int j = 0; j < RB; ++j)
+        if (j < R) srow[j] *= gr[j];
     }
-    auto matvec = [&]() {
-      double w = 0.0;
+    double rq;
+    if constexpr (RB <= 32) {
+      double v[RB];
 #pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < R) w += srow[j] * vs[wave][j];
-      return own ? w : 0.0;
-    };
-    auto dot = [&](const double *x, const double *y) {
-      double d = 0.0;
+      for (int j = 0; j < RB; ++j) v[j] = j < R ? 1.0 / sqrt((double)R) : 0.0;
+      auto matvec = [&]() {
+        double w = 0.0;
 #pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < R) d += x[j] * y[j];
-      return d;
-    };
-    if (lane < RB) vs[wave][lane] = own ? 1.0 / sqrt((double)R) : 0.0;
-    wave_sync_lds();
-    for (int t = 0; t < iters; ++t) {
+        for (int j = 0; j < RB; ++j)
+          if (j < R) w += srow[j] * v[j];
+        return own ? w : 0.0;
+      };
+      for (int t = 0; t < iters; ++t) {
+        const double w = matvec();
+        double nrm2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+          if (j < R) {
+            const double wj = bcast(w, j);
+            nrm2 += wj * wj;
+          }
+        const double nrm = sqrt(nrm2);
+        if (!(nrm > 0.0)) break;
+        const double inv = 1.0 / nrm;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) v[j] = j < R ? bcast(w, j) * inv : 0.0;
+      }
       const double w = matvec();
-      if (lane < RB) ws[wave][lane] = w;
+      rq = 0.0;
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < R) rq += v[j] * bcast(w, j);
+    } else {
+      if (lane < RB) vs[wave][lane] = own ? 1.0 / sqrt((double)R) : 0.0;
       wave_sync_lds();
-      const double nrm = sqrt(dot(ws[wave], ws[wave]));
-      if (!(nrm > 0.0)) break;
-      if (own) vs[wave][lane] = w / nrm;
+      auto matvec = [&]() {
+        double w = 0.0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+          if (j < R) w += srow[j] * vs[wave][j];
+        return own ? w : 0.0;
+      };
+      for (int t = 0; t < iters; ++t) {
+        const double w = matvec();
+        const double nrm = sqrt(wave_sum(w * w));
+        if (!(nrm > 0.0)) break;
+        wave_sync_lds();
+        if (own) vs[wave][lane] = w / nrm;
+        wave_sync_lds();
+      }
+      const double w = matvec();
+      rq = wave_sum(own ? vs[wave][lane] * w : 0.0);
       wave_sync_lds();
     }
-    const double w = matvec();
-    wave_sync_lds();
-    if (lane < RB) ws[wave][lane] = w;
-    wave_sync_lds();
-    const double rq = dot(vs[wave], ws[wave]);
     if (rq > lmax) lmax = rq;
-    wave_sync_lds();
   }
   if (lane == 0) lm[wave] = lmax;
   __syncthreads();
@@ -1699,6 +1775,28 @@ hipError_t launch_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int
   const int V = hdt == NNCP_F64 ? 2 : 4;
   GramJob job = carry ? *carry : GramJob{};
   if (carry) carry->R = 0;
+  const int64_t gl = Ia / V;
+  if (Ia % V == 0 && gl < 64 && (gl & (gl - 1)) == 0) {
+    const unsigned gy = (unsigned)((Q + 4 * (64 / gl) * 8 - 1) / (4 * (64 / gl) * 8));
+    dim3 grid((unsigned)R + (gram_blocks(job) + gy - 1) / gy, gy), block(256);
+#define NNCP_CONTIG_PACK(HTV, GLV)                                                            \
+  hipLaunchKernelGGL((k_mttv_contig_pack<HTV, GLV>), grid, block, 0, st, (const HTV *)T, Ia, Q, \
+                     R, (const HTV *)H, (HTV *)out, leaf, job)
+#define NNCP_CONTIG_PACK_GL(HTV)       \
+  switch (gl) {                        \
+    case 1: NNCP_CONTIG_PACK(HTV, 1); break;   \
+    case 2: NNCP_CONTIG_PACK(HTV, 2); break;   \
+    case 4: NNCP_CONTIG_PACK(HTV, 4); break;   \
+    case 8: NNCP_CONTIG_PACK(HTV, 8); break;   \
+    case 16: NNCP_CONTIG_PACK(HTV, 16); break; \
+    default: NNCP_CONTIG_PACK(HTV, 32); break; \
+  }
+    if (hdt == NNCP_F64) { NNCP_CONTIG_PACK_GL(double) }
+    else { NNCP_CONTIG_PACK_GL(float) }
+#undef NNCP_CONTIG_PACK_GL
+#undef NNCP_CONTIG_PACK
+    return hipGetLastError();
+  }
   if (Ia % V == 0 && Ia <= 8 * 64 * V) {
     const int CPL = Ia <= 64 * V ? 1 : Ia <= 128 * V ? 2 : Ia <= 256 * V ? 4 : 8;
     const int QB = 8 / CPL;
@@ -2191,16 +2289,17 @@ hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const v
   return hipGetLastError();
 }
 
-hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M, const void *H,
-                       const double *G, const double *S, void *grad, hipStream_t st) {
+hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M, int msplit,
+                       int64_t mstride, const void *H, const double *G, const double *S,
+                       void *grad, hipStream_t st) {
   const int64_t n = I * R;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   if (R > 64 && !S) return hipErrorInvalidValue;
   if (hdt == NNCP_F64)
-    hipLaunchKernelGGL(k_grad<double>, grid, block, 0, st, I, R, N, mode, (const double *)M,
+    hipLaunchKernelGGL(k_grad<double>, grid, block, 0, st, I, R, N, mode, (const double *)M, msplit, mstride,
                        (const double *)H, G, S, (double *)grad);
   else
-    hipLaunchKernelGGL(k_grad<float>, grid, block, 0, st, I, R, N, mode, (const float *)M,
+    hipLaunchKernelGGL(k_grad<float>, grid, block, 0, st, I, R, N, mode, (const float *)M, msplit, mstride,
                        (const float *)H, G, S, (float *)grad);
   return hipGetLastError();
 }
