@@ -343,10 +343,12 @@ def summarize_counters(fetch_csv, write_csv, cmd_fetch, cmd_write, prefix="",
     import statistics
     fe = _read_counter_csv(fetch_csv, "FETCH_SIZE")
     wr = _read_counter_csv(write_csv, "WRITE_SIZE")
+    # the probe is the first copy of exactly COPY_PROBE_BYTES (it runs before
+    # anything else; the 256^4 workload is generated in copies of that size)
     probe = [d for d, (n, v) in wr.items() if "copyBuffer" in n and abs(v * 1024 - COPY_PROBE_BYTES) < 1]
-    if len(probe) != 1:
-        raise SystemExit(f"copy probe dispatch not found uniquely: {probe}")
-    d0 = probe[0]
+    if not probe:
+        raise SystemExit("copy probe dispatch not found")
+    d0 = min(probe)
     f_read = COPY_PROBE_BYTES / (fe[d0][1] * 1024)
     f_write = COPY_PROBE_BYTES / (wr[d0][1] * 1024)
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
