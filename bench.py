@@ -456,7 +456,7 @@ def main():
         if len(sys.argv) > 3 and sys.argv[3] == "anchor":
             summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
                             f"{pa} -- python3 bench.py --anchor-only", "kernels_256x4_hals.txt",
-                            ANCHOR + " (5 graph-replayed and 5 event-timed sweeps)")
+                            ANCHOR + " (10 graph-replayed and 10 event-timed sweeps)")
             return
         summarize_trace(sys.argv[2], "rocprofv3 --kernel-trace --stats --output-format csv "
                         f"{pa} -- python3 bench.py --steps 10 --warmup 2 --reps 5 "
@@ -717,7 +717,7 @@ def llc_cold_gemms(nn, torch, ctx, dims, R, reps=5):
     return out
 
 
-def dram_anchor(nn, torch, gen, dev, nsweeps=5):
+def dram_anchor(nn, torch, gen, dev, nsweeps=10):
     """The 256^4 BF16 R = 64 HALS workload (8 GiB, far beyond the last-level
     cache): sweeps/s by graph replay, and the partial MTTKRPs' event-timed
     rates (algorithmic bytes: the tensor once plus the output temporary)."""
