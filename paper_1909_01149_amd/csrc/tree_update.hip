@@ -1435,6 +1435,9 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
   // in a dead column (as lambda_r = 0 would make it), else the row as stored
   const double lam = a.fold_lambda ? a.lambda[c] : (a.dead[c] != 0.0 ? 0.0 : 1.0);
   const int ns = a.msplit;
+  // beta and gamma feed only the relative error (asked for after the last
+  // mode of a sweep)
+  const bool want = a.relerr_out != nullptr || a.scal != nullptr;
   for (int64_t blk = blockIdx.x; blk * 4 < a.I; blk += gridDim.x) {
     const int64_t i = blk * 4 + wave;
     const bool live = i < a.I;
@@ -1478,16 +1481,18 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
     if (ok) H[i * R + c] = hst;
     const double hs = ok ? (double)hst : 0.0;
     if (lane < RB) rows[wave][lane] = hs;
-    // (hs S)(c), j in order
-    double gs = 0.0;
+    if (want) {
+      // (hs S)(c), j in order
+      double gs = 0.0;
 #pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (j < R) gs += bcast(hs, j) * sc[j];
-    const double beta = wave_sum(ok ? m * h : 0.0);
-    const double gam = wave_sum(ok ? hs * gs : 0.0);
-    if (lane == 0) {
-      bred[wave][0] = beta;
-      bred[wave][1] = gam;
+      for (int j = 0; j < RB; ++j)
+        if (j < R) gs += bcast(hs, j) * sc[j];
+      const double beta = wave_sum(ok ? m * h : 0.0);
+      const double gam = wave_sum(ok ? hs * gs : 0.0);
+      if (lane == 0) {
+        bred[wave][0] = beta;
+        bred[wave][1] = gam;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -1497,7 +1502,7 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
       const double bv = rows[lr][16 * ty[q] + lc];
       gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, gacc[q], 0, 0, 0);
     }
-    if (threadIdx.x == 0) {
+    if (want && threadIdx.x == 0) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         bsum += bred[w][0];
@@ -1515,7 +1520,7 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) gp[(lr + 4 * v) * 16 + lc] = gacc[q][v];
   }
-  if (threadIdx.x == 0) {
+  if (want && threadIdx.x == 0) {
     a.part[blockIdx.x] = bsum;
     a.part[gridDim.x + blockIdx.x] = gsum;
   }
