@@ -58,7 +58,11 @@ struct Layout {
   // byte offsets into the workspace
   size_t off_G, off_Gt, off_S, off_scal, off_ones, off_hhat, off_upart, off_gpart,
       off_red, off_M, off_A, off_B, off_R, off_kfR, off_part, off_kf, off_ks, off_pgdH, off_pgdG, off_outer, off_admmU,
-      off_admmMc, off_admmP, off_admmNorm, off_admmStatus, total;
+      off_admmMc, off_admmP, off_admmNorm, off_admmStatus, off_gradpart, total;
+  // the gradient's strided multi-TTV partials, one region per mode (element
+  // offsets into the region at off_gradpart and their sizes; 0 for a mode
+  // whose M is not formed by a strided multi-TTV)
+  int64_t gradpart_off[NNCP_MAX_MODES], gradpart_elems[NNCP_MAX_MODES];
 };
 
 nncp_options default_options() {
@@ -315,6 +319,20 @@ int make_layout(Layout &L, int N, const int64_t *dims, int R, int xdt, int hdt,
   L.off_admmP = take(admm ? sizeof(double) * (R * R + 2) : 0);
   L.off_admmNorm = take(admm ? sizeof(double) * kAdmmMaxit * ((L.maxI + 3) / 4) * 4 : 0);
   L.off_admmStatus = take(admm ? sizeof(int) * kAdmmMaxit : 0);
+  {
+    int64_t t = 0;
+    for (int n = 0; n < NNCP_MAX_MODES; ++n) L.gradpart_off[n] = L.gradpart_elems[n] = 0;
+    if (R <= 64)
+      for (int side = 0; side < 2; ++side) {
+        const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : N;
+        for (int a = lo; a < hi - 1; ++a) {
+          L.gradpart_off[a] = t;
+          L.gradpart_elems[a] = mttv_strided_part_elems(hdt, L.dims[a], L.dims + a + 1, hi - a - 1, R);
+          t += L.gradpart_elems[a];
+        }
+      }
+    L.off_gradpart = take(hs * t);
+  }
   L.total = o;
   return NNCP_OK;
 }
@@ -356,7 +374,11 @@ struct nncp_ctx {
   double *admmU, *admmMc, *admmP, *admmNorm;
   int *admmStatus;
   double *outer;
-  void *M, *nodeA, *nodeB, *nodeR, *kfR, *part, *kf, *ks;
+  void *M, *nodeA, *nodeB, *nodeR, *kfR, *part, *kf, *ks, *gradpart;
+  // when set, the strided multi-TTV writes its split partials here (with
+  // room for part_override_elems) instead of into part
+  void *part_override = nullptr;
+  int64_t part_override_elems = 0;
   void *pgdH[NNCP_MAX_MODES], *pgdG[NNCP_MAX_MODES];
   // set while nncp_grad walks the right subtree from the fused pass: the
   // right root node lives in nodeR
@@ -565,10 +587,12 @@ int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_ro
     const void *Hq[NNCP_MAX_MODES];
     for (int k = n + 1; k < hi; ++k) Hq[k - n - 1] = F.H[k];
     int ns = 1;
+    void *part = c->part_override ? c->part_override : c->part;
+    const int64_t cap = c->part_override ? c->part_override_elems : L.part_elems;
     TIMED(3, launch_mttv_strided(L.hdt, node_buf(c, side, n), L.dims[n], L.dims + n + 1,
-                                 hi - n - 1, Hq, R, defer ? nullptr : Mout, c->part,
-                                 L.part_elems, c->st, &ns, &c->pending));
-    if (defer) *defer = MRef{c->part, ns, L.dims[n] * R};
+                                 hi - n - 1, Hq, R, defer ? nullptr : Mout, part, cap, c->st, &ns,
+                                 &c->pending));
+    if (defer) *defer = MRef{part, ns, L.dims[n] * R};
   }
   return NNCP_OK;
 }
@@ -771,6 +795,7 @@ int nncp_init(nncp_ctx **out, int N, const int64_t *dims, int R, int x_dtype, co
   c->part = c->ws + L.off_part;
   c->kf = c->ws + L.off_kf;
   c->ks = c->ws + L.off_ks;
+  c->gradpart = c->ws + L.off_gradpart;
   {
     const size_t hs = xsize(h_dtype);
     size_t oh = L.off_pgdH, og = L.off_pgdG;
@@ -1269,6 +1294,50 @@ static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const
   if (dual) {
     int rc = dual_roots(c, F);
     if (rc) return rc;
+  }
+  if (grads && L.R <= 64) {
+    // every M^(n) kept until one launch forms all the gradients and the
+    // loss: M^(n) for n < N-1 in its gradient buffer (or, when a strided
+    // multi-TTV forms it, its split partials in the mode's own region),
+    // M^(N-1) in c->M (or nodeR) for the loss
+    GradAllArgs ga{};
+    for (int n = 0; n < L.N; ++n) {
+      const bool lastm = n == L.N - 1;
+      MRef mr{lastm ? c->M : grads[n], 1, 0};
+      void *Mout = lastm ? c->M : grads[n];
+      int rc = NNCP_OK;
+      c->part_override = L.gradpart_elems[n] ? (char *)c->gradpart + xsize(L.hdt) * L.gradpart_off[n]
+                                             : nullptr;
+      c->part_override_elems = L.gradpart_elems[n];
+      if (dual && n == L.S && L.N - L.S == 1) {
+        mr = MRef{c->nodeR, 1, 0};  // M^(N-1), added from the fused pass's partials
+      } else if (dual) {
+        c->right_root_in_R = true;
+        rc = mttkrp_tree(c, F, n, Mout, false, lastm ? nullptr : &mr, true);
+        c->right_root_in_R = false;
+      } else {
+        rc = mttkrp_tree(c, F, n, Mout, false, lastm ? nullptr : &mr);
+      }
+      c->part_override = nullptr;
+      c->part_override_elems = 0;
+      if (rc) return rc;
+      ga.M[n] = mr.p;
+      ga.msplit[n] = mr.msplit;
+      ga.mstride[n] = mr.mstride;
+      ga.H[n] = F.H[n];
+      ga.grad[n] = grads[n];
+      ga.I[n] = L.dims[n];
+    }
+    ga.N = L.N;
+    ga.R = L.R;
+    ga.G = G;
+    ga.ones = c->ones;
+    ga.alpha = c->scal + 8;
+    ga.loss = loss;
+    ga.scal = c->scal + 4;
+    HIPCHK(flush_gram(c));
+    HIPCHK(launch_grad_all(L.hdt, ga, c->st));
+    return NNCP_OK;
   }
   void *Mn = c->M;
   for (int n = 0; n < L.N; ++n) {

@@ -417,18 +417,17 @@ __device__ inline void gram_part(const GramJob &j, int p) {
   const int u = 32 * p + e32;
   const int uc = u < slice ? u : slice - 1;
   const int nw = j.nw;
-  double acc = 0.0;
-  for (int w0 = grp; w0 < nw; w0 += 32) {
-    double v[4];
+  // every slice of this thread in flight at once (nw <= kGramSlices)
+  double v[kGramSlices / 8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int w = w0 + 8 * k;
-      v[k] = j.gpart[(int64_t)(w < nw ? w : nw - 1) * slice + uc];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (w0 + 8 * k < nw) acc += v[k];
+  for (int k = 0; k < kGramSlices / 8; ++k) {
+    const int w = grp + 8 * k;
+    v[k] = w < nw ? j.gpart[(int64_t)w * slice + uc] : 0.0;
   }
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < kGramSlices / 8; ++k)
+    if (grp + 8 * k < nw) acc += v[k];
   red[grp][e32] = acc;
   __syncthreads();
   if (tid < 32 && u < slice) {
@@ -556,6 +555,28 @@ hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const v
 hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M, int msplit,
                        int64_t mstride, const void *H, const double *G, const double *S,
                        void *grad, hipStream_t st);
+
+// Every mode's gradient grad[n] = H^(n) S^(n) - M^(n) (lambda = 1, R <= 64)
+// and the loss from M^(N-1), in one launch.  M[n] holds msplit[n] partial
+// copies mstride[n] apart (1: M itself) and may be grad[n] itself; M[N-1]
+// must be M itself and not a gradient buffer.  wg0 is filled in by the
+// launcher.
+struct GradAllArgs {
+  const void *M[NNCP_MAX_MODES];
+  int64_t mstride[NNCP_MAX_MODES];
+  const void *H[NNCP_MAX_MODES];
+  void *grad[NNCP_MAX_MODES];
+  int64_t I[NNCP_MAX_MODES];
+  int msplit[NNCP_MAX_MODES];
+  int wg0[NNCP_MAX_MODES + 1];
+  int N, R;
+  const double *G;
+  const double *ones;   // R ones (lambda = 1)
+  const double *alpha;
+  double *loss;         // may be NULL
+  double *scal;         // may be NULL: [0]=beta [1]=gamma [2]=raw relerr^2
+};
+hipError_t launch_grad_all(int hdt, GradAllArgs a, hipStream_t st);
 
 // eta0 = 1 / max_n lmax(S^(n)) by power iteration; writes eta[0] (R <= 64)
 hipError_t launch_pgd_eta(const double *G, int N, int R, int iters, double *eta, hipStream_t st);

@@ -1584,20 +1584,22 @@ __global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_run(j, bl
 // ---------------------------------------------------------------------------
 // loss of [[lambda; H]] given M^(N-1) at the current factors
 // ---------------------------------------------------------------------------
-template <typename HT>
-__global__ __launch_bounds__(1024) void k_loss(int N, int R, int64_t In, const HT *__restrict__ M,
-                                               const HT *__restrict__ H,
-                                               const double *__restrict__ lambda,
-                                               const double *__restrict__ G,
-                                               const double *__restrict__ alpha, double *loss,
-                                               double *relerr, double *scal) {
-  __shared__ double wred[16][2];
+// one workgroup of NT threads: beta = <M, H diag(lambda)>, gamma =
+// lambda^T (prod_k G^(k)) lambda, the loss 0.5 (alpha - 2 beta + gamma)
+template <typename HT, int NT>
+__device__ __forceinline__ void loss_block(int N, int R, int64_t In, const HT *__restrict__ M,
+                                           const HT *__restrict__ H,
+                                           const double *__restrict__ lambda,
+                                           const double *__restrict__ G,
+                                           const double *__restrict__ alpha, double *loss,
+                                           double *relerr, double *scal,
+                                           double (*wred)[2] /* LDS, NT / 64 rows */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double beta = 0.0;
-  for (int64_t e = threadIdx.x; e < In * R; e += 1024)
+  for (int64_t e = threadIdx.x; e < In * R; e += NT)
     beta += (double)M[e] * (double)H[e] * lambda[e % R];
   double gamma = 0.0;
-  for (int e = threadIdx.x; e < R * R; e += 1024) {
+  for (int e = threadIdx.x; e < R * R; e += NT) {
     double s = 1.0;
     for (int k = 0; k < N; ++k) s *= G[(int64_t)k * R * R + e];
     gamma += lambda[e / R] * s * lambda[e % R];
@@ -1608,7 +1610,7 @@ __global__ __launch_bounds__(1024) void k_loss(int N, int R, int64_t In, const H
   __syncthreads();
   if (threadIdx.x == 0) {
     double b = 0.0, g = 0.0;
-    for (int w = 0; w < 16; ++w) { b += wred[w][0]; g += wred[w][1]; }
+    for (int w = 0; w < NT / 64; ++w) { b += wred[w][0]; g += wred[w][1]; }
     const double al = alpha[0];
     const double r2 = al - 2.0 * b + g;
     if (loss) loss[0] = 0.5 * r2;
@@ -1617,17 +1619,28 @@ __global__ __launch_bounds__(1024) void k_loss(int N, int R, int64_t In, const H
   }
 }
 
+template <typename HT>
+__global__ __launch_bounds__(1024) void k_loss(int N, int R, int64_t In, const HT *__restrict__ M,
+                                               const HT *__restrict__ H,
+                                               const double *__restrict__ lambda,
+                                               const double *__restrict__ G,
+                                               const double *__restrict__ alpha, double *loss,
+                                               double *relerr, double *scal) {
+  __shared__ double wred[16][2];
+  loss_block<HT, 1024>(N, R, In, M, H, lambda, G, alpha, loss, relerr, scal, wred);
+}
+
 // ---------------------------------------------------------------------------
 // gradient of 0.5 ||X - [[H]]||^2 for one mode: grad = H S - M
 // ---------------------------------------------------------------------------
+// grad = H S - M for the entries of workgroup `blk` of one mode
 template <typename HT>
-__global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
-                                              const HT *__restrict__ M, int msplit,
-                                              int64_t mstride, const HT *__restrict__ H,
-                                              const double *__restrict__ G,
-                                              const double *__restrict__ Sg, HT *__restrict__ grad) {
+__device__ __forceinline__ void grad_block(int64_t blk, int64_t I, int R, int N, int mode,
+                                           const HT *__restrict__ M, int msplit, int64_t mstride,
+                                           const HT *__restrict__ H, const double *__restrict__ G,
+                                           const double *__restrict__ Sg, HT *__restrict__ grad,
+                                           double *sS /* LDS, 64 x 64 */) {
   // S in LDS for R <= 64, else read from the global Hadamard product Sg
-  __shared__ double sS[64 * 64];
   const bool lds = R <= 64;
   if (lds) {
     for (int e = threadIdx.x; e < R * R; e += 256) {
@@ -1638,7 +1651,7 @@ __global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
     }
   }
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = blk * 256 + threadIdx.x;
   if (e >= I * R) return;
   const int64_t i = e / R;
   const int r = (int)(e % R);
@@ -1647,6 +1660,37 @@ __global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
   double s = 0.0;
   for (int c = 0; c < R; ++c) s += (double)H[i * R + c] * (lds ? sS[c * R + r] : Sg[c * R + r]);
   grad[e] = (HT)(s - (double)m);
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_grad(int64_t I, int R, int N, int mode,
+                                              const HT *__restrict__ M, int msplit,
+                                              int64_t mstride, const HT *__restrict__ H,
+                                              const double *__restrict__ G,
+                                              const double *__restrict__ Sg, HT *__restrict__ grad) {
+  __shared__ double sS[64 * 64];
+  grad_block<HT>(blockIdx.x, I, R, N, mode, M, msplit, mstride, H, G, Sg, grad, sS);
+}
+
+// Every mode's gradient in one launch (R <= 64): workgroups wg0[n] ..
+// wg0[n + 1] - 1 take mode n (M^(n) as a.M[n], msplit partial copies; a
+// mode's M may be its gradient buffer itself: each entry is read before the
+// same thread overwrites it), and workgroup wg0[N] the loss from M^(N-1)
+// (which must not be a gradient buffer).
+template <typename HT>
+__global__ __launch_bounds__(256) void k_grad_all(GradAllArgs a) {
+  __shared__ double sS[64 * 64];
+  const int b = blockIdx.x;
+  if (b == a.wg0[a.N]) {
+    const int n = a.N - 1;
+    loss_block<HT, 256>(a.N, a.R, a.I[n], (const HT *)a.M[n], (const HT *)a.H[n], a.ones, a.G,
+                        a.alpha, a.loss, nullptr, a.scal, reinterpret_cast<double (*)[2]>(sS));
+    return;
+  }
+  int n = 0;
+  while (n + 1 < a.N && b >= a.wg0[n + 1]) ++n;
+  grad_block<HT>(b - a.wg0[n], a.I[n], a.R, a.N, n, (const HT *)a.M[n], a.msplit[n],
+                 a.mstride[n], (const HT *)a.H[n], a.G, nullptr, (HT *)a.grad[n], sS);
 }
 
 // ---------------------------------------------------------------------------
@@ -2291,6 +2335,16 @@ hipError_t launch_loss(int hdt, int N, int R, int64_t In, const void *M, const v
   else
     hipLaunchKernelGGL(k_loss<float>, dim3(1), dim3(1024), 0, st, N, R, In, (const float *)M,
                        (const float *)H, lambda, G, alpha, loss, relerr, scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_all(int hdt, GradAllArgs a, hipStream_t st) {
+  if (a.R > 64 || a.N < 2 || a.N > NNCP_MAX_MODES) return hipErrorInvalidValue;
+  a.wg0[0] = 0;
+  for (int n = 0; n < a.N; ++n) a.wg0[n + 1] = a.wg0[n] + (int)((a.I[n] * a.R + 255) / 256);
+  dim3 grid((unsigned)a.wg0[a.N] + 1), block(256);
+  if (hdt == NNCP_F64) hipLaunchKernelGGL(k_grad_all<double>, grid, block, 0, st, a);
+  else hipLaunchKernelGGL(k_grad_all<float>, grid, block, 0, st, a);
   return hipGetLastError();
 }
 
