@@ -511,6 +511,8 @@ __device__ inline void gram_run(const GramJob &j, int p) {
 // rows go straight into H unnormalised, in one kernel that also leaves the
 // Gram slices and the <M, Hhat> partials for the Gram step.
 hipError_t launch_update(int hdt, const UpdateArgs &a, hipStream_t st, GramJob *job);
+// waves (rows per pass) of a workgroup of the deferred row kernel
+constexpr int kDeferWaves = 4;
 // workgroups of the deferred row kernel (at most kGramSlices)
 int defer_workgroups(int64_t I);
 // End of the sweep's deferred path: s_k(r) = sqrt(G^(k)(r, r)) for every

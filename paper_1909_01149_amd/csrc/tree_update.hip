@@ -1397,31 +1397,32 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
 // once at the end of the call (k_norm_scales, k_apply_scales): the iterates
 // are those of the normalised iteration up to rounding.  The kernel writes
 // the rows straight into H; there is no separate normalisation launch.
-// 4 rows per pass (256 threads, one row per wave, lane c owns column c and
+// kDeferWaves rows per pass (one row per wave, lane c owns column c and
 // keeps column c of S in registers), row blocks gridDim.x apart.  The stored
 // (rounded) rows also feed the workgroup's slice of the Gram of the new
-// factor (upper 16 x 16 tiles on FP64 MFMA, the pass's four rows one step;
-// wave w owns tiles w, w + 4, w + 8) and its shares of beta = <M, Hhat> and
+// factor (upper 16 x 16 tiles on FP64 MFMA, four rows a step; wave w owns
+// tiles w, w + kDeferWaves) and its shares of beta = <M, Hhat> and
 // of gamma = sum_i hs_i S hs_i^T (hs the stored row), which the relative
 // error identity needs with lambda = 1; both added in row-block and wave
 // order.  The arithmetic of a row is that of k_update_rows_small.
 template <typename HT, int RB>
-__global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
-  __shared__ double rows[4][RB];
-  __shared__ double bred[4][2];
+__global__ __launch_bounds__(64 * kDeferWaves) void k_update_rows_defer(UpdateArgs a) {
+  constexpr int WV = kDeferWaves, TQ = (10 + WV - 1) / WV;  // at most 10 upper tiles
+  __shared__ double rows[WV][RB];
+  __shared__ double bred[WV][2];
   const int R = a.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int T = (R + 15) / 16, ntile = T * (T + 1) / 2;
-  int tx[3], ty[3];
+  int tx[TQ], ty[TQ];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < TQ; ++q) {
     tx[q] = ty[q] = -1;
-    if (wave + 4 * q < ntile) tile_pair(wave + 4 * q, T, tx[q], ty[q]);
+    if (wave + WV * q < ntile) tile_pair(wave + WV * q, T, tx[q], ty[q]);
   }
   const int lr = lane >> 4, lc = lane & 15;
-  f64x4 gacc[3];
+  f64x4 gacc[TQ];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) gacc[q][0] = gacc[q][1] = gacc[q][2] = gacc[q][3] = 0.0;
+  for (int q = 0; q < TQ; ++q) gacc[q][0] = gacc[q][1] = gacc[q][2] = gacc[q][3] = 0.0;
   double bsum = 0.0, gsum = 0.0;
   const HT *M = (const HT *)a.M;
   HT *H = (HT *)a.H;
@@ -1438,8 +1439,8 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
   // beta and gamma feed only the relative error (asked for after the last
   // mode of a sweep)
   const bool want = a.relerr_out != nullptr || a.scal != nullptr;
-  for (int64_t blk = blockIdx.x; blk * 4 < a.I; blk += gridDim.x) {
-    const int64_t i = blk * 4 + wave;
+  for (int64_t blk = blockIdx.x; blk * WV < a.I; blk += gridDim.x) {
+    const int64_t i = blk * WV + wave;
     const bool live = i < a.I;
     const int64_t ir = live ? i : a.I - 1;
     const HT *mp = M + ir * R + c;
@@ -1495,16 +1496,20 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
       }
     }
     __syncthreads();
+    // the pass's rows four at a time (the K of one 16x16x4 step)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < TQ; ++q) {
       if (tx[q] < 0) continue;
-      const double av = rows[lr][16 * tx[q] + lc];
-      const double bv = rows[lr][16 * ty[q] + lc];
-      gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, gacc[q], 0, 0, 0);
+#pragma unroll
+      for (int k0 = 0; k0 < WV; k0 += 4) {
+        const double av = rows[k0 + lr][16 * tx[q] + lc];
+        const double bv = rows[k0 + lr][16 * ty[q] + lc];
+        gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, gacc[q], 0, 0, 0);
+      }
     }
     if (want && threadIdx.x == 0) {
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
+      for (int w = 0; w < WV; ++w) {
         bsum += bred[w][0];
         gsum += bred[w][1];
       }
@@ -1514,9 +1519,9 @@ __global__ __launch_bounds__(256) void k_update_rows_defer(UpdateArgs a) {
   // this workgroup's slice: entry (lr + 4 v, lc) of tile t, as the finish
   // kernel writes its slices
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < TQ; ++q) {
     if (tx[q] < 0) continue;
-    double *gp = a.gpart + ((int64_t)blockIdx.x * ntile + wave + 4 * q) * 256;
+    double *gp = a.gpart + ((int64_t)blockIdx.x * ntile + wave + WV * q) * 256;
 #pragma unroll
     for (int v = 0; v < 4; ++v) gp[(lr + 4 * v) * 16 + lc] = gacc[q][v];
   }
@@ -1700,11 +1705,9 @@ __global__ __launch_bounds__(256) void k_grad_all(GradAllArgs a) {
 // lambda_max by `iters` power steps from the normalised all-ones vector and a
 // final Rayleigh quotient.  One wave per mode (modes n, n + 8, ... for wave
 // n of eight): lane i < R keeps row i of S^(n) = prod_{k != n} G^(k) in
-// registers (the Grams' rows read mode by mode, all loads of a mode in
-// flight together).  w = S v is one product per lane (j in order); for
-// R <= 32 every lane then takes all of w through v_readlane and forms the
-// norm and the next v itself (the same values in every lane), for R > 32 v
-// goes through the wave's LDS row and the norm is a wave reduction.
+// registers; the iterate goes through the wave's LDS row, read as a
+// broadcast by every lane, and the norm is a wave reduction.  w_i = sum_j
+// S(i, j) v_j is added in j order.
 template <int RB>
 __global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, int N, int R,
                                                  int iters, double *__restrict__ eta) {
@@ -1717,69 +1720,34 @@ __global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, i
   for (int n = wave; n < N; n += 8) {
     double srow[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) srow[j] = 1.0;
-    for (int k = 0; k < N; ++k) {
-      if (k == n) continue;
-      const double *gr = G + (int64_t)k * R * R + (int64_t)i * R;
+    for (int j = 0; j < RB; ++j) {
+      double p = 1.0;
+      if (own && j < R)
+        for (int k = 0; k < N; ++k)
+          if (k != n) p *= G[(int64_t)k * R * R + i * R + j];
+      srow[j] = (own && j < R) ? p : 0.0;
+    }
+    if (lane < RB) vs[wave][lane] = lane < R ? 1.0 / sqrt((double)R) : 0.0;
+    wave_sync_lds();
+    auto matvec = [&]() {
+      double w = 0.0;
 #pragma unroll
       for (int j = 0; j < RB; ++j)
-        if (j < R) srow[j] *= gr[j];
-    }
-    double rq;
-    if constexpr (RB <= 32) {
-      double v[RB];
-#pragma unroll
-      for (int j = 0; j < RB; ++j) v[j] = j < R ? 1.0 / sqrt((double)R) : 0.0;
-      auto matvec = [&]() {
-        double w = 0.0;
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-          if (j < R) w += srow[j] * v[j];
-        return own ? w : 0.0;
-      };
-      for (int t = 0; t < iters; ++t) {
-        const double w = matvec();
-        double nrm2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-          if (j < R) {
-            const double wj = bcast(w, j);
-            nrm2 += wj * wj;
-          }
-        const double nrm = sqrt(nrm2);
-        if (!(nrm > 0.0)) break;
-        const double inv = 1.0 / nrm;
-#pragma unroll
-        for (int j = 0; j < RB; ++j) v[j] = j < R ? bcast(w, j) * inv : 0.0;
-      }
+        if (j < R) w += srow[j] * vs[wave][j];
+      return w;
+    };
+    for (int t = 0; t < iters; ++t) {
       const double w = matvec();
-      rq = 0.0;
-#pragma unroll
-      for (int j = 0; j < RB; ++j)
-        if (j < R) rq += v[j] * bcast(w, j);
-    } else {
-      if (lane < RB) vs[wave][lane] = own ? 1.0 / sqrt((double)R) : 0.0;
+      const double nrm = sqrt(wave_sum(own ? w * w : 0.0));
+      if (!(nrm > 0.0)) break;
       wave_sync_lds();
-      auto matvec = [&]() {
-        double w = 0.0;
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-          if (j < R) w += srow[j] * vs[wave][j];
-        return own ? w : 0.0;
-      };
-      for (int t = 0; t < iters; ++t) {
-        const double w = matvec();
-        const double nrm = sqrt(wave_sum(w * w));
-        if (!(nrm > 0.0)) break;
-        wave_sync_lds();
-        if (own) vs[wave][lane] = w / nrm;
-        wave_sync_lds();
-      }
-      const double w = matvec();
-      rq = wave_sum(own ? vs[wave][lane] * w : 0.0);
+      if (own) vs[wave][lane] = w / nrm;
       wave_sync_lds();
     }
+    const double w = matvec();
+    const double rq = wave_sum(own ? vs[wave][lane] * w : 0.0);
     if (rq > lmax) lmax = rq;
+    wave_sync_lds();
   }
   if (lane == 0) lm[wave] = lmax;
   __syncthreads();
@@ -2006,7 +1974,7 @@ hipError_t launch_sumsq(int xdt, const void *X, int64_t n, double *part, double 
 }
 
 int defer_workgroups(int64_t I) {
-  const int64_t blocks = (I + 3) / 4;
+  const int64_t blocks = (I + kDeferWaves - 1) / kDeferWaves;
   return (int)(blocks < kGramSlices ? blocks : kGramSlices);
 }
 
@@ -2043,9 +2011,10 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     job->mode = a.mode;
     job->next_mode = a.next_mode;
     job->nw = nw;
-    if (a.R <= 16) hipLaunchKernelGGL((k_update_rows_defer<HT, 16>), dim3(nw), dim3(256), 0, st, a);
-    else if (a.R <= 32) hipLaunchKernelGGL((k_update_rows_defer<HT, 32>), dim3(nw), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_update_rows_defer<HT, 64>), dim3(nw), dim3(256), 0, st, a);
+    const dim3 blk(64 * kDeferWaves);
+    if (a.R <= 16) hipLaunchKernelGGL((k_update_rows_defer<HT, 16>), dim3(nw), blk, 0, st, a);
+    else if (a.R <= 32) hipLaunchKernelGGL((k_update_rows_defer<HT, 32>), dim3(nw), blk, 0, st, a);
+    else hipLaunchKernelGGL((k_update_rows_defer<HT, 64>), dim3(nw), blk, 0, st, a);
     return hipGetLastError();
   }
   if (a.R <= 64) {
