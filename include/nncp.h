@@ -332,8 +332,11 @@ int nncp_sweep_capture(nncp_ctx *ctx, int algo, int nsweeps, double *relerr_hist
  * options.fused_grad is set and the fused path applies (BF16 tensor,
  * R <= 32, at least two modes left of the root split, its buffers within the
  * LDS; see options.fused_grad for the grid size); otherwise one pass per root
- * (two passes).  nncp_uses_fused_grad tells which.
- *   grads  host array of N device pointers, each I_n x R h_dtype
+ * (two passes).  nncp_uses_fused_grad tells which.  For R <= 64 every
+ * M^(n) is kept (M^(n), n < N-1, in grads[n] itself) until one launch forms
+ * all gradients and the loss.
+ *   grads  host array of N device pointers, each I_n x R h_dtype; they must
+ *          not overlap each other, the factors or the workspace
  *   loss   1 FP64: L via the identity (may be NULL)
  */
 int nncp_grad(nncp_ctx *ctx, void *const *grads, double *loss);

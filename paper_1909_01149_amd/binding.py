@@ -493,6 +493,16 @@ class Context:
         if grads is None:
             grads = [torch.empty_like(f) for f in self.factors]
         grads = self._check_factors(grads, "gradient")
+        # the gradient buffers hold the MTTKRPs until the last launch: they
+        # must not share memory with each other, the factors or the workspace
+        spans = [(t.data_ptr(), t.data_ptr() + t.numel() * t.element_size(), name)
+                 for t, name in [(g, f"gradient {n}") for n, g in enumerate(grads)]
+                 + [(f, f"factor {n}") for n, f in enumerate(self.factors)]
+                 + [(self.workspace, "workspace")]]
+        spans.sort()
+        for (a0, a1, an), (b0, b1, bn) in zip(spans, spans[1:]):
+            if b0 < a1:
+                raise ValueError(f"{an} and {bn} overlap")
         if loss is None:
             loss = torch.empty(1, dtype=torch.float64, device=self.X.device)
         _need(loss, "loss", (1,), torch.float64, self.X.device)

@@ -112,3 +112,21 @@ def test_cploss_uses_fused_pass(nn):
     for h, ref in zip(Hs, go):
         assert relerr(h.grad.double().cpu().numpy(), ref) <= 1e-4
     ctx.close()
+
+
+def test_grad_rejects_overlapping_buffers(nn):
+    """The gradient buffers keep the MTTKRPs until the last launch, so a
+    gradient buffer that is a factor (or another gradient buffer) is refused
+    before anything runs."""
+    banner("grad buffer overlap")
+    dims, R = [16, 12, 20], 8
+    X64, H64 = gen.small_lowrank(dims, R, R, 3, noise=0.05)
+    X = torch.from_numpy(X64).float().cuda()
+    ctx = nn.Context(X, [torch.from_numpy(h).float().cuda() for h in H64])
+    g = [torch.empty_like(f) for f in ctx.factors]
+    with pytest.raises(ValueError, match="overlap"):
+        ctx.grad([ctx.factors[0]] + g[1:])
+    big = torch.empty(40, R, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError, match="overlap"):
+        ctx.grad([big[0:16], g[1], big[10:30]])
+    ctx.close()
