@@ -293,6 +293,7 @@ struct GramJob {
 // S_next(y, x), and no other thread touches either.  All loads of a round are
 // unconditional (clamped indices) so that they are in flight together; the
 // slices are added in slice order, eight at a time.
+template <int FE>
 __device__ inline void gram_finish(const GramJob &j) {
   __shared__ double gred[4];
   const int R = j.R, RR = R * R, T = (R + 15) >> 4, slice = (T * (T + 1) / 2) * 256;
@@ -310,8 +311,6 @@ __device__ inline void gram_finish(const GramJob &j) {
   const double alpha = j.alpha[0];
   double beta = j.beta[0];  // both always valid addresses
   double gsum = 0.0;
-  // FE entries per thread and round trip (one round up to R = 32)
-  constexpr int FE = 3;
   for (int u0 = tid; u0 < slice; u0 += 256 * FE) {
     double sv[FE], la[FE], lb[FE], pn[FE], sum[FE];
     int xs[FE], ys[FE];
@@ -417,17 +416,20 @@ __device__ inline void gram_part(const GramJob &j, int p) {
   const int u = 32 * p + e32;
   const int uc = u < slice ? u : slice - 1;
   const int nw = j.nw;
-  // every slice of this thread in flight at once (nw <= kGramSlices)
-  double v[kGramSlices / 8];
-#pragma unroll
-  for (int k = 0; k < kGramSlices / 8; ++k) {
-    const int w = grp + 8 * k;
-    v[k] = w < nw ? j.gpart[(int64_t)w * slice + uc] : 0.0;
-  }
+  // this thread's slices eight at a time (few registers: the step rides
+  // along with kernels whose own register use is small)
   double acc = 0.0;
+  for (int w0 = grp; w0 < nw; w0 += 64) {
+    double v[8];
 #pragma unroll
-  for (int k = 0; k < kGramSlices / 8; ++k)
-    if (grp + 8 * k < nw) acc += v[k];
+    for (int k = 0; k < 8; ++k) {
+      const int w = w0 + 8 * k;
+      v[k] = w < nw ? j.gpart[(int64_t)w * slice + uc] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (w0 + 8 * k < nw) acc += v[k];
+  }
   red[grp][e32] = acc;
   __syncthreads();
   if (tid < 32 && u < slice) {
@@ -496,12 +498,15 @@ __device__ inline void gram_part(const GramJob &j, int p) {
 __host__ __device__ inline int gram_blocks(const GramJob &j) {
   return j.R == 0 ? 0 : (j.parts > 0 ? j.parts : 1);
 }
-// run block p of a Gram step (a carrier's extra workgroups, or its own kernel)
+// run block p of a Gram step: FE = 3 entries per thread and round for the
+// kernel of its own (one round up to R = 32), FE = 1 in a carrier, whose own
+// kernel's register budget (and so its occupancy) it would otherwise set
+template <int FE = 1>
 __device__ inline void gram_run(const GramJob &j, int p) {
   if (j.parts > 0) {
     if (p < j.parts) gram_part(j, p);
   } else if (p == 0) {
-    gram_finish(j);
+    gram_finish<FE>(j);
   }
 }
 

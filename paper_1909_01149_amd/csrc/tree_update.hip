@@ -1584,7 +1584,7 @@ __global__ __launch_bounds__(256) void k_apply_scales(ScaleArgs a, double *__res
 }
 
 // the Gram step as a kernel of its own (gram_blocks(j) workgroups)
-__global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_run(j, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_gram_finish(GramJob j) { gram_run<3>(j, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // loss of [[lambda; H]] given M^(N-1) at the current factors
