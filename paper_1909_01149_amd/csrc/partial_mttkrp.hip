@@ -841,6 +841,22 @@ __global__ __launch_bounds__(64 * left_waves(sizeof(XT), QV, NT, SLOW)) void k_g
 constexpr int kDualWaves = 8;
 constexpr int kDualWin = 128;
 
+// Piece (16 bytes) of slot row sl that holds fragment c = h NT + nt.  With
+// NT = 2 (four pieces a row) the pieces of any 16 consecutive lanes, and of
+// any aligned 8 of them, land in distinct 16-byte bank groups, both for the
+// writers (16 consecutive rows, one fragment) and for the readers (four
+// consecutive columns r times q & 3, see the reduction); NT = 1 rotates by
+// l / 16 only.
+template <int NT>
+__device__ __forceinline__ int dual_slot_piece(int sl, int c) {
+  if constexpr (NT == 2) {
+    const int f = 2 * (((sl >> 3) ^ (sl >> 1)) & 1) + ((sl >> 2) & 1);
+    return c ^ f ^ ((sl >> 4) & 3);
+  } else {
+    return c ^ ((sl >> 4) & (2 * NT - 1));
+  }
+}
+
 struct DualArgs {
   int64_t m, k;
   int PfL;             // fast length of K_L (a multiple of 32), staged whole
@@ -954,13 +970,16 @@ __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
 #pragma unroll
     for (int u = 0; u < KL; ++u) dst[u] = xload<NTL, u32x4>(xp + (tt * KSTEP + u) * (int64_t)m);
   };
+  // step t + 2 is loaded into step t's registers as soon as step t has been
+  // copied to the LDS tile (halfway through step t), so about a step and a
+  // half of X is in flight per wave with two register buffers
   load_step(buf[0], 0);
+  load_step(buf[1], 1);
   int64_t wcur = -1;
   for (int64_t t0 = 0; t0 < steps; t0 += NB) {
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
       const int64_t t = t0 + jb;
-      load_step(buf[(jb + 1) % NB], t + 1);
       if (t >= steps) break;
       const u32x4 *rw = buf[jb];
       const int64_t j0 = t * KSTEP;
@@ -1003,6 +1022,7 @@ __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
         const int row = 8 * g + u;
         *reinterpret_cast<u32x4 *>(xt + row * 128 + ((rho ^ (row & 15)) * SVEC)) = rw[u];
       }
+      load_step(buf[jb], t + 2);
       wave_sync_lds();
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -1033,25 +1053,32 @@ __global__ __launch_bounds__(64 * kDualWaves) void k_gemm_dual_mfma(
       // ---- the waves' T_R results of this step, added in wave order.  Lane
       // l's fragment (h, nt) holds rows jj = 16 h + 4 (l / 16) + v (v < 4) of
       // the step at column r = 16 nt + l % 16; its 16-byte piece goes to
-      // chunk (h NT + nt) ^ (l / 16) of the lane's slot row, so that the
-      // readers below, which take the four rows of one column from the
-      // lanes l % 16 = r % 16, spread over the banks.
+      // piece dual_slot_piece(l, h NT + nt) of the lane's slot row.
       float *slot = str + ((int)(t & 1) * WV + wave) * SLOT;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const int ch = (h * NT + nt) ^ (g & (2 * NT - 1));
+          const int ch = dual_slot_piece<NT>(lane, h * NT + nt);
           *reinterpret_cast<f32x4 *>(slot + lane * (8 * NT) + ch * 4) = cr[h][nt];
           czero(cr[h][nt]);
         }
       __syncthreads();
       // thread (r, q): rows 4 q .. 4 q + 3 of the step at column r, one
-      // 16-byte piece per wave
+      // 16-byte piece per wave.  NT = 2: 16 consecutive threads take four
+      // consecutive r times the four q & 3 (one h), a wave eight r times all
+      // eight q (whole 128-byte row pieces of the result); NT = 1: q = tid % 8.
       if (tid < 8 * RP) {
-        const int q = tid & 7, r = tid >> 3;
+        int q, r;
+        if constexpr (NT == 2) {
+          q = (tid & 3) + 4 * ((tid >> 4) & 1);
+          r = ((tid >> 2) & 3) + 4 * (tid >> 5);
+        } else {
+          q = tid & 7;
+          r = tid >> 3;
+        }
         const int sl = (r & 15) + 16 * (q & 3);
-        const int ch = ((q >> 2) * NT + (r >> 4)) ^ ((q & 3) & (2 * NT - 1));
+        const int ch = dual_slot_piece<NT>(sl, (q >> 2) * NT + (r >> 4));
         const float *sb = str + (int)(t & 1) * WV * SLOT + sl * (8 * NT) + ch * 4;
         f32x4 s = *reinterpret_cast<const f32x4 *>(sb);
 #pragma unroll 2
