@@ -356,6 +356,13 @@ struct SweepGraph {
   uint64_t binding = 0;
 };
 
+// Multi-TTVs collected instead of launched (see flush_batch).
+constexpr int kBatchMax = 32;
+struct MttvBatch {
+  MttvJob j[kBatchMax];
+  int n = 0;
+};
+
 struct nncp_ctx {
   int magic;
   Layout L;
@@ -383,6 +390,8 @@ struct nncp_ctx {
   // set while nncp_grad walks the right subtree from the fused pass: the
   // right root node lives in nodeR
   bool right_root_in_R = false;
+  // when set, the walks' multi-TTVs are collected here and run by flush_batch
+  MttvBatch *batch = nullptr;
   // node cache of nncp_mttkrp: a version per factor, bumped whenever the
   // library writes the factor or the caller reports a write
   // (nncp_factors_changed), and for each node buffer the node it holds with
@@ -520,10 +529,52 @@ void set_tag(nncp_ctx *c, int side, int a) {
   for (int q = 0; q < NNCP_MAX_MODES; ++q) t.ver[q] = c->ver[q];
 }
 
+// Runs the collected multi-TTVs (launch_mttv_jobs: as few launches as their
+// dependencies allow).
+int flush_batch(nncp_ctx *c) {
+  if (!c->batch || c->batch->n == 0) return NNCP_OK;
+  TIMED(3, launch_mttv_jobs(c->L.hdt, c->batch->j, c->batch->n, c->st));
+  c->batch->n = 0;
+  return NNCP_OK;
+}
+
+// A contiguous multi-TTV: collected when a batch is open and the job is of a
+// groupable kind, else launched (after the collected ones).
+int run_mttv_contig(nncp_ctx *c, const void *T, int64_t Ia, int64_t Q, const void *H, void *out,
+                    int leaf) {
+  if (c->batch && c->pending.R == 0 && c->batch->n < kBatchMax &&
+      plan_mttv_contig(c->L.hdt, T, Ia, Q, c->L.R, H, out, leaf, &c->batch->j[c->batch->n])) {
+    ++c->batch->n;
+    return NNCP_OK;
+  }
+  int rc = flush_batch(c);
+  if (rc) return rc;
+  TIMED(3, launch_mttv_contig(c->L.hdt, T, Ia, Q, c->L.R, H, out, leaf, c->st, &c->pending));
+  return NNCP_OK;
+}
+
+// A strided multi-TTV, likewise (collected only when its partials are left
+// for the consumer, M == NULL).
+int run_mttv_strided(nncp_ctx *c, const void *T, int64_t Ia, const int64_t *qdims, int nq,
+                     const void *const *Hq, void *M, void *part, int64_t cap, int *ns) {
+  if (c->batch && !M && c->pending.R == 0 && c->batch->n < kBatchMax &&
+      plan_mttv_strided(c->L.hdt, T, Ia, qdims, nq, Hq, c->L.R, part, cap,
+                        &c->batch->j[c->batch->n], ns)) {
+    ++c->batch->n;
+    return NNCP_OK;
+  }
+  int rc = flush_batch(c);
+  if (rc) return rc;
+  TIMED(3, launch_mttv_strided(c->L.hdt, T, Ia, qdims, nq, Hq, c->L.R, M, part, cap, c->st, ns,
+                               &c->pending));
+  return NNCP_OK;
+}
+
 // Root partial MTTKRP of one side into node[lo] (or into Mout if the subtree
 // has a single mode).
 int root_gemm(nncp_ctx *c, const FactorSet &F, int side, void *Mout, MRef *defer) {
   const Layout &L = c->L;
+  if (int rc = flush_batch(c)) return rc;
   const GemmPlan &p = L.gp[side];
   const int lo = side == 0 ? 0 : L.S, hi = side == 0 ? L.S : L.N;
   const bool leaf = hi - lo == 1;
@@ -580,8 +631,8 @@ int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_ro
     const int64_t Q = prod(L.dims, a, hi);
     const bool leaf = a == hi - 1;
     void *out = leaf ? Mout : node_buf(c, side, a);
-    TIMED(3, launch_mttv_contig(L.hdt, node_buf(c, side, a - 1), Ia, Q, R, F.H[a - 1], out,
-                                leaf ? 1 : 0, c->st, &c->pending));
+    int rc = run_mttv_contig(c, node_buf(c, side, a - 1), Ia, Q, F.H[a - 1], out, leaf ? 1 : 0);
+    if (rc) return rc;
   }
   if (n < hi - 1) {
     const void *Hq[NNCP_MAX_MODES];
@@ -589,9 +640,9 @@ int mttkrp_tree(nncp_ctx *c, const FactorSet &F, int n, void *Mout, bool from_ro
     int ns = 1;
     void *part = c->part_override ? c->part_override : c->part;
     const int64_t cap = c->part_override ? c->part_override_elems : L.part_elems;
-    TIMED(3, launch_mttv_strided(L.hdt, node_buf(c, side, n), L.dims[n], L.dims + n + 1,
-                                 hi - n - 1, Hq, R, defer ? nullptr : Mout, part, cap, c->st, &ns,
-                                 &c->pending));
+    int rc = run_mttv_strided(c, node_buf(c, side, n), L.dims[n], L.dims + n + 1, hi - n - 1, Hq,
+                              defer ? nullptr : Mout, part, cap, &ns);
+    if (rc) return rc;
     if (defer) *defer = MRef{part, ns, L.dims[n] * R};
   }
   return NNCP_OK;
@@ -1301,6 +1352,14 @@ static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const
     // multi-TTV forms it, its split partials in the mode's own region),
     // M^(N-1) in c->M (or nodeR) for the loss
     GradAllArgs ga{};
+    // on the fused path the walks launch nothing but multi-TTVs: collect
+    // them and run them grouped (flushed before the gradient launch)
+    MttvBatch batch;
+    struct BatchGuard {
+      nncp_ctx *c;
+      ~BatchGuard() { c->batch = nullptr; }
+    } guard{c};
+    if (dual) c->batch = &batch;
     for (int n = 0; n < L.N; ++n) {
       const bool lastm = n == L.N - 1;
       MRef mr{lastm ? c->M : grads[n], 1, 0};
@@ -1335,6 +1394,8 @@ static int grad_at(nncp_ctx *c, const FactorSet &F, const double *G, void *const
     ga.alpha = c->scal + 8;
     ga.loss = loss;
     ga.scal = c->scal + 4;
+    if (int rc = flush_batch(c)) return rc;
+    c->batch = nullptr;
     HIPCHK(flush_gram(c));
     HIPCHK(launch_grad_all(L.hdt, ga, c->st));
     return NNCP_OK;

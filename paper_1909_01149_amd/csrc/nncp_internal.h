@@ -170,6 +170,47 @@ hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t
                                GramJob *carry = nullptr);
 int64_t mttv_strided_part_elems(int hdt, int64_t Ia, const int64_t *qdims, int nq, int R);
 
+// Launch parameters of a strided multi-TTV (the kernel's argument).
+struct StridedArgs {
+  const void *H[NNCP_MAX_MODES];
+  int64_t qd[NNCP_MAX_MODES];
+  int nq;
+  int64_t Ia, Q;
+  int R, IT, QS, nsplit;
+};
+
+// A multi-TTV planned instead of launched, for launch_mttv_jobs.
+struct MttvJob {
+  int kind;  // 0 strided (split partials left in out), 1 contiguous (packed form)
+  const void *T;
+  void *out;  // strided: the split partials; contiguous: the node or M
+  StridedArgs sa;
+  int64_t gx;  // strided: workgroups along i
+  int64_t Ia, Q;
+  int R, leaf;
+  const void *H;
+  int64_t blocks;
+  int vec;                   // the job's kernel variant (strided V, contiguous GL)
+  const char *rd0, *rd1;     // bytes read (T; the factors are only read)
+  const char *wr0, *wr1;     // bytes written
+};
+
+// The launch launch_mttv_contig / launch_mttv_strided (partials left for the
+// consumer, no Gram step to carry) would make, as a job, when it is one of
+// the kinds launch_mttv_jobs can group (strided, or contiguous with
+// Ia / (16 / sizeof element) a power of two below 64); false otherwise.
+bool plan_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R, const void *H,
+                      void *out, int leaf, MttvJob *j);
+bool plan_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
+                       const void *const *Hq, int R, void *part, int64_t part_elems, MttvJob *j,
+                       int *nsplit_out);
+// Run planned jobs in as few launches as their data dependencies allow: a job
+// goes after every earlier job that writes bytes it reads or writes, or reads
+// bytes it writes; independent jobs of one level share a launch (up to four,
+// of matching kernel variants).  Results equal those of the separate launches
+// in job order.
+hipError_t launch_mttv_jobs(int hdt, const MttvJob *jobs, int n, hipStream_t st);
+
 // Gram G = H^T H (FP64) for one factor; single workgroup.
 hipError_t launch_gram(int hdt, const void *H, int64_t I, int R, double *G, hipStream_t st);
 

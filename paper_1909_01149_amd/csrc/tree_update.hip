@@ -179,25 +179,18 @@ __global__ __launch_bounds__(256) void k_mttv_contig_reg(const HT *__restrict__ 
 // over its GL lanes, which is the wave-wide butterfly of the kernel above
 // with the stages that only add the idle lanes' zeros left out.
 template <typename HT, int GL>
-__global__ __launch_bounds__(256) void k_mttv_contig_pack(const HT *__restrict__ T, int64_t Ia,
-                                                          int64_t Q, int R,
-                                                          const HT *__restrict__ H,
-                                                          HT *__restrict__ out, int leaf,
-                                                          GramJob job) {
+__device__ __forceinline__ void contig_pack_block(const HT *__restrict__ T, int64_t Ia, int64_t Q,
+                                                  int R, const HT *__restrict__ H,
+                                                  HT *__restrict__ out, int leaf, int r, int by,
+                                                  HT *hs_lds) {
   constexpr int V = 16 / (int)sizeof(HT);
   constexpr int OPL = 64 / GL;  // outputs per load of a wave
   constexpr int NL = 8;         // loads per lane
   typedef HT vt __attribute__((ext_vector_type(V)));
-  __shared__ vt hs[GL];
-  // extra columns of workgroups when carrying the Gram step
-  if (job.R && blockIdx.x >= R) {
-    gram_run(job, (blockIdx.x - R) * gridDim.y + blockIdx.y);
-    return;
-  }
-  const int r = blockIdx.x;
+  vt *hs = reinterpret_cast<vt *>(hs_lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / GL, sub = lane % GL;
-  const int64_t qw = ((int64_t)blockIdx.y * 4 + wave) * (OPL * NL);
+  const int64_t qw = ((int64_t)by * 4 + wave) * (OPL * NL);
   const HT *Tr = T + (int64_t)r * Ia * Q;
   vt x[NL];
 #pragma unroll
@@ -205,8 +198,7 @@ __global__ __launch_bounds__(256) void k_mttv_contig_pack(const HT *__restrict__
     const int64_t q = qw + u * OPL + grp;
     x[u] = reinterpret_cast<const vt *>(Tr + Ia * (q < Q ? q : Q - 1))[sub];
   }
-  HT *hsf = reinterpret_cast<HT *>(hs);
-  for (int64_t i = threadIdx.x; i < Ia; i += 256) hsf[i] = H[i * R + r];
+  for (int64_t i = threadIdx.x; i < Ia; i += 256) hs_lds[i] = H[i * R + r];
   __syncthreads();
   const vt hv = hs[sub];
 #pragma unroll
@@ -224,36 +216,37 @@ __global__ __launch_bounds__(256) void k_mttv_contig_pack(const HT *__restrict__
   }
 }
 
+template <typename HT, int GL>
+__global__ __launch_bounds__(256) void k_mttv_contig_pack(const HT *__restrict__ T, int64_t Ia,
+                                                          int64_t Q, int R,
+                                                          const HT *__restrict__ H,
+                                                          HT *__restrict__ out, int leaf,
+                                                          GramJob job) {
+  constexpr int V = 16 / (int)sizeof(HT);
+  __shared__ __align__(16) HT hs[GL * V];
+  // extra columns of workgroups when carrying the Gram step
+  if (job.R && blockIdx.x >= R) {
+    gram_run(job, (blockIdx.x - R) * gridDim.y + blockIdx.y);
+    return;
+  }
+  contig_pack_block<HT, GL>(T, Ia, Q, R, H, out, leaf, blockIdx.x, blockIdx.y, hs);
+}
+
 // ---------------------------------------------------------------------------
 // multi-TTV, strided reduction keeping the first mode:
 //   part[z][i][r] = sum_{q in split z} T[r][i + Ia q] K(q, r),
 //   K(q, r) = prod_k H^(k)(digit_k(q), r) over the node's remaining modes.
 // Block = IT columns i x QS q-lanes; q-lanes added in order through LDS.
 // ---------------------------------------------------------------------------
-struct StridedArgs {
-  const void *H[NNCP_MAX_MODES];
-  int64_t qd[NNCP_MAX_MODES];
-  int nq;
-  int64_t Ia, Q;
-  int R, IT, QS, nsplit;
-};
-
 template <typename HT, int V>
-__global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, StridedArgs a,
-                                                      HT *__restrict__ part, GramJob job) {
+__device__ __forceinline__ void strided_block(const HT *__restrict__ T, const StridedArgs &a,
+                                              HT *__restrict__ part, int bx, int r, int64_t z,
+                                              HT *red_lds, HT *kq) {
   typedef HT vt __attribute__((ext_vector_type(V)));
-  __shared__ vt red[256];
-  __shared__ HT kq[1024];
-  // extra rows of workgroups (blockIdx.y >= R) when carrying the Gram step
-  if (job.R && blockIdx.y >= a.R) {
-    gram_run(job, ((blockIdx.y - a.R) * gridDim.z + blockIdx.z) * gridDim.x + blockIdx.x);
-    return;
-  }
+  vt *red = reinterpret_cast<vt *>(red_lds);
   const int il = threadIdx.x % a.IT, qs = threadIdx.x / a.IT;
-  const int64_t i0 = ((int64_t)blockIdx.x * a.IT + il) * V;
+  const int64_t i0 = ((int64_t)bx * a.IT + il) * V;
   const bool live = i0 < a.Ia;
-  const int r = blockIdx.y;
-  const int64_t z = blockIdx.z;
   const int64_t q0 = a.Q * z / a.nsplit, q1 = a.Q * (z + 1) / a.nsplit;
   const HT *const *H = (const HT *const *)a.H;
   const HT *t = T + (int64_t)r * a.Ia * a.Q + (live ? i0 : 0);
@@ -294,6 +287,56 @@ __global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, 
     for (int k = 1; k < QS; ++k) sum += red[k * a.IT + il];
 #pragma unroll
     for (int v = 0; v < V; ++v) part[(z * Ia + i0 + v) * a.R + r] = sum[v];
+  }
+}
+
+template <typename HT, int V>
+__global__ __launch_bounds__(256) void k_mttv_strided(const HT *__restrict__ T, StridedArgs a,
+                                                      HT *__restrict__ part, GramJob job) {
+  __shared__ __align__(16) HT red[256 * V];
+  __shared__ HT kq[1024];
+  // extra rows of workgroups (blockIdx.y >= R) when carrying the Gram step
+  if (job.R && blockIdx.y >= a.R) {
+    gram_run(job, ((blockIdx.y - a.R) * gridDim.z + blockIdx.z) * gridDim.x + blockIdx.x);
+    return;
+  }
+  strided_block<HT, V>(T, a, part, blockIdx.x, blockIdx.y, blockIdx.z, red, kq);
+}
+
+// ---------------------------------------------------------------------------
+// Several independent multi-TTVs of the kinds above in one launch (the
+// gradient's walks, where every M^(n) is taken at the same factors): job k
+// owns workgroups start[k] .. start[k+1]-1, numbered as its own launch
+// would number them (strided: x fastest, then r, then the split; contiguous:
+// r fastest, then the q-block).
+// ---------------------------------------------------------------------------
+constexpr int kMttvGroupMax = 4;
+struct MttvGroup {
+  MttvJob j[kMttvGroupMax];
+  int64_t start[kMttvGroupMax + 1];
+  int n;
+};
+
+template <typename HT, int V, int GL>
+__global__ __launch_bounds__(256) void k_mttv_group(MttvGroup g) {
+  constexpr int VC = 16 / (int)sizeof(HT);
+  __shared__ __align__(16) HT red[256 * V];
+  __shared__ HT kq[1024];
+  __shared__ __align__(16) HT hs[GL * VC];
+  const int64_t b = blockIdx.x;
+  int k = 0;
+#pragma unroll
+  for (int q = 1; q < kMttvGroupMax; ++q)
+    if (q < g.n && b >= g.start[q]) k = q;
+  const MttvJob &j = g.j[k];
+  const int64_t lb = b - g.start[k];
+  if (j.kind == 0) {
+    const int64_t bx = lb % j.gx, rest = lb / j.gx;
+    strided_block<HT, V>((const HT *)j.T, j.sa, (HT *)j.out, (int)bx, (int)(rest % j.R),
+                         rest / j.R, red, kq);
+  } else {
+    contig_pack_block<HT, GL>((const HT *)j.T, j.Ia, j.Q, j.R, (const HT *)j.H, (HT *)j.out, j.leaf,
+                              (int)(lb % j.R), (int)(lb / j.R), hs);
   }
 }
 
@@ -1943,6 +1986,146 @@ hipError_t launch_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t
       hipLaunchKernelGGL(k_sum_splits<float>, g2, dim3(256), 0, st, (const float *)part, n, a.nsplit, (float *)M);
   }
   return hipGetLastError();
+}
+
+bool plan_mttv_contig(int hdt, const void *T, int64_t Ia, int64_t Q, int R, const void *H,
+                      void *out, int leaf, MttvJob *j) {
+  const int V = hdt == NNCP_F64 ? 2 : 4;
+  const int64_t gl = Ia / V;
+  if (Ia % V != 0 || gl >= 64 || (gl & (gl - 1)) != 0) return false;
+  const size_t hs = hdt == NNCP_F64 ? 8 : 4;
+  const int64_t gy = (Q + 4 * (64 / gl) * 8 - 1) / (4 * (64 / gl) * 8);
+  *j = MttvJob{};
+  j->kind = 1;
+  j->T = T;
+  j->out = out;
+  j->Ia = Ia;
+  j->Q = Q;
+  j->R = R;
+  j->leaf = leaf;
+  j->H = H;
+  j->blocks = (int64_t)R * gy;
+  j->vec = (int)gl;
+  j->rd0 = (const char *)T;
+  j->rd1 = j->rd0 + hs * (size_t)(R * Ia * Q);
+  j->wr0 = (const char *)out;
+  j->wr1 = j->wr0 + hs * (size_t)(Q * R);
+  return true;
+}
+
+bool plan_mttv_strided(int hdt, const void *T, int64_t Ia, const int64_t *qdims, int nq,
+                       const void *const *Hq, int R, void *part, int64_t part_elems, MttvJob *j,
+                       int *nsplit_out) {
+  StridedArgs a;
+  int64_t Q = 1;
+  for (int k = 0; k < NNCP_MAX_MODES; ++k) {
+    a.H[k] = k < nq ? Hq[k] : nullptr;
+    a.qd[k] = k < nq ? qdims[k] : 1;
+    if (k < nq) Q *= qdims[k];
+  }
+  a.nq = nq; a.Ia = Ia; a.Q = Q; a.R = R;
+  int64_t gx;
+  const int V = strided_vec(hdt, Ia);
+  strided_shape(Ia, V, Q, R, a.IT, a.QS, a.nsplit, gx);
+  if ((int64_t)a.nsplit * Ia * R > part_elems) return false;
+  const size_t hs = hdt == NNCP_F64 ? 8 : 4;
+  *j = MttvJob{};
+  j->kind = 0;
+  j->T = T;
+  j->out = part;
+  j->sa = a;
+  j->gx = gx;
+  j->Ia = Ia;
+  j->Q = Q;
+  j->R = R;
+  j->blocks = gx * R * a.nsplit;
+  j->vec = V;
+  j->rd0 = (const char *)T;
+  j->rd1 = j->rd0 + hs * (size_t)(R * Ia * Q);
+  j->wr0 = (const char *)part;
+  j->wr1 = j->wr0 + hs * (size_t)(a.nsplit * Ia * R);
+  if (nsplit_out) *nsplit_out = a.nsplit;
+  return true;
+}
+
+static bool overlap(const char *a0, const char *a1, const char *b0, const char *b1) {
+  return a0 < b1 && b0 < a1;
+}
+
+template <typename HT>
+static hipError_t launch_group(const MttvGroup &g, int sv, int cv, hipStream_t st) {
+  const dim3 grid((unsigned)g.start[g.n]), block(256);
+#define NNCP_GROUP(VV, GLV) hipLaunchKernelGGL((k_mttv_group<HT, VV, GLV>), grid, block, 0, st, g)
+#define NNCP_GROUP_GL(VV)                   \
+  switch (cv) {                             \
+    case 1: NNCP_GROUP(VV, 1); break;       \
+    case 2: NNCP_GROUP(VV, 2); break;       \
+    case 4: NNCP_GROUP(VV, 4); break;       \
+    case 8: NNCP_GROUP(VV, 8); break;       \
+    case 16: NNCP_GROUP(VV, 16); break;     \
+    case 32: NNCP_GROUP(VV, 32); break;     \
+    default: return hipErrorInvalidValue;   \
+  }
+  constexpr int VW = sizeof(HT) == 8 ? 2 : 4;
+  if (sv == VW) {
+    NNCP_GROUP_GL(VW)
+  } else if (sv == 1) {
+    NNCP_GROUP_GL(1)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef NNCP_GROUP_GL
+#undef NNCP_GROUP
+  return hipGetLastError();
+}
+
+hipError_t launch_mttv_jobs(int hdt, const MttvJob *jobs, int n, hipStream_t st) {
+  constexpr int kMax = 64;
+  if (n < 0 || n > kMax) return hipErrorInvalidValue;
+  int level[kMax];
+  int top = -1;
+  for (int b = 0; b < n; ++b) {
+    const MttvJob &y = jobs[b];
+    level[b] = 0;
+    for (int a = 0; a < b; ++a) {
+      const MttvJob &x = jobs[a];
+      if (overlap(x.wr0, x.wr1, y.rd0, y.rd1) || overlap(x.wr0, x.wr1, y.wr0, y.wr1) ||
+          overlap(x.rd0, x.rd1, y.wr0, y.wr1))
+        level[b] = level[b] > level[a] + 1 ? level[b] : level[a] + 1;
+    }
+    top = top > level[b] ? top : level[b];
+  }
+  for (int lv = 0; lv <= top; ++lv) {
+    // the level's jobs in order, a launch per run of matching variants
+    MttvGroup g{};
+    int sv = 0, cv = 0;
+    auto flush = [&]() -> hipError_t {
+      if (g.n == 0) return hipSuccess;
+      hipError_t e = hdt == NNCP_F64 ? launch_group<double>(g, sv ? sv : 1, cv ? cv : 1, st)
+                                     : launch_group<float>(g, sv ? sv : 1, cv ? cv : 1, st);
+      g = MttvGroup{};
+      sv = cv = 0;
+      return e;
+    };
+    for (int b = 0; b < n; ++b) {
+      if (level[b] != lv) continue;
+      const MttvJob &y = jobs[b];
+      const bool fits = g.n < kMttvGroupMax && (y.kind == 0 ? (sv == 0 || sv == y.vec)
+                                                            : (cv == 0 || cv == y.vec));
+      if (!fits) {
+        const hipError_t e = flush();
+        if (e != hipSuccess) return e;
+      }
+      if (y.kind == 0) sv = y.vec;
+      else cv = y.vec;
+      g.j[g.n] = y;
+      g.start[g.n + 1] = g.start[g.n] + y.blocks;
+      ++g.n;
+    }
+    const hipError_t e = flush();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_gram(int hdt, const void *H, int64_t I, int R, double *G, hipStream_t st) {

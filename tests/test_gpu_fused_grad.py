@@ -39,6 +39,12 @@ CASES = [
     ([64, 48, 96], 24),
     ([128, 40, 64], 12),
     ([64, 20, 25, 32, 16], 28),
+    # the walks' multi-TTVs are grouped into launches by their data
+    # dependencies: a three-mode right subtree (its node shares a buffer with
+    # the left subtree's), and a four-mode left subtree (node 2 overwrites the
+    # left root that earlier jobs read)
+    ([64, 6, 8, 8, 16, 12], 20),
+    ([8, 8, 8, 8, 16, 16], 16),
 ]
 
 
