@@ -1322,10 +1322,10 @@ int nncp_sweep_capture(nncp_ctx *c, int algo, int nsweeps, double *relerr_hist) 
 static int dual_roots(nncp_ctx *c, const FactorSet &F) {
   const Layout &L = c->L;
   HIPCHK(flush_gram(c));
-  TIMED(2, launch_krp_operands(L.xdt, L.gp[1], L.R, L.dims, L.N, F, c->kf, c->ks, c->st));
-  // the left operand whole (its slow part, a row of ones, goes to scratch)
-  TIMED(2, launch_krp_operands(L.xdt, dual_full_plan(L.gp[0], L.S, L.N), L.R, L.dims, L.N, F,
-                               c->kfR, c->red, c->st));
+  // the right operand's parts, and the left operand whole (its slow part, a
+  // row of ones, goes to scratch), in one launch
+  TIMED(2, launch_krp_operands2(L.xdt, L.gp[1], c->kf, c->ks, dual_full_plan(L.gp[0], L.S, L.N),
+                                c->kfR, c->red, L.R, L.dims, L.N, F, c->st));
   // the right partials in the layout of their destination: [R][k] for the
   // right root node, [k][R] for M^(N-1), so that the sum reads and writes
   // whole lines

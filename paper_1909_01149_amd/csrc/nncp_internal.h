@@ -105,6 +105,11 @@ struct GramJob;  // the Gram step of an update (below)
 hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t *dims, int N,
                                const FactorSet &F, void *kfast, void *kslow, hipStream_t st,
                                GramJob *carry = nullptr);
+// The operands of two plans in one launch (not FP16, no Gram step carried):
+// the same values as two launch_krp_operands calls.
+hipError_t launch_krp_operands2(int xdt, const GemmPlan &p0, void *kf0, void *ks0,
+                                const GemmPlan &p1, void *kf1, void *ks1, int R,
+                                const int64_t *dims, int N, const FactorSet &F, hipStream_t st);
 
 // Partial MTTKRP.  `out` receives [nsplit][...] partials (see the kernels) or,
 // when nsplit == 1, the node itself ([r][row] layout) for the left product.

@@ -151,18 +151,12 @@ __device__ double krp_entry(const KrpArgs &a, int lo, int hi, int64_t rho, int r
   return p;
 }
 
+// Column r of the operand, the part that workgroup row by of gy forms.
 template <typename XT, typename HT>
-__global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict__ kfast,
-                                                      HT *__restrict__ kslow, GramJob job) {
-  // extra columns of workgroups (blockIdx.x >= Rpad) when carrying the
-  // Gram step of the previous update
-  if (job.R && blockIdx.x >= a.Rpad) {
-    gram_run(job, (blockIdx.x - a.Rpad) * gridDim.y + blockIdx.y);
-    return;
-  }
-  const int r = blockIdx.x;
+__device__ __forceinline__ void krp_column(const KrpArgs &a, XT *__restrict__ kfast,
+                                           HT *__restrict__ kslow, int r, int by, int gy,
+                                           double *red) {
   const bool live = r < a.R;
-  __shared__ double red[256];
   double mx = 0.0;
   // the column maximum only matters for the FP16 scaling
   if (a.scale16) {
@@ -186,8 +180,8 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
     e = 14 - E;     // max entry lands in [2^13, 2^14)
   }
   const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
-  // without the FP16 scaling the column is split over gridDim.y workgroups
-  const int64_t t0 = threadIdx.x + 256 * (int64_t)blockIdx.y, ts = 256 * (int64_t)gridDim.y;
+  // without the FP16 scaling the column is split over gy workgroups
+  const int64_t t0 = threadIdx.x + 256 * (int64_t)by, ts = 256 * (int64_t)gy;
   for (int64_t p = t0; p < a.Pf; p += ts) {
     const double v = live ? krp_entry<HT>(a, a.fast_lo, a.fast_hi, p, r) * up : 0.0;
     const XT hi = from_d<XT>(v);
@@ -198,6 +192,33 @@ __global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict_
     const double w = live ? krp_entry<HT>(a, a.slow_lo, a.slow_hi, q, r) * down : 0.0;
     kslow[q * a.Rpad + r] = (HT)w;
   }
+}
+
+template <typename XT, typename HT>
+__global__ __launch_bounds__(256) void k_krp_operands(KrpArgs a, XT *__restrict__ kfast,
+                                                      HT *__restrict__ kslow, GramJob job) {
+  // extra columns of workgroups (blockIdx.x >= Rpad) when carrying the
+  // Gram step of the previous update
+  if (job.R && blockIdx.x >= a.Rpad) {
+    gram_run(job, (blockIdx.x - a.Rpad) * gridDim.y + blockIdx.y);
+    return;
+  }
+  __shared__ double red[256];
+  krp_column<XT, HT>(a, kfast, kslow, blockIdx.x, blockIdx.y, gridDim.y, red);
+}
+
+// Two operands in one launch (columns of the first, then of the second), no
+// FP16 scaling.
+template <typename XT, typename HT>
+__global__ __launch_bounds__(256) void k_krp_operands2(KrpArgs a0, XT *__restrict__ kf0,
+                                                       HT *__restrict__ ks0, KrpArgs a1,
+                                                       XT *__restrict__ kf1,
+                                                       HT *__restrict__ ks1) {
+  __shared__ double red[256];
+  if ((int)blockIdx.x < a0.Rpad)
+    krp_column<XT, HT>(a0, kf0, ks0, blockIdx.x, blockIdx.y, gridDim.y, red);
+  else
+    krp_column<XT, HT>(a1, kf1, ks1, blockIdx.x - a0.Rpad, blockIdx.y, gridDim.y, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1295,6 +1316,34 @@ hipError_t launch_krp_operands(int xdt, const GemmPlan &p, int R, const int64_t 
       break;
     case NNCP_F64:
       hipLaunchKernelGGL((k_krp_operands<double, double>), grid, block, 0, st, a, (double *)kfast, (double *)kslow, job);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_krp_operands2(int xdt, const GemmPlan &p0, void *kf0, void *ks0,
+                                const GemmPlan &p1, void *kf1, void *ks1, int R,
+                                const int64_t *dims, int N, const FactorSet &F, hipStream_t st) {
+  if (xdt == NNCP_F16) return hipErrorInvalidValue;
+  const KrpArgs a0 = make_krp_args(p0, R, dims, F, N), a1 = make_krp_args(p1, R, dims, F, N);
+  const int64_t longest = std::max(std::max(p0.Pf, p0.Ps), std::max(p1.Pf, p1.Ps));
+  int64_t chunks = (longest + 255) / 256;
+  if (chunks > 64) chunks = 64;
+  const dim3 grid((unsigned)(p0.Rpad + p1.Rpad), (unsigned)chunks), block(256);
+  switch (xdt) {
+    case NNCP_BF16:
+      hipLaunchKernelGGL((k_krp_operands2<bf16_t, float>), grid, block, 0, st, a0, (bf16_t *)kf0,
+                         (float *)ks0, a1, (bf16_t *)kf1, (float *)ks1);
+      break;
+    case NNCP_F32:
+      hipLaunchKernelGGL((k_krp_operands2<float, float>), grid, block, 0, st, a0, (float *)kf0,
+                         (float *)ks0, a1, (float *)kf1, (float *)ks1);
+      break;
+    case NNCP_F64:
+      hipLaunchKernelGGL((k_krp_operands2<double, double>), grid, block, 0, st, a0, (double *)kf0,
+                         (double *)ks0, a1, (double *)kf1, (double *)ks1);
       break;
     default:
       return hipErrorInvalidValue;
