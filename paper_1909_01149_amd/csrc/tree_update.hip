@@ -9,6 +9,8 @@
 // at r * P + i_a + I_a (i_{a+1} + ...), P = I_a ... I_b.
 // Factors and M are I x R row-major.  Every reduction is done in a fixed order
 // (no atomics), so results are bitwise reproducible run to run.
+#include <type_traits>
+
 #include "nncp_internal.h"
 
 namespace nncp {
@@ -1448,12 +1450,13 @@ __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, 
 // of gamma = sum_i hs_i S hs_i^T (hs the stored row), which the relative
 // error identity needs with lambda = 1; both added in row-block and wave
 // order.  The arithmetic of a row is that of k_update_rows_small.
-template <typename HT, int RB>
+template <typename HT, int RB, bool FULL>
 __global__ __launch_bounds__(64 * kDeferWaves) void k_update_rows_defer(UpdateArgs a) {
   constexpr int WV = kDeferWaves, TQ = (10 + WV - 1) / WV;  // at most 10 upper tiles
   __shared__ double rows[WV][RB];
   __shared__ double bred[WV][2];
-  const int R = a.R;
+  // FULL: R == RB, known when compiling (no per-column bound tests)
+  const int R = FULL ? RB : a.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int T = (R + 15) / 16, ntile = T * (T + 1) / 2;
   int tx[TQ], ty[TQ];
@@ -1487,15 +1490,31 @@ __global__ __launch_bounds__(64 * kDeferWaves) void k_update_rows_defer(UpdateAr
     const bool live = i < a.I;
     const int64_t ir = live ? i : a.I - 1;
     const HT *mp = M + ir * R + c;
-    HT mv[32];
+    // the split partials in split order, NL loads issued together (indices
+    // clamped, so that none waits on a bound test)
+    auto msum = [&](auto nl) -> HT {
+      constexpr int NL = decltype(nl)::value;
+      HT mv[NL];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) mv[k] = k < ns ? mp[(int64_t)k * a.mstride] : (HT)0;
+      for (int k = 0; k < NL; ++k) mv[k] = mp[(int64_t)(k < ns ? k : ns - 1) * a.mstride];
+      HT sum = mv[0];
+#pragma unroll
+      for (int k = 1; k < NL; ++k)
+        if (k < ns) sum += mv[k];
+      return sum;
+    };
+    HT macc;
+    if (ns == 1) {
+      macc = mp[0];
+    } else if (ns <= 8) {
+      macc = msum(std::integral_constant<int, 8>{});
+    } else if (ns <= 16) {
+      macc = msum(std::integral_constant<int, 16>{});
+    } else {
+      macc = msum(std::integral_constant<int, 32>{});
+      for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
+    }
     const HT h_raw = H[ir * R + c];
-    HT macc = mv[0];
-#pragma unroll
-    for (int k = 1; k < 32; ++k)
-      if (k < ns) macc += mv[k];
-    for (int k = 32; k < ns; ++k) macc += mp[(int64_t)k * a.mstride];
     const bool ok = live && own;
     double h = ok ? (double)h_raw * lam : 0.0;
     const double m = ok ? (double)macc : 0.0;
@@ -2195,9 +2214,17 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     job->next_mode = a.next_mode;
     job->nw = nw;
     const dim3 blk(64 * kDeferWaves);
-    if (a.R <= 16) hipLaunchKernelGGL((k_update_rows_defer<HT, 16>), dim3(nw), blk, 0, st, a);
-    else if (a.R <= 32) hipLaunchKernelGGL((k_update_rows_defer<HT, 32>), dim3(nw), blk, 0, st, a);
-    else hipLaunchKernelGGL((k_update_rows_defer<HT, 64>), dim3(nw), blk, 0, st, a);
+#define NNCP_DEFER(RBV)                                                                     \
+  if (a.R == RBV) hipLaunchKernelGGL((k_update_rows_defer<HT, RBV, true>), dim3(nw), blk, 0, st, a); \
+  else hipLaunchKernelGGL((k_update_rows_defer<HT, RBV, false>), dim3(nw), blk, 0, st, a);
+    if (a.R <= 16) {
+      NNCP_DEFER(16)
+    } else if (a.R <= 32) {
+      NNCP_DEFER(32)
+    } else {
+      NNCP_DEFER(64)
+    }
+#undef NNCP_DEFER
     return hipGetLastError();
   }
   if (a.R <= 64) {
