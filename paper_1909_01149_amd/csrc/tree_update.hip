@@ -1662,13 +1662,51 @@ __device__ __forceinline__ void loss_block(int N, int R, int64_t In, const HT *_
                                            double *relerr, double *scal,
                                            double (*wred)[2] /* LDS, NT / 64 rows */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // beta: the thread's entries e = t, t + NT, ... in order, eight at a time
+  // with their loads issued together (the column e % R kept incrementally)
   double beta = 0.0;
-  for (int64_t e = threadIdx.x; e < In * R; e += NT)
-    beta += (double)M[e] * (double)H[e] * lambda[e % R];
+  {
+    const int64_t n = In * R;
+    const int rstep = NT % R;
+    int r = (int)(threadIdx.x % R);
+    int64_t e = threadIdx.x;
+    for (; e + 7 * NT < n; e += 8 * NT) {
+      HT mv[8], hv[8];
+      double lv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        mv[u] = M[e + u * NT];
+        hv[u] = H[e + u * NT];
+        lv[u] = lambda[r];
+        r += rstep;
+        if (r >= R) r -= R;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) beta += (double)mv[u] * (double)hv[u] * lv[u];
+    }
+    for (; e < n; e += NT) {
+      beta += (double)M[e] * (double)H[e] * lambda[r];
+      r += rstep;
+      if (r >= R) r -= R;
+    }
+  }
+  // gamma: the N Gram entries of an e loaded together (N <= 8), multiplied
+  // in mode order (the unused slots are 1)
   double gamma = 0.0;
   for (int e = threadIdx.x; e < R * R; e += NT) {
     double s = 1.0;
-    for (int k = 0; k < N; ++k) s *= G[(int64_t)k * R * R + e];
+    if (N <= 8) {
+      double gv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double v = G[(int64_t)(k < N ? k : N - 1) * R * R + e];
+        gv[k] = k < N ? v : 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s *= gv[k];
+    } else {
+      for (int k = 0; k < N; ++k) s *= G[(int64_t)k * R * R + e];
+    }
     gamma += lambda[e / R] * s * lambda[e % R];
   }
   beta = wave_sum(beta);
