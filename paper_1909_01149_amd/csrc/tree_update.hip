@@ -704,11 +704,11 @@ __global__ __launch_bounds__(1024) void k_update_finish(UpdateArgs a, int nblock
 // broadcast and every lane folds the change into its entry of the gradient,
 // so a step costs a few dependent instructions.  The HALS quotient uses the
 // reciprocal of S(r, r) (within one rounding of the quotient).
-template <typename HT, int RB, bool NES>
+template <typename HT, int RB, bool NES, bool FULL>
 __global__ __launch_bounds__(256) void k_update_rows_small(UpdateArgs a) {
   __shared__ double wred[4][64];
   __shared__ double bred[4];
-  const int R = a.R;
+  const int R = FULL ? RB : a.R;  // FULL: R == RB, known when compiling
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const HT *M = (const HT *)a.M;
   const HT *H = (const HT *)a.H;
@@ -854,10 +854,10 @@ __device__ double nes_power(const double (&sr)[RB], int R, int lane, double shif
   return wave_sum(own ? v * sv : 0.0);
 }
 
-template <int RB>
+template <int RB, bool FULL>
 __global__ __launch_bounds__(64) void k_nes_prep(UpdateArgs a) {
   __shared__ double vs[64];
-  const int R = a.R, lane = threadIdx.x;
+  const int R = FULL ? RB : a.R, lane = threadIdx.x;
   const bool own = lane < R;
   double sr[RB];
 #pragma unroll
@@ -1164,14 +1164,14 @@ __global__ __launch_bounds__(1024) void k_admm_prep(UpdateArgs a) {
 // per-workgroup norms (every workgroup adds them in the same order, so all
 // agree) and does nothing once the updates have stopped.  Each pass leaves
 // the row kernel's partials (column sums of squares and beta) of its result.
-template <typename HT, int RB>
+template <typename HT, int RB, bool FULL>
 __global__ __launch_bounds__(256) void k_admm_pass(UpdateArgs a, int pass, int nblocks) {
   __shared__ double wred[4][64];
   __shared__ double nred[4][4];
   __shared__ double bred[4];
   __shared__ double tred[256][4];
   __shared__ int run_s;
-  const int R = a.R;
+  const int R = FULL ? RB : a.R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 4 + wave;
   const bool live = i < a.I;
@@ -1299,14 +1299,14 @@ int norm_gpart_elems(int R) { return (int)norm_pn_offset(R) + R * R; }
 // mode and next_mode (256 entries each, in turn).  Adding the slices, gamma
 // and the next mode's S are left to the Gram step (gram_finish), which a
 // later kernel runs once these are complete.
-template <typename HT, int RB>
+template <typename HT, int RB, bool FULL>
 __global__ __launch_bounds__(256) void k_update_norm(UpdateArgs a, int nblocks, int64_t rpw) {
   constexpr int TB = RB / 16;                     // tile grid bound
   constexpr int TW = (TB * (TB + 1) / 2 + 3) / 4; // tiles per wave
   __shared__ double rowbuf[4096];
   __shared__ double colsum[256];
   __shared__ double lam_s[64];
-  const int R = a.R;
+  const int R = FULL ? RB : a.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nct = R + 1, tpc = 256 / nct;
   const int pc = tid % nct, pj = tid / nct;
@@ -2283,32 +2283,41 @@ static hipError_t update_dispatch(const UpdateArgs &a, hipStream_t st, GramJob *
     job->mode = a.mode;
     job->next_mode = a.next_mode;
     job->nw = nw;
-#define NNCP_UPDATE_SMALL(RBV)                                                           \
-  if (a.algo == NNCP_NES) {                                                             \
-    hipLaunchKernelGGL((k_nes_prep<RBV>), dim3(1), dim3(64), 0, st, a);                 \
-    hipLaunchKernelGGL((k_update_rows_small<HT, RBV, true>), grid, block, 0, st, a);    \
-    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
-  } else if (a.algo == NNCP_ADMM) {                                                     \
-    hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(1024), 0, st, a);              \
-    for (int p = 0; p < kAdmmMaxit; ++p)                                                \
-      hipLaunchKernelGGL((k_admm_pass<HT, RBV>), grid, block, 0, st, a, p, nb);         \
-    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
-  } else if (a.algo == NNCP_BPP) {                                                      \
-    constexpr int WPB = RBV <= 32 ? 4 : 1;                                              \
-    const int nbb = (int)((a.I + WPB - 1) / WPB);                                       \
-    hipLaunchKernelGGL((k_update_bpp<HT, RBV>), dim3(nbb), dim3(64 * WPB), 0, st, a);   \
-    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nbb, rpw); \
-  } else {                                                                               \
-    hipLaunchKernelGGL((k_update_rows_small<HT, RBV, false>), grid, block, 0, st, a);   \
-    hipLaunchKernelGGL((k_update_norm<HT, RBV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+#define NNCP_UPDATE_SMALL(RBV, FV)                                                         \
+  if (a.algo == NNCP_NES) {                                                               \
+    hipLaunchKernelGGL((k_nes_prep<RBV, FV>), dim3(1), dim3(64), 0, st, a);               \
+    hipLaunchKernelGGL((k_update_rows_small<HT, RBV, true, FV>), grid, block, 0, st, a);  \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV, FV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+  } else if (a.algo == NNCP_ADMM) {                                                       \
+    hipLaunchKernelGGL((k_admm_prep<RBV>), dim3(1), dim3(1024), 0, st, a);                \
+    for (int p = 0; p < kAdmmMaxit; ++p)                                                  \
+      hipLaunchKernelGGL((k_admm_pass<HT, RBV, FV>), grid, block, 0, st, a, p, nb);       \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV, FV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+  } else if (a.algo == NNCP_BPP) {                                                        \
+    constexpr int WPB = RBV <= 32 ? 4 : 1;                                                \
+    const int nbb = (int)((a.I + WPB - 1) / WPB);                                         \
+    hipLaunchKernelGGL((k_update_bpp<HT, RBV>), dim3(nbb), dim3(64 * WPB), 0, st, a);     \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV, FV>), dim3(nw), dim3(256), 0, st, a, nbb, rpw); \
+  } else {                                                                                 \
+    hipLaunchKernelGGL((k_update_rows_small<HT, RBV, false, FV>), grid, block, 0, st, a); \
+    hipLaunchKernelGGL((k_update_norm<HT, RBV, FV>), dim3(nw), dim3(256), 0, st, a, nb, rpw); \
+  }
+    // R equal to the tile width (compiled without per-column bound tests),
+    // or below it
+#define NNCP_UPDATE_SMALL_R(RBV)   \
+  if (a.R == RBV) {                \
+    NNCP_UPDATE_SMALL(RBV, true)   \
+  } else {                         \
+    NNCP_UPDATE_SMALL(RBV, false)  \
   }
     if (a.R <= 16) {
-      NNCP_UPDATE_SMALL(16);
+      NNCP_UPDATE_SMALL_R(16)
     } else if (a.R <= 32) {
-      NNCP_UPDATE_SMALL(32);
+      NNCP_UPDATE_SMALL_R(32)
     } else {
-      NNCP_UPDATE_SMALL(64);
+      NNCP_UPDATE_SMALL_R(64)
     }
+#undef NNCP_UPDATE_SMALL_R
 #undef NNCP_UPDATE_SMALL
   } else {
     if (a.algo == NNCP_BPP || a.algo == NNCP_ADMM || a.algo == NNCP_NES) return hipErrorInvalidValue;
@@ -2523,16 +2532,21 @@ hipError_t launch_norm_only(int hdt, const UpdateArgs &a, int nblocks, hipStream
   job->mode = a.mode;
   job->next_mode = a.next_mode;
   job->nw = nw;
-#define NNCP_NORM_ONLY(HTV, RBV) \
-  hipLaunchKernelGGL((k_update_norm<HTV, RBV>), dim3(nw), dim3(256), 0, st, a, nblocks, rpw)
+#define NNCP_NORM_ONLY(HTV, RBV)                                                                     \
+  {                                                                                                  \
+    if (a.R == RBV)                                                                                  \
+      hipLaunchKernelGGL((k_update_norm<HTV, RBV, true>), dim3(nw), dim3(256), 0, st, a, nblocks, rpw); \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_update_norm<HTV, RBV, false>), dim3(nw), dim3(256), 0, st, a, nblocks, rpw); \
+  }
   if (hdt == NNCP_F64) {
-    if (a.R <= 16) NNCP_NORM_ONLY(double, 16);
-    else if (a.R <= 32) NNCP_NORM_ONLY(double, 32);
-    else NNCP_NORM_ONLY(double, 64);
+    if (a.R <= 16) NNCP_NORM_ONLY(double, 16)
+    else if (a.R <= 32) NNCP_NORM_ONLY(double, 32)
+    else NNCP_NORM_ONLY(double, 64)
   } else {
-    if (a.R <= 16) NNCP_NORM_ONLY(float, 16);
-    else if (a.R <= 32) NNCP_NORM_ONLY(float, 32);
-    else NNCP_NORM_ONLY(float, 64);
+    if (a.R <= 16) NNCP_NORM_ONLY(float, 16)
+    else if (a.R <= 32) NNCP_NORM_ONLY(float, 32)
+    else NNCP_NORM_ONLY(float, 64)
   }
 #undef NNCP_NORM_ONLY
   return hipGetLastError();
