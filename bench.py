@@ -490,7 +490,8 @@ def main():
     ap.add_argument("--reps", type=int, default=5, help="timed replays (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dram", action="store_true",
-                    help="skip the DRAM-only measurements (LLC-cold 512^3 products, 256^4 workload)")
+                    help="skip the measurements beside the 512^3 sweep (LLC-cold 512^3 products, "
+                         "256^4 workload, 64^5 gradient)")
     ap.add_argument("--anchor-only", action="store_true",
                     help="only the 256^4 measurement (for its counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -507,9 +508,10 @@ def main():
     # about 6% slower in both partial MTTKRPs (GEMM-L 5,671 against
     # 6,066 GB/s), which depends on the process's allocation history, not on
     # the kernels
-    anchor_child = None
+    anchor_child = grad_child = None
     if not args.no_dram and not args.anchor_only:
         anchor_child = anchor_subprocess()
+        grad_child = gradient_subprocess()
 
     import torch
     import nncp_inputs as gen
@@ -649,6 +651,7 @@ def main():
         "stream_read": ceiling,
         "llc_cold": cold,
         "dram_anchor": anchor,
+        "gradient": grad_child,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -727,19 +730,36 @@ def llc_cold_gemms(nn, torch, ctx, dims, R, reps=5):
     return out
 
 
-def anchor_subprocess():
-    """Run `bench.py --anchor-only` as a child process and return its
-    dram_anchor record (its log lines pass through to stderr)."""
+def child_json(argv, what):
+    """Run `bench.py <argv>` as a child process and return the last JSON
+    line it prints (its log lines pass through to stderr)."""
     import subprocess
-    log("256^4 workload in a child process")
-    p = subprocess.run([sys.executable, os.path.abspath(__file__), "--anchor-only"],
+    log(f"{what} in a child process")
+    p = subprocess.run([sys.executable, os.path.abspath(__file__)] + argv,
                        stdout=subprocess.PIPE, stderr=None, text=True, timeout=900)
     if p.returncode != 0:
-        raise RuntimeError(f"the 256^4 measurement failed (exit {p.returncode})")
+        raise RuntimeError(f"the {what} measurement failed (exit {p.returncode})")
     lines = [ln for ln in p.stdout.splitlines() if ln.startswith("{")]
     if not lines:
-        raise RuntimeError("the 256^4 measurement printed no result")
-    return json.loads(lines[-1])["dram_anchor"]
+        raise RuntimeError(f"the {what} measurement printed no result")
+    return json.loads(lines[-1])
+
+
+def anchor_subprocess():
+    """The dram_anchor record of `bench.py --anchor-only`, run as a child."""
+    return child_json(["--anchor-only"], "256^4 workload")["dram_anchor"]
+
+
+def gradient_subprocess():
+    """The 64^5 R = 32 gradient (`bench.py --configs c5`, run as a child):
+    gradients/s of the BF16 tensor (one fused pass over X) and the FP32
+    tensor (two passes), each the mean of 10 back-to-back gradients."""
+    r = child_json(["--configs", "c5"], "64^5 gradient")
+    out = {"workload": r["workload"], "R": 32}
+    for key, form in (("Xbf16", "bf16"), ("X32", "fp32")):
+        out[form] = {k: r[key][k] for k in ("ms_per_gradient", "gradients_per_s",
+                                             "loss0", "loss_after_100_pgd", "pgd_100_steps_s")}
+    return out
 
 
 def dram_anchor(nn, torch, gen, dev, nsweeps=10):
