@@ -1808,25 +1808,33 @@ __global__ __launch_bounds__(256) void k_grad_all(GradAllArgs a) {
 // registers; the iterate goes through the wave's LDS row, read as a
 // broadcast by every lane, and the norm is a wave reduction.  w_i = sum_j
 // S(i, j) v_j is added in j order.
-template <int RB>
-__global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, int N, int R,
+template <int RB, bool FULL>
+__global__ __launch_bounds__(512) void k_pgd_eta(const double *__restrict__ G, int N, int Rin,
                                                  int iters, double *__restrict__ eta) {
   __shared__ double vs[8][RB];
   __shared__ double lm[8];
+  const int R = FULL ? RB : Rin;  // FULL: R == RB, known when compiling
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool own = lane < R;
   const int i = own ? lane : 0;
   double lmax = 0.0;
   for (int n = wave; n < N; n += 8) {
+    // row i of S^(n): the other modes' Gram rows one mode at a time, each
+    // row's loads issued together (indices clamped), multiplied in mode order
     double srow[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      double p = 1.0;
-      if (own && j < R)
-        for (int k = 0; k < N; ++k)
-          if (k != n) p *= G[(int64_t)k * R * R + i * R + j];
-      srow[j] = (own && j < R) ? p : 0.0;
+    for (int j = 0; j < RB; ++j) srow[j] = 1.0;
+    for (int k = 0; k < N; ++k) {
+      if (k == n) continue;
+      const double *gk = G + (int64_t)k * R * R + (int64_t)i * R;
+      double gv[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) gv[j] = gk[j < R ? j : R - 1];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) srow[j] *= gv[j];
     }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) srow[j] = (own && j < R) ? srow[j] : 0.0;
     if (lane < RB) vs[wave][lane] = lane < R ? 1.0 / sqrt((double)R) : 0.0;
     wave_sync_lds();
     auto matvec = [&]() {
@@ -2596,9 +2604,17 @@ hipError_t launch_grad(int hdt, int64_t I, int R, int N, int mode, const void *M
 
 hipError_t launch_pgd_eta(const double *G, int N, int R, int iters, double *eta, hipStream_t st) {
   if (R > 64) return hipErrorInvalidValue;
-  if (R <= 16) hipLaunchKernelGGL((k_pgd_eta<16>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);
-  else if (R <= 32) hipLaunchKernelGGL((k_pgd_eta<32>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);
-  else hipLaunchKernelGGL((k_pgd_eta<64>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);
+#define NNCP_PGD_ETA(RBV)                                                                           \
+  {                                                                                                 \
+    if (R == RBV)                                                                                   \
+      hipLaunchKernelGGL((k_pgd_eta<RBV, true>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta);  \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_pgd_eta<RBV, false>), dim3(1), dim3(512), 0, st, G, N, R, iters, eta); \
+  }
+  if (R <= 16) NNCP_PGD_ETA(16)
+  else if (R <= 32) NNCP_PGD_ETA(32)
+  else NNCP_PGD_ETA(64)
+#undef NNCP_PGD_ETA
   return hipGetLastError();
 }
 
