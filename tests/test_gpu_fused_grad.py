@@ -45,6 +45,8 @@ CASES = [
     # left root that earlier jobs read)
     ([64, 6, 8, 8, 16, 12], 20),
     ([8, 8, 8, 8, 16, 16], 16),
+    # both at once (four left and three right modes), R < 16
+    ([64, 4, 4, 4, 8, 8, 8], 16),
 ]
 
 
