@@ -502,12 +502,12 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    # the 256^4 measurement runs first, in a process of its own started before
-    # this one touches the GPU: in one process, the same 8 GiB workload
-    # measured after other device memory had been allocated and freed ran
-    # about 6% slower in both partial MTTKRPs (GEMM-L 5,671 against
-    # 6,066 GB/s), which depends on the process's allocation history, not on
-    # the kernels
+    # the 256^4 and 64^5 measurements run first, each in a process of its own
+    # started before this one touches the GPU: in one process, the 8 GiB
+    # workload measured after other device memory had been allocated and
+    # freed ran about 6% slower in both partial MTTKRPs (GEMM-L 5,671
+    # against 6,066 GB/s), which depends on the process's allocation
+    # history, not on the kernels
     anchor_child = grad_child = None
     if not args.no_dram and not args.anchor_only:
         anchor_child = anchor_subprocess()
